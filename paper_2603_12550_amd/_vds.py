@@ -1,0 +1,209 @@
+"""ctypes binding of libvds.so: the C ABI of include/vds.h, one Python function
+per C entry point with the same name, plus a small `Context` convenience class.
+
+Argument marshalling only: tensors pass their device pointers, host structs are
+ctypes mirrors of the C ones.  Every step of the computation runs in the HIP
+library; if it is not built this module raises at import time.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvds.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2603_12550_amd/build.py "
+                      "(or __graft_entry__.build()); there is no CPU fallback")
+_lib = C.CDLL(LIB_PATH)
+
+VDS_OK, VDS_ERR_ARG, VDS_ERR_HIP, VDS_ERR_NOMEM, VDS_ERR_NOT_CONVERGED, VDS_ERR_STATE = range(6)
+VDS_HOOKEAN, VDS_FENE = 0, 1
+VDS_EXPLICIT, VDS_IMPLICIT = 0, 1
+VDS_PAIR_MFMA, VDS_PAIR_VALU = 0, 1
+VDS_TIMER_PAIR, VDS_TIMER_GEMM, VDS_TIMER_KGEMM, VDS_TIMER_PROJ = range(4)
+STATUS_NAMES = {0: "VDS_OK", 1: "VDS_ERR_ARG", 2: "VDS_ERR_HIP", 3: "VDS_ERR_NOMEM",
+                4: "VDS_ERR_NOT_CONVERGED", 5: "VDS_ERR_STATE"}
+
+
+class vds_problem(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("potential", C.c_int32), ("P", C.c_int64), ("kT", C.c_double),
+                ("zeta", C.c_double), ("n", C.c_double), ("h", C.c_double), ("dt", C.c_double),
+                ("G", C.c_double * 9), ("b_max", C.c_double), ("scheme", C.c_int32),
+                ("picard_max", C.c_int32), ("picard_rtol", C.c_double), ("picard_batch", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class vds_diag(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("iters", C.c_int32), ("last_iters", C.c_int32),
+                ("energy_valid", C.c_int32), ("resid", C.c_double), ("F", C.c_double),
+                ("dissipation", C.c_double), ("work", C.c_double), ("tau", C.c_double * 9)]
+
+    def as_dict(self):
+        return dict(steps=self.steps, iters=self.iters, last_iters=self.last_iters,
+                    energy_valid=self.energy_valid, resid=self.resid, F=self.F,
+                    dissipation=self.dissipation, work=self.work,
+                    tau=np.array(self.tau[:]).reshape(3, 3))
+
+
+class vds_tuning(C.Structure):
+    _fields_ = [("impl", C.c_int32), ("rows_per_wave", C.c_int32), ("col_splits", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_P = C.c_void_p
+_sigs = {
+    "vds_create": ([C.POINTER(vds_problem), C.POINTER(C.c_double), _P, C.POINTER(_P)], C.c_int),
+    "vds_destroy": ([_P], None),
+    "vds_workspace_bytes": ([C.POINTER(vds_problem)], C.c_size_t),
+    "vds_bind_workspace": ([_P, _P, C.c_size_t], C.c_int),
+    "vds_last_error": ([_P], C.c_char_p),
+    "vds_set_tuning": ([_P, C.POINTER(vds_tuning)], C.c_int),
+    "vds_get_tuning": ([_P, C.POINTER(vds_tuning)], C.c_int),
+    "vds_autotune": ([_P, _P, _P], C.c_int),
+    "vds_pair_sums": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "vds_velocity": ([_P, _P, _P, _P, C.POINTER(vds_diag)], C.c_int),
+    "vds_step": ([_P, _P, _P, C.c_int32, C.POINTER(vds_diag)], C.c_int),
+    "vds_stress": ([_P, _P, _P, C.POINTER(C.c_double)], C.c_int),
+    "vds_energy": ([_P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "vds_density_at": ([_P, _P, _P, _P, C.c_int64, _P], C.c_int),
+    "vds_timing_enable": ([_P, C.c_int32], C.c_int),
+    "vds_timing_read": ([_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
+}
+for _name, (_args, _ret) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _ret
+
+EXPORTED = tuple(_sigs)
+
+
+class VDSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(status, ctx=None):
+    if status != VDS_OK:
+        msg = _lib.vds_last_error(ctx)
+        raise VDSError(status, msg.decode() if msg else "")
+
+
+def make_problem(nb, P, h, dt=1e-3, kT=1.0, zeta=4.0, n=1.0, G=None, potential="hookean", b_max=0.0,
+                 scheme="implicit", picard_max=50, picard_rtol=1e-6, picard_batch=3) -> vds_problem:
+    pr = vds_problem()
+    pr.nb, pr.P, pr.h, pr.dt, pr.kT, pr.zeta, pr.n = int(nb), int(P), float(h), float(dt), float(kT), float(zeta), float(n)
+    G = np.zeros((3, 3)) if G is None else np.asarray(G, dtype=np.float64).reshape(3, 3)
+    for i, v in enumerate(G.reshape(-1)):
+        pr.G[i] = float(v)
+    pr.potential = VDS_FENE if potential == "fene" else VDS_HOOKEAN
+    pr.b_max = float(b_max)
+    pr.scheme = VDS_IMPLICIT if scheme == "implicit" else VDS_EXPLICIT
+    pr.picard_max, pr.picard_rtol, pr.picard_batch = int(picard_max), float(picard_rtol), int(picard_batch)
+    return pr
+
+
+class Context:
+    """One problem on one HIP stream, with a torch-allocated workspace."""
+
+    def __init__(self, nb, P, h, H=None, stream=None, device="cuda", poison=False, **kw):
+        self.nb, self.P, self.D = int(nb), int(P), 3 * int(nb)
+        self.device = torch.device(device)
+        self.prob = make_problem(nb, P, h, **kw)
+        H = np.ones(self.nb) if H is None else np.asarray(H, dtype=np.float64)
+        self._H = (C.c_double * self.nb)(*[float(v) for v in H])
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        _check(_lib.vds_create(C.byref(self.prob), self._H, C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+        nbytes = _lib.vds_workspace_bytes(C.byref(self.prob))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if poison:  # NaN-fill: any read of workspace the library did not write shows up
+            self.ws.fill_(255)
+        _check(_lib.vds_bind_workspace(self.ctx, _ptr(self.ws), nbytes), self.ctx)
+
+    def __del__(self):
+        if getattr(self, "ctx", None):
+            _lib.vds_destroy(self.ctx)
+            self.ctx = None
+
+    # -- tuning / timing --
+    def set_tuning(self, impl=VDS_PAIR_MFMA, rows_per_wave=2, col_splits=8):
+        t = vds_tuning(impl, rows_per_wave, col_splits, 0)
+        _check(_lib.vds_set_tuning(self.ctx, C.byref(t)), self.ctx)
+
+    def get_tuning(self):
+        t = vds_tuning()
+        _check(_lib.vds_get_tuning(self.ctx, C.byref(t)), self.ctx)
+        return dict(impl=t.impl, rows_per_wave=t.rows_per_wave, col_splits=t.col_splits)
+
+    def autotune(self, q, w=None):
+        _check(_lib.vds_autotune(self.ctx, _ptr(q), _ptr(w)), self.ctx)
+        return self.get_tuning()
+
+    def timing_enable(self, on=True):
+        _check(_lib.vds_timing_enable(self.ctx, 1 if on else 0), self.ctx)
+
+    def timing_read(self, which=VDS_TIMER_PAIR):
+        ms, n, work = C.c_double(), C.c_int64(), C.c_double()
+        _check(_lib.vds_timing_read(self.ctx, which, C.byref(ms), C.byref(n), C.byref(work)), self.ctx)
+        return dict(ms=ms.value, launches=n.value, work=work.value)
+
+    # -- scheme --
+    def _state(self):
+        return torch.empty((self.nb, self.P, 3), dtype=torch.float32, device=self.device)
+
+    def pair_sums(self, q, w=None):
+        S = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        t1, t2 = self._state(), self._state()
+        _check(_lib.vds_pair_sums(self.ctx, _ptr(q), _ptr(w), _ptr(S), _ptr(t1), _ptr(t2)), self.ctx)
+        return S, t1, t2
+
+    def velocity(self, q, w=None, diag=False):
+        v = self._state()
+        d = vds_diag()
+        _check(_lib.vds_velocity(self.ctx, _ptr(q), _ptr(w), _ptr(v), C.byref(d) if diag else None), self.ctx)
+        return (v, d.as_dict()) if diag else v
+
+    def step(self, q, w=None, nsteps=1):
+        d = vds_diag()
+        st = _lib.vds_step(self.ctx, _ptr(q), _ptr(w), int(nsteps), C.byref(d))
+        _check(st, self.ctx)
+        return d.as_dict()
+
+    def stress(self, q, w=None):
+        tau = (C.c_double * 9)()
+        _check(_lib.vds_stress(self.ctx, _ptr(q), _ptr(w), tau), self.ctx)
+        return np.array(tau[:]).reshape(3, 3)
+
+    def energy(self, q, w=None):
+        F, Dd, W = C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.vds_energy(self.ctx, _ptr(q), _ptr(w), C.byref(F), C.byref(Dd), C.byref(W)), self.ctx)
+        return F.value, Dd.value, W.value
+
+    def density_at(self, q, y, w=None):
+        y = y.contiguous()
+        f = torch.empty(y.shape[0], dtype=torch.float32, device=self.device)
+        _check(_lib.vds_density_at(self.ctx, _ptr(q), _ptr(w), _ptr(y), int(y.shape[0]), _ptr(f)), self.ctx)
+        return f
+
+
+# C names, re-exported for callers who drive the ABI directly
+globals().update({name: getattr(_lib, name) for name in EXPORTED})

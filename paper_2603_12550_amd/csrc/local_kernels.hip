@@ -1,0 +1,455 @@
+// O(P D) kernels around the pair passes: centring and operand packing, the
+// two finalisations (term1 and the pass-B weights; term2, drift and update),
+// the implicit-iteration control, and FP64 reductions of stress, energy,
+// dissipation and work.  All reductions are two-stage (per-block partials in
+// a fixed tree, then a fixed-order sum), so results are bitwise reproducible.
+#include "vds_internal.h"
+
+namespace vds {
+
+// Fixed-order tree sum over the 256 threads of a block for NS values each.
+template <int NS>
+__device__ void block_sum(double (&v)[NS], double (*sm)[kRedBlock]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) sm[s][t] = v[s];
+  __syncthreads();
+  for (int stride = kRedBlock / 2; stride > 0; stride >>= 1) {
+    if (t < stride) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) sm[s][t] += sm[s][t + stride];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < NS; ++s) v[s] = sm[s][0];
+}
+
+__device__ inline float load_weight(const float *w, int64_t I, float uniform_w) {
+  return w != nullptr ? w[I] : uniform_w;
+}
+
+// Swizzled operand positions (see pair_kernels.hip):
+//   QB/KA: element k of the augmented vector of particle I at
+//          [((I / 16) * KK + k / 4) * 64 + (I % 16) + 16 (k % 4)]
+//   VB:    element n of V_J at [((J / 16) * 64 + ((J % 16) / 4) * 16 + n) * 4 + (J % 4)]
+__device__ inline int64_t qk_index(int64_t I, int k, int KK) {
+  return ((I >> 4) * KK + (k >> 2)) * 64 + (I & 15) + 16 * (k & 3);
+}
+__device__ inline int64_t v_index(int64_t J, int n) {
+  return ((J >> 4) * 64 + ((J & 15) >> 2) * 16 + n) * 4 + (J & 3);
+}
+
+// Partial sums of w_I x_I (FP64) per block, for the weighted centring.
+__global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const float *__restrict__ q,
+                                                             const float *__restrict__ w, double *__restrict__ meanp,
+                                                             const int *__restrict__ done) {
+  __shared__ double sm[kMaxD][kRedBlock];
+  if (done != nullptr && *done) return;
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  double v[kMaxD];
+  const double wi = I < p.P ? (double)load_weight(w, I, p.uniform_w) : 0.0;
+#pragma unroll
+  for (int a = 0; a < kMaxD; ++a) {
+    const int k = a / 3, al = a % 3;
+    v[a] = (I < p.P && a < p.D) ? wi * (double)q[((int64_t)k * p.P + I) * 3 + al] : 0.0;
+  }
+  block_sum<kMaxD>(v, sm);
+  if (threadIdx.x < kMaxD) meanp[(int64_t)blockIdx.x * 16 + threadIdx.x] = v[threadIdx.x];
+}
+
+// Sum of the centring partials, computed identically by every block.
+__device__ void load_mean(const EvalParams &p, const double *meanp, int nmeanp, float *mean_sh) {
+  if (threadIdx.x < p.D) {
+    double s = 0.0;
+    for (int b = 0; b < nmeanp; ++b) s += meanp[(int64_t)b * 16 + threadIdx.x];
+    mean_sh[threadIdx.x] = (float)s;
+  }
+  __syncthreads();
+}
+
+// Centre, pack Q/K operands and the pass-A V operand (weights w).
+__global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *__restrict__ q,
+                                                    const float *__restrict__ w, const double *__restrict__ meanp,
+                                                    int nmeanp, float *__restrict__ xc, float *__restrict__ wv,
+                                                    float *__restrict__ QB, float *__restrict__ KA,
+                                                    float *__restrict__ VA, const int *__restrict__ done) {
+  __shared__ float mean_sh[kMaxD];
+  if (done != nullptr && *done) return;
+  load_mean(p, meanp, nmeanp, mean_sh);
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (I >= p.Ppad) return;
+  const bool real = I < p.P;
+  float x[kMaxD];
+  float nrm = 0.f;
+#pragma unroll
+  for (int a = 0; a < kMaxD; ++a) {
+    const int k = a / 3, al = a % 3;
+    x[a] = (real && a < p.D) ? q[((int64_t)k * p.P + I) * 3 + al] - mean_sh[a] : 0.f;
+    nrm = fmaf(x[a], x[a], nrm);
+  }
+  const float wi = real ? load_weight(w, I, p.uniform_w) : 0.f;
+  wv[I] = wi;
+  for (int a = 0; a < p.D; ++a) xc[I * p.D + a] = x[a];
+  const int alen = 4 * p.KK;
+  for (int k = 0; k < alen; ++k) {
+    float qa, ka;
+    if (!real) {
+      qa = 0.f;
+      ka = 0.f;
+    } else if (k < p.D) {
+      qa = x[k];
+      ka = 2.f * p.kappa * x[k];
+    } else if (k == p.D) {
+      qa = -p.kappa * nrm;
+      ka = 1.f;
+    } else if (k == p.D + 1) {
+      qa = 1.f;
+      ka = -p.kappa * nrm;
+    } else {
+      qa = 0.f;
+      ka = 0.f;
+    }
+    QB[qk_index(I, k, p.KK)] = qa;
+    KA[qk_index(I, k, p.KK)] = ka;
+  }
+  for (int n = 0; n < 16; ++n) {
+    float v = 0.f;
+    if (n < p.D) v = wi * x[n];
+    else if (n == p.D) v = wi;
+    VA[v_index(I, n)] = v;
+  }
+}
+
+// Sum of the split partials of row I in FP64: o[n] for n <= D.
+__device__ inline void sum_splits(const EvalParams &p, const float *__restrict__ partial, int splits, int64_t I,
+                                  double (&o)[kMaxD + 1]) {
+#pragma unroll
+  for (int n = 0; n <= kMaxD; ++n) o[n] = 0.0;
+  for (int s = 0; s < splits; ++s) {
+    const float *src = partial + ((int64_t)s * p.Ppad + I) * 16;
+#pragma unroll
+    for (int n = 0; n <= kMaxD; ++n)
+      if (n <= p.D) o[n] += (double)src[n];
+  }
+}
+
+// Pass-A finalisation: S_I = sum_J w_J e_IJ, term1_I = -(1/h^2) sum_J w_J e_IJ (x_I - x_J) / S_I,
+// and the pass-B operand with weights w_J / S_J.
+__global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, int splits,
+                                                          const float *__restrict__ xc, const float *__restrict__ wv,
+                                                          float *__restrict__ S, float *__restrict__ t1,
+                                                          float *__restrict__ VB, const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (I >= p.Ppad) return;
+  if (I >= p.P) {  // padding columns carry zero weight in pass B too
+    for (int n = 0; n < 16; ++n) VB[v_index(I, n)] = 0.f;
+    return;
+  }
+  double o[kMaxD + 1];
+  sum_splits(p, partial, splits, I, o);
+  const double Si = o[p.D] + (double)wv[I];  // the pass left out the self term w_I e_II = w_I
+  S[I] = (float)Si;
+  const float wb = (float)((double)wv[I] / Si);
+  for (int a = 0; a < p.D; ++a) {
+    t1[I * p.D + a] = (float)(-(double)p.inv_h2 * o[a] / Si);
+    VB[v_index(I, a)] = wb * xc[I * p.D + a];
+  }
+  VB[v_index(I, p.D)] = wb;
+  for (int n = p.D + 1; n < 16; ++n) VB[v_index(I, n)] = 0.f;
+}
+
+__device__ inline void atomic_max_bits(unsigned *addr, float v) {
+  atomicMax(addr, __float_as_uint(fabsf(v)));
+}
+
+// Pass-B finalisation and everything local: term2, b = term1 + term2,
+// g = kT b + grad Psi, u = -(1/zeta)(A (x) I) g, flow G q, and by mode the
+// terms, the velocity, an explicit update or a fixed-point update.  With `obs`
+// it also accumulates F_h, dissipation, work and stress in FP64.
+__global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, int obs,
+                                                       const float *__restrict__ partial, int splits,
+                                                       const float *__restrict__ xc, const float *__restrict__ t1,
+                                                       const float *__restrict__ S, const float *__restrict__ wv,
+                                                       const float *qin, const float *__restrict__ qstar,
+                                                       float *out, float *out2, double *__restrict__ redp,
+                                                       Ctrl *ctrl, const int *__restrict__ done) {
+  __shared__ double sm[12][kRedBlock];
+  if (done != nullptr && *done) return;
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  const bool real = I < p.P;
+  double red[12];
+#pragma unroll
+  for (int s = 0; s < 12; ++s) red[s] = 0.0;
+  float resid = 0.f, xmax = 0.f;
+
+  if (real) {
+    double o[kMaxD + 1];
+    sum_splits(p, partial, splits, I, o);
+    float b[kMaxD], t2v[kMaxD];
+#pragma unroll
+    for (int a = 0; a < kMaxD; ++a) {
+      if (a < p.D) {
+        t2v[a] = (float)(-(double)p.inv_h2 * o[a]);
+        b[a] = t1[I * p.D + a] + t2v[a];
+      } else {
+        t2v[a] = 0.f;
+        b[a] = 0.f;
+      }
+    }
+    if (mode == MODE_TERMS) {
+      for (int a = 0; a < p.D; ++a) {
+        const int k = a / 3, al = a % 3;
+        out[((int64_t)k * p.P + I) * 3 + al] = t1[I * p.D + a];
+        out2[((int64_t)k * p.P + I) * 3 + al] = t2v[a];
+      }
+    } else {
+      float qv[kMaxD], g[kMaxD], psi = 0.f, gp[kMaxD];
+#pragma unroll
+      for (int a = 0; a < kMaxD; ++a) qv[a] = 0.f;
+      for (int a = 0; a < p.D; ++a) qv[a] = qin[((int64_t)(a / 3) * p.P + I) * 3 + (a % 3)];
+#pragma unroll
+      for (int k = 0; k < kMaxNb; ++k) {
+        if (k >= p.nb) break;
+        const float r2 = qv[3 * k] * qv[3 * k] + qv[3 * k + 1] * qv[3 * k + 1] + qv[3 * k + 2] * qv[3 * k + 2];
+        float fac = p.H[k];
+        if (p.potential == VDS_FENE) {
+          const float s = 1.f - r2 / p.b_max;
+          fac = p.H[k] / s;
+          psi += -0.5f * p.H[k] * p.b_max * logf(s);
+        } else {
+          psi += 0.5f * p.H[k] * r2;
+        }
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          gp[3 * k + al] = fac * qv[3 * k + al];
+          g[3 * k + al] = p.kT * b[3 * k + al] + gp[3 * k + al];
+        }
+      }
+      // (A (x) I) g with A = tridiag(-1, 2, -1)
+      float Ag[kMaxD];
+#pragma unroll
+      for (int k = 0; k < kMaxNb; ++k) {
+        if (k >= p.nb) break;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          float v = 2.f * g[3 * k + al];
+          if (k > 0) v -= g[3 * (k - 1) + al];
+          if (k + 1 < p.nb) v -= g[3 * (k + 1) + al];
+          Ag[3 * k + al] = v;
+        }
+      }
+      for (int k = 0; k < p.nb; ++k) {
+        float flow[3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+          flow[al] = p.G[3 * al] * qv[3 * k] + p.G[3 * al + 1] * qv[3 * k + 1] + p.G[3 * al + 2] * qv[3 * k + 2];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          const int a = 3 * k + al;
+          const int64_t idx = ((int64_t)k * p.P + I) * 3 + al;
+          const float u = -p.inv_zeta * Ag[a];
+          if (mode == MODE_VELOCITY) {
+            out[idx] = flow[al] + u;
+          } else if (mode == MODE_EXPLICIT) {
+            out[idx] = qv[a] + p.dt * (flow[al] + u);
+          } else if (mode == MODE_PICARD) {
+            const float xn = qstar[idx] + p.dt * u;
+            out[idx] = xn;
+            resid = fmaxf(resid, fabsf(xn - qv[a]));
+            xmax = fmaxf(xmax, fabsf(xn));
+          }
+        }
+        if (obs) {
+          const double wi = (double)wv[I];
+          for (int al = 0; al < 3; ++al) {
+            const int a = 3 * k + al;
+            red[RED_DISS] += wi * (double)g[a] * (double)Ag[a] * (double)p.inv_zeta;
+            red[RED_WORK] += wi * (double)g[a] * (double)flow[al];
+            for (int be = 0; be < 3; ++be)
+              red[RED_TAU + 3 * al + be] += (double)p.n * wi * (double)qv[a] * (double)gp[3 * k + be];
+          }
+        }
+      }
+      if (obs) {
+        const double wi = (double)wv[I];
+        red[RED_F] = wi * ((double)p.kT * (log((double)S[I]) - (double)p.log_norm) + (double)psi);
+      }
+    }
+  }
+  if (obs) {
+    block_sum<12>(red, sm);
+    if (threadIdx.x < 12) redp[(int64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
+  }
+  if (mode == MODE_PICARD) {
+    // wave-level max, then one atomic per wave (max is order independent)
+    for (int off = 32; off > 0; off >>= 1) {
+      resid = fmaxf(resid, __shfl_xor(resid, off));
+      xmax = fmaxf(xmax, __shfl_xor(xmax, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomic_max_bits(&ctrl->resid, resid);
+      atomic_max_bits(&ctrl->xmax, xmax);
+    }
+  }
+}
+
+__global__ void k_reduce_final(const double *__restrict__ redp, int nblk, int nslots, double *__restrict__ out,
+                               const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int s = threadIdx.x;
+  if (s >= nslots) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += redp[(int64_t)b * 16 + s];
+  out[s] = acc;
+}
+
+// q* = q + dt G q (the flow term of the implicit step is taken at t).
+__global__ __launch_bounds__(kRedBlock) void k_qstar(EvalParams p, const float *__restrict__ q,
+                                                     float *__restrict__ qstar) {
+  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (i >= (int64_t)p.nb * p.P) return;
+  const float a = q[i * 3], b = q[i * 3 + 1], c = q[i * 3 + 2];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+    qstar[i * 3 + al] = q[i * 3 + al] + p.dt * (p.G[3 * al] * a + p.G[3 * al + 1] * b + p.G[3 * al + 2] * c);
+}
+
+__global__ void k_picard_check(Ctrl *ctrl, float rtol, int iter) {
+  if (threadIdx.x != 0 || ctrl->done) return;
+  const float r = __uint_as_float(ctrl->resid);
+  const float xm = __uint_as_float(ctrl->xmax);
+  ctrl->last_resid = r;
+  ctrl->checked = iter + 1;
+  if (r <= rtol * fmaxf(1.f, xm)) {
+    ctrl->done = 1;
+    ctrl->conv_iter = iter;
+  }
+  ctrl->resid = 0u;
+  ctrl->xmax = 0u;
+}
+
+__global__ void k_ctrl_reset(Ctrl *ctrl) {
+  if (threadIdx.x != 0) return;
+  ctrl->done = 0;
+  ctrl->conv_iter = -1;
+  ctrl->resid = 0u;
+  ctrl->xmax = 0u;
+  ctrl->last_resid = 0.f;
+  ctrl->checked = 0;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_stress(EvalParams p, const float *__restrict__ q,
+                                                      const float *__restrict__ w, double *__restrict__ redp) {
+  __shared__ double sm[9][kRedBlock];
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  double t[9];
+#pragma unroll
+  for (int s = 0; s < 9; ++s) t[s] = 0.0;
+  if (I < p.P) {
+    const double wi = (double)load_weight(w, I, p.uniform_w) * (double)p.n;
+    for (int k = 0; k < p.nb; ++k) {
+      const float *qk = q + ((int64_t)k * p.P + I) * 3;
+      const float r2 = qk[0] * qk[0] + qk[1] * qk[1] + qk[2] * qk[2];
+      const float fac = p.potential == VDS_FENE ? p.H[k] / (1.f - r2 / p.b_max) : p.H[k];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t[3 * a + b] += wi * (double)qk[a] * (double)(fac * qk[b]);
+    }
+  }
+  block_sum<9>(t, sm);
+  if (threadIdx.x < 9) redp[(int64_t)blockIdx.x * 16 + threadIdx.x] = t[threadIdx.x];
+}
+
+// Foreign rows y[ny][D] (particle-major) as Q operands, centred like the particles.
+__global__ __launch_bounds__(kRedBlock) void k_density_rows(EvalParams p, const float *__restrict__ y, int64_t ny,
+                                                            const double *__restrict__ meanp, int nmeanp,
+                                                            float *__restrict__ QB, int64_t nrows_pad) {
+  __shared__ float mean_sh[kMaxD];
+  load_mean(p, meanp, nmeanp, mean_sh);
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (I >= nrows_pad) return;
+  float x[kMaxD];
+  float nrm = 0.f;
+  for (int a = 0; a < p.D; ++a) {
+    x[a] = I < ny ? y[I * p.D + a] - mean_sh[a] : 0.f;
+    nrm = fmaf(x[a], x[a], nrm);
+  }
+  for (int k = 0; k < 4 * p.KK; ++k) {
+    float qa = 0.f;
+    if (I < ny) {
+      if (k < p.D) qa = x[k];
+      else if (k == p.D) qa = -p.kappa * nrm;
+      else if (k == p.D + 1) qa = 1.f;
+    }
+    QB[qk_index(I, k, p.KK)] = qa;
+  }
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_density_out(const float *__restrict__ partial, int splits,
+                                                           int64_t stride_rows, int64_t ny, int D, float norm,
+                                                           float *__restrict__ f) {
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (I >= ny) return;
+  float s = 0.f;
+  for (int sp = 0; sp < splits; ++sp) s += partial[((int64_t)sp * stride_rows + I) * 16 + D];
+  f[I] = s * norm;
+}
+
+// ---- launchers ----
+
+static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kRedBlock - 1) / kRedBlock); }
+
+void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done,
+                          hipStream_t s) {
+  k_mean_partials<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, meanp, done);
+}
+void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
+                 float *wv, float *QB, float *KA, float *VA, const int *done, hipStream_t s) {
+  k_prep<<<nblocks(p.Ppad), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, done);
+}
+void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
+                       float *S, float *t1, float *VB, const int *done, hipStream_t s) {
+  k_finalize_a<<<nblocks(p.Ppad), kRedBlock, 0, s>>>(p, partial, splits, xc, wv, S, t1, VB, done);
+}
+void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
+                    const float *t1, const float *S, const float *wv, const float *qin, const float *qstar,
+                    float *out, float *out2, double *redp, Ctrl *ctrl, const int *done, hipStream_t s) {
+  k_combine<<<nblocks(p.P), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, qstar,
+                                               out, out2, redp, ctrl, done);
+}
+void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s) {
+  k_reduce_final<<<1, 64, 0, s>>>(redp, nblk, nslots, out, done);
+}
+void launch_qstar(const EvalParams &p, const float *q, float *qstar, hipStream_t s) {
+  k_qstar<<<nblocks((int64_t)p.nb * p.P), kRedBlock, 0, s>>>(p, q, qstar);
+}
+void launch_picard_check(Ctrl *ctrl, float rtol, int iter, hipStream_t s) {
+  k_picard_check<<<1, 64, 0, s>>>(ctrl, rtol, iter);
+}
+void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s) { k_ctrl_reset<<<1, 64, 0, s>>>(ctrl); }
+void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s) {
+  k_stress<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, redp);
+}
+void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,
+                         float *QB, hipStream_t s) {
+  // rows are padded to a multiple of 256 within the Ppad-row operand buffer
+  const int64_t nrows_pad = round_up(ny, kRowAlign);
+  k_density_rows<<<nblocks(nrows_pad), kRedBlock, 0, s>>>(p, y, ny, meanp, nmeanp, QB, nrows_pad);
+}
+void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm, float *f,
+                        hipStream_t s) {
+  k_density_out<<<nblocks(ny), kRedBlock, 0, s>>>(partial, splits, p.Ppad, ny, p.D, norm, f);
+}
+
+__global__ void k_copy(const float *__restrict__ src, float *__restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+void launch_copy(const float *src, float *dst, int64_t n, const int *, hipStream_t s) {
+  k_copy<<<nblocks(n), kRedBlock, 0, s>>>(src, dst, n);
+}
+
+}  // namespace vds

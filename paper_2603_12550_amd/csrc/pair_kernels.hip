@@ -1,0 +1,281 @@
+// Pair kernels: the O(P^2) Gaussian blob-kernel sums of the particle scheme.
+//
+// One pass computes, for every row particle I and a column weight vector wh,
+//   O_I[n] = sum_J e_IJ V_J[n],   V_J = (wh_J x_J, wh_J),
+//   e_IJ   = exp2(min(t_IJ, 0)),  t_IJ = -kappa |x_I - x_J|^2,  kappa = log2(e) / 2h^2,
+// over all J including J = I (eq. model_DeteParAppr and the two kernel sums of
+// eq. model_DymRepPar).  The squared distance is expanded through augmented
+// vectors so that t_IJ is one dot product:
+//   Q_I = (x_I, -kappa |x_I|^2, 1),  K_J = (2 kappa x_J, 1, -kappa |x_J|^2),
+//   t_IJ = Q_I . K_J.
+// The min(., 0) is the clamp of the expanded |x_I - x_J|^2 at zero.
+//
+// Two implementations share the operand arrays the prep kernel writes:
+//  * MFMA: each wavefront owns RB blocks of 16 rows; per 16-column chunk,
+//    ceil((D+2)/4) v_mfma_f32_16x16x4_f32 form t for a 16x16 pair tile, the
+//    VALU takes exp2, and four more MFMAs accumulate e V.  The accumulator
+//    layout of the first product is already the A-operand layout of the second
+//    once the chunk's columns are visited in the order 4k + i, which is how the
+//    prep kernel stores V.  Operands are pre-swizzled so every lane reads
+//    consecutive dwords.
+//  * VALU: one thread per row pair, column tiles of 256 staged in LDS, FP32
+//    FMAs, v_exp_f32.
+// Column ranges are split over blockIdx.y; every split writes its own partial
+// sums, reduced later in a fixed order (deterministic, no float atomics).
+//
+// Accuracy: the drift needs x_I S_I - M_I, a difference of two sums whose
+// magnitudes can exceed it by an order of magnitude (narrow kernels, isolated
+// particles).  Plain FP32 accumulation over thousands of columns would leave
+// errors of ~1e-6 relative to the sums, amplified by that ratio.  So the FP32
+// accumulators are flushed into FP64 running sums every kFlush chunks (16
+// columns each), and the kernel itself forms, in FP64,
+//   A_I[n] = x_I[n] O_I[D] - O_I[n]  (n < D),   O_I[D] = sum_J e_IJ wh_J,
+// i.e. it writes sum_J e_IJ wh_J (x_I - x_J) and the weighted kernel sum.
+// With exclude_self the J = I term is left out of both sums: it adds nothing to
+// the difference sum, but for an isolated particle it dominates the kernel sum
+// and would swamp its neighbours' contributions in FP32.  The caller adds the
+// self weight back in FP64.
+#include "vds_internal.h"
+
+namespace vds {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFlush = 4;  // chunks per FP32 accumulation group
+
+template <int KK, int RB>
+__global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB, int64_t nrow_blocks,
+                                                   const float *__restrict__ KA, const float4 *__restrict__ VB,
+                                                   int64_t ncol_chunks, int64_t chunks_per_split,
+                                                   const float *__restrict__ xc, int D, int exclude_self,
+                                                   float *__restrict__ partial, int64_t part_stride_rows,
+                                                   const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int lane = threadIdx.x & 63;
+  // position of the self pair inside a diagonal 16x16 tile, per element i
+  const int diag_i = (lane & 15) - 4 * (lane >> 4);  // in 0..3 when this lane holds one
+  const int wave = threadIdx.x >> 6;
+  const int64_t rb0 = ((int64_t)blockIdx.x * 4 + wave) * RB;
+  if (rb0 >= nrow_blocks) return;  // no barriers below: a wave may leave alone
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = min(ncol_chunks, c0 + chunks_per_split);
+
+  float qv[RB][KK];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+      qv[r][kk] = (rb0 + r < nrow_blocks) ? QB[((rb0 + r) * KK + kk) * 64 + lane] : 0.f;
+
+  double tot[RB][4];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[r][i] = 0.0;
+
+  float ka[KK];
+  float4 vb;
+  if (c0 < c1) {
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) ka[kk] = KA[(c0 * KK + kk) * 64 + lane];
+    vb = VB[c0 * 64 + lane];
+  }
+  for (int64_t c = c0; c < c1;) {
+    const int64_t cg_end = min(c1, c + kFlush);
+    floatx4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; c < cg_end; ++c) {
+      // prefetch the next chunk's operands while this one computes
+      float kn[KK];
+      float4 vn;
+      const int64_t cn = (c + 1 < c1) ? c + 1 : c;
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk) kn[kk] = KA[(cn * KK + kk) * 64 + lane];
+      vn = VB[cn * 64 + lane];
+
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        floatx4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ka[kk], qv[r][kk], t, 0, 0, 0);
+        float e0 = __builtin_amdgcn_exp2f(fminf(t[0], 0.f));
+        float e1 = __builtin_amdgcn_exp2f(fminf(t[1], 0.f));
+        float e2 = __builtin_amdgcn_exp2f(fminf(t[2], 0.f));
+        float e3 = __builtin_amdgcn_exp2f(fminf(t[3], 0.f));
+        if (exclude_self && c == rb0 + r) {  // wave-uniform: the diagonal tile
+          e0 = diag_i == 0 ? 0.f : e0;
+          e1 = diag_i == 1 ? 0.f : e1;
+          e2 = diag_i == 2 ? 0.f : e2;
+          e3 = diag_i == 3 ? 0.f : e3;
+        }
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(e0, vb.x, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(e1, vb.y, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(e2, vb.z, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(e3, vb.w, acc[r], 0, 0, 0);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk) ka[kk] = kn[kk];
+      vb = vn;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tot[r][i] += (double)acc[r][i];
+  }
+
+  // lane holds O[row 4 (lane / 16) + i][column lane % 16] of each row block;
+  // the weighted kernel sum O[.][D] sits in lane (lane & 48) + D
+  const int n = lane & 15;
+  const int src = (lane & 48) + D;
+  float *out = partial + (int64_t)blockIdx.y * part_stride_rows * 16;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (rb0 + r >= nrow_blocks) break;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double s = __shfl(tot[r][i], src);
+      const int64_t row = (rb0 + r) * 16 + 4 * (lane >> 4) + i;
+      double v = 0.0;
+      if (n < D) v = (double)xc[row * D + n] * s - tot[r][i];
+      else if (n == D) v = s;
+      out[row * 16 + n] = (float)v;
+    }
+  }
+}
+
+// VALU variant.  D is the configuration dimension; the augmented length is D + 2.
+// FP32 accumulation over 64 columns, then FP64 running sums (see above).
+template <int D>
+__global__ __launch_bounds__(256) void k_pair_valu(const float *__restrict__ QB, int64_t nrows,
+                                                   const float *__restrict__ KA, const float *__restrict__ VB,
+                                                   int64_t ncol_chunks, int64_t chunks_per_split, int exclude_self,
+                                                   float *__restrict__ partial, int64_t part_stride_rows,
+                                                   const int *__restrict__ done) {
+  constexpr int KA_LEN = D + 2;
+  constexpr int KK = (D + 2 + 3) / 4;
+  constexpr int NV = D + 1;
+  constexpr int RT = 2;
+  __shared__ float sK[KA_LEN][256];
+  __shared__ float sV[NV][256];
+  if (done != nullptr && *done) return;
+
+  const int tid = threadIdx.x;
+  int64_t rows[RT];
+  float q[RT][KA_LEN];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    rows[r] = (int64_t)blockIdx.x * (256 * RT) + r * 256 + tid;
+    const int64_t I = rows[r] < nrows ? rows[r] : 0;
+#pragma unroll
+    for (int k = 0; k < KA_LEN; ++k)
+      q[r][k] = QB[((I >> 4) * KK + (k >> 2)) * 64 + (I & 15) + 16 * (k & 3)];
+  }
+  double tot[RT][NV];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int n = 0; n < NV; ++n) tot[r][n] = 0.0;
+
+  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t c1 = min(ncol_chunks, c0 + chunks_per_split);
+  for (int64_t tile = c0; tile < c1; tile += 16) {
+    const int64_t c = tile + (tid >> 4);
+    const int jj = tid & 15;
+    if (c < c1) {
+#pragma unroll
+      for (int k = 0; k < KA_LEN; ++k) sK[k][tid] = KA[(c * KK + (k >> 2)) * 64 + jj + 16 * (k & 3)];
+#pragma unroll
+      for (int n = 0; n < NV; ++n) sV[n][tid] = VB[(c * 64 + (jj >> 2) * 16 + n) * 4 + (jj & 3)];
+    } else {
+#pragma unroll
+      for (int k = 0; k < KA_LEN; ++k) sK[k][tid] = 0.f;
+#pragma unroll
+      for (int n = 0; n < NV; ++n) sV[n][tid] = 0.f;
+    }
+    __syncthreads();
+    for (int j0 = 0; j0 < 256; j0 += 64) {
+      float acc[RT][NV];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int n = 0; n < NV; ++n) acc[r][n] = 0.f;
+      for (int j = j0; j < j0 + 64; ++j) {
+        const int64_t col = tile * 16 + j;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          float t = 0.f;
+#pragma unroll
+          for (int k = 0; k < KA_LEN; ++k) t = fmaf(q[r][k], sK[k][j], t);
+          float e = __builtin_amdgcn_exp2f(fminf(t, 0.f));
+          if (exclude_self && col == rows[r]) e = 0.f;
+#pragma unroll
+          for (int n = 0; n < NV; ++n) acc[r][n] = fmaf(e, sV[n][j], acc[r][n]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int n = 0; n < NV; ++n) tot[r][n] += (double)acc[r][n];
+    }
+    __syncthreads();
+  }
+  float *out = partial + (int64_t)blockIdx.y * part_stride_rows * 16;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    if (rows[r] >= nrows) continue;
+    const double s = tot[r][D];
+#pragma unroll
+    for (int n = 0; n < D; ++n) out[rows[r] * 16 + n] = (float)((double)q[r][n] * s - tot[r][n]);
+    out[rows[r] * 16 + D] = (float)s;
+  }
+}
+
+bool pair_shape_ok(const vds_tuning &t, int D) {
+  if (D < 3 || D > kMaxD || D % 3 != 0) return false;
+  if (t.col_splits < 1 || t.col_splits > kMaxSplits) return false;
+  if (t.impl == VDS_PAIR_MFMA) return t.rows_per_wave == 1 || t.rows_per_wave == 2 || t.rows_per_wave == 4;
+  return t.impl == VDS_PAIR_VALU;
+}
+
+template <int KK>
+static void launch_mfma_kk(int rb, dim3 grid, const float *QB, int64_t nrb, const float *KA, const float *VB,
+                           int64_t ncc, int64_t cps, const float *xc, int D, int ex, float *partial, int64_t stride,
+                           const int *done, hipStream_t s) {
+  const float4 *vb = reinterpret_cast<const float4 *>(VB);
+  switch (rb) {
+    case 1: k_pair_mfma<KK, 1><<<grid, 256, 0, s>>>(QB, nrb, KA, vb, ncc, cps, xc, D, ex, partial, stride, done); break;
+    case 2: k_pair_mfma<KK, 2><<<grid, 256, 0, s>>>(QB, nrb, KA, vb, ncc, cps, xc, D, ex, partial, stride, done); break;
+    default: k_pair_mfma<KK, 4><<<grid, 256, 0, s>>>(QB, nrb, KA, vb, ncc, cps, xc, D, ex, partial, stride, done); break;
+  }
+}
+
+void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64_t nrow_blocks, const float *KA,
+                      const float *VB, int64_t ncol_chunks, const float *xc, bool exclude_self, float *partial,
+                      int64_t part_stride_rows, const int *done, hipStream_t s) {
+  const int ex = exclude_self ? 1 : 0;
+  const int splits = t.col_splits;
+  const int64_t cps = (ncol_chunks + splits - 1) / splits;
+  if (t.impl == VDS_PAIR_MFMA) {
+    const int rb = t.rows_per_wave;
+    dim3 grid((unsigned)((nrow_blocks + 4 * rb - 1) / (4 * rb)), (unsigned)splits);
+    switch (KK) {
+      case 2: launch_mfma_kk<2>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      case 3: launch_mfma_kk<3>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      case 4: launch_mfma_kk<4>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      default: launch_mfma_kk<5>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+    }
+  } else {
+    const int64_t nrows = nrow_blocks * 16;
+    dim3 grid((unsigned)((nrows + 511) / 512), (unsigned)splits);
+    switch (D) {
+      case 3: k_pair_valu<3><<<grid, 256, 0, s>>>(QB, nrows, KA, VB, ncol_chunks, cps, ex, partial, part_stride_rows, done); break;
+      case 6: k_pair_valu<6><<<grid, 256, 0, s>>>(QB, nrows, KA, VB, ncol_chunks, cps, ex, partial, part_stride_rows, done); break;
+      case 9: k_pair_valu<9><<<grid, 256, 0, s>>>(QB, nrows, KA, VB, ncol_chunks, cps, ex, partial, part_stride_rows, done); break;
+      case 12: k_pair_valu<12><<<grid, 256, 0, s>>>(QB, nrows, KA, VB, ncol_chunks, cps, ex, partial, part_stride_rows, done); break;
+      default: k_pair_valu<15><<<grid, 256, 0, s>>>(QB, nrows, KA, VB, ncol_chunks, cps, ex, partial, part_stride_rows, done); break;
+    }
+  }
+}
+
+}  // namespace vds

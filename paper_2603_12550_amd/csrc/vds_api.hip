@@ -1,0 +1,538 @@
+// C ABI of the particle scheme: context, workspace binding, evaluation
+// sequences, the implicit iteration loop, observables and kernel timing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vds_internal.h"
+
+using namespace vds;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Layout {
+  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, qstar, xb0, xb1, total;
+};
+
+struct TimerAcc {
+  double ms = 0.0;
+  int64_t launches = 0;
+  double work = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<double> pending_work;
+};
+
+}  // namespace
+
+struct vds_ctx_s {
+  vds_problem prob{};
+  std::vector<double> H;
+  hipStream_t stream = nullptr;
+  EvalParams ep{};
+  vds_tuning tune{VDS_PAIR_MFMA, 2, 8, 0};
+  Layout lay{};
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+  bool timing = false;
+  TimerAcc timers[VDS_TIMER_COUNT];
+  std::vector<hipEvent_t> event_pool;
+
+  // workspace views
+  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *qstar, *xb[2];
+  double *meanp, *redp, *redout;
+  Ctrl *ctrl;
+  int nblk;  // blocks of the O(P) kernels over real particles
+};
+
+namespace {
+
+bool problem_valid(const vds_problem *p, std::string *why) {
+  auto fail = [&](const char *m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (p == nullptr) return fail("problem is NULL");
+  if (p->nb < 1 || p->nb > kMaxNb) return fail("nb must be in 1..5 (D = 3 nb <= 15)");
+  if (p->P < 1) return fail("P must be >= 1");
+  if (p->P > (int64_t)1 << 28) return fail("P too large");
+  if (!(p->h > 0.0) || !std::isfinite(p->h)) return fail("h must be positive and finite");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail("dt must be positive and finite");
+  if (!(p->zeta > 0.0) || !std::isfinite(p->zeta)) return fail("zeta must be positive and finite");
+  if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return fail("kT must be >= 0 and finite");
+  if (!std::isfinite(p->n)) return fail("n must be finite");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(p->G[i])) return fail("G must be finite");
+  if (p->potential != VDS_HOOKEAN && p->potential != VDS_FENE) return fail("unknown potential");
+  if (p->potential == VDS_FENE && !(p->b_max > 0.0)) return fail("FENE needs b_max > 0");
+  if (p->scheme != VDS_EXPLICIT && p->scheme != VDS_IMPLICIT) return fail("unknown scheme");
+  if (p->scheme == VDS_IMPLICIT) {
+    if (p->picard_max < 1) return fail("picard_max must be >= 1");
+    if (!(p->picard_rtol > 0.0)) return fail("picard_rtol must be > 0");
+    if (p->picard_batch < 1) return fail("picard_batch must be >= 1");
+  }
+  return true;
+}
+
+Layout make_layout(const vds_problem &p) {
+  const int64_t Ppad = round_up(p.P, kRowAlign);
+  const int D = 3 * p.nb;
+  const int KK = (D + 2 + 3) / 4;
+  const int64_t nblk = (p.P + kRedBlock - 1) / kRedBlock;
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += round_up((int64_t)bytes, 256);
+    return o;
+  };
+  L.QB = take(sizeof(float) * Ppad * KK * 4);
+  L.KA = take(sizeof(float) * Ppad * KK * 4);
+  L.VA = take(sizeof(float) * Ppad * 16);
+  L.VB = take(sizeof(float) * Ppad * 16);
+  L.part = take(sizeof(float) * (size_t)kMaxSplits * Ppad * 16);
+  L.xc = take(sizeof(float) * Ppad * D);
+  L.t1 = take(sizeof(float) * Ppad * D);
+  L.S = take(sizeof(float) * Ppad);
+  L.wv = take(sizeof(float) * Ppad);
+  L.meanp = take(sizeof(double) * nblk * 16);
+  L.redp = take(sizeof(double) * nblk * 16);
+  L.redout = take(sizeof(double) * 16);
+  L.ctrl = take(sizeof(Ctrl));
+  L.qstar = take(sizeof(float) * p.P * D);
+  L.xb0 = take(sizeof(float) * p.P * D);
+  L.xb1 = take(sizeof(float) * p.P * D);
+  L.total = off;
+  return L;
+}
+
+void fill_params(vds_ctx c) {
+  const vds_problem &p = c->prob;
+  EvalParams &e = c->ep;
+  e.P = p.P;
+  e.Ppad = round_up(p.P, kRowAlign);
+  e.nb = p.nb;
+  e.D = 3 * p.nb;
+  e.KK = (e.D + 2 + 3) / 4;
+  e.kappa = (float)(1.4426950408889634 / (2.0 * p.h * p.h));
+  e.inv_h2 = (float)(1.0 / (p.h * p.h));
+  e.kT = (float)p.kT;
+  e.inv_zeta = (float)(1.0 / p.zeta);
+  e.dt = (float)p.dt;
+  e.n = (float)p.n;
+  for (int i = 0; i < 9; ++i) e.G[i] = (float)p.G[i];
+  for (int k = 0; k < kMaxNb; ++k) e.H[k] = k < p.nb ? (float)c->H[k] : 0.f;
+  e.b_max = (float)p.b_max;
+  e.potential = p.potential;
+  e.uniform_w = (float)(1.0 / (double)p.P);
+  e.log_norm = (float)(0.5 * e.D * std::log(2.0 * M_PI * p.h * p.h));
+  c->nblk = (int)((p.P + kRedBlock - 1) / kRedBlock);
+}
+
+vds_status set_err(vds_ctx c, vds_status st, const std::string &m) {
+  if (c) c->err = m;
+  return st;
+}
+
+vds_status hip_check(vds_ctx c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return VDS_OK;
+  return set_err(c, VDS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+vds_status ready(vds_ctx c) {
+  if (c == nullptr) return VDS_ERR_ARG;
+  if (c->ws == nullptr) return set_err(c, VDS_ERR_STATE, "no workspace bound");
+  return VDS_OK;
+}
+
+hipEvent_t get_event(vds_ctx c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Times `fn` with an event pair on the context stream when timing is on.
+template <class F>
+void timed(vds_ctx c, int which, double work, F &&fn) {
+  if (!c->timing) {
+    fn();
+    return;
+  }
+  hipEvent_t a = get_event(c), b = get_event(c);
+  (void)hipEventRecord(a, c->stream);
+  fn();
+  (void)hipEventRecord(b, c->stream);
+  c->timers[which].pending.emplace_back(a, b);
+  c->timers[which].pending_work.push_back(work);
+}
+
+void drain_timers(vds_ctx c) {
+  for (auto &t : c->timers) {
+    for (size_t i = 0; i < t.pending.size(); ++i) {
+      float ms = 0.f;
+      (void)hipEventSynchronize(t.pending[i].second);
+      (void)hipEventElapsedTime(&ms, t.pending[i].first, t.pending[i].second);
+      t.ms += ms;
+      t.launches += 1;
+      t.work += t.pending_work[i];
+      c->event_pool.push_back(t.pending[i].first);
+      c->event_pool.push_back(t.pending[i].second);
+    }
+    t.pending.clear();
+    t.pending_work.clear();
+  }
+}
+
+int64_t ncol_chunks(const vds_ctx c) { return (c->prob.P + 15) / 16; }
+
+// One pair pass over all particle rows with the V operand `V`.
+void pair_pass(vds_ctx c, const float *V, const int *done) {
+  const int64_t nrb = c->ep.Ppad / 16;
+  const double pairs = (double)c->prob.P * (double)c->prob.P;
+  timed(c, VDS_TIMER_PAIR, pairs, [&] {
+    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->QB, nrb, c->KA, V, ncol_chunks(c), c->xc, true, c->part, c->ep.Ppad,
+                     done, c->stream);
+  });
+}
+
+// Prep + pass A + finalize A + pass B + combine(mode).
+void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, const float *qstar, float *out,
+              float *out2, const int *done) {
+  const EvalParams &e = c->ep;
+  launch_mean_partials(e, q, w, c->meanp, done, c->stream);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, done, c->stream);
+  pair_pass(c, c->VA, done);
+  launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
+  pair_pass(c, c->VB, done);
+  launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, qstar, out, out2, c->redp,
+                 c->ctrl, done, c->stream);
+  if (obs) launch_reduce_final(c->redp, c->nblk, 12, c->redout, done, c->stream);
+}
+
+vds_status fetch_obs(vds_ctx c, vds_diag *d) {
+  double r[16];
+  vds_status st = hip_check(c, hipMemcpyAsync(r, c->redout, sizeof(double) * 12, hipMemcpyDeviceToHost, c->stream),
+                            "copy observables");
+  if (st != VDS_OK) return st;
+  st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+  if (st != VDS_OK) return st;
+  d->F = r[RED_F];
+  d->dissipation = r[RED_DISS];
+  d->work = r[RED_WORK];
+  for (int i = 0; i < 9; ++i) d->tau[i] = r[RED_TAU + i];
+  d->energy_valid = 1;
+  return VDS_OK;
+}
+
+vds_status stress_into(vds_ctx c, const float *q, const float *w, double *tau) {
+  launch_stress(c->ep, q, w, c->redp, c->stream);
+  launch_reduce_final(c->redp, c->nblk, 9, c->redout, nullptr, c->stream);
+  double r[9];
+  vds_status st =
+      hip_check(c, hipMemcpyAsync(r, c->redout, sizeof(double) * 9, hipMemcpyDeviceToHost, c->stream), "copy stress");
+  if (st != VDS_OK) return st;
+  st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+  if (st != VDS_OK) return st;
+  std::memcpy(tau, r, sizeof(r));
+  return VDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vds_workspace_bytes(const vds_problem *prob) {
+  if (!problem_valid(prob, nullptr)) return 0;
+  return make_layout(*prob).total;
+}
+
+vds_status vds_create(const vds_problem *prob, const double *H_host, void *hip_stream, vds_ctx *out) {
+  std::string why;
+  if (out == nullptr) {
+    g_create_error = "out is NULL";
+    return VDS_ERR_ARG;
+  }
+  *out = nullptr;
+  if (!problem_valid(prob, &why)) {
+    g_create_error = why;
+    return VDS_ERR_ARG;
+  }
+  if (H_host == nullptr) {
+    g_create_error = "H is NULL";
+    return VDS_ERR_ARG;
+  }
+  for (int k = 0; k < prob->nb; ++k)
+    if (!(H_host[k] > 0.0) || !std::isfinite(H_host[k])) {
+      g_create_error = "spring constants H must be positive and finite";
+      return VDS_ERR_ARG;
+    }
+  vds_ctx c = new (std::nothrow) vds_ctx_s();
+  if (c == nullptr) {
+    g_create_error = "host allocation failed";
+    return VDS_ERR_NOMEM;
+  }
+  c->prob = *prob;
+  c->H.assign(H_host, H_host + prob->nb);
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->lay = make_layout(*prob);
+  fill_params(c);
+  *out = c;
+  return VDS_OK;
+}
+
+void vds_destroy(vds_ctx c) {
+  if (c == nullptr) return;
+  for (auto &t : c->timers)
+    for (auto &pr : t.pending) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char *vds_last_error(vds_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
+  if (c == nullptr) return VDS_ERR_ARG;
+  if (ws == nullptr) return set_err(c, VDS_ERR_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return set_err(c, VDS_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < c->lay.total) return set_err(c, VDS_ERR_NOMEM, "workspace smaller than vds_workspace_bytes()");
+  c->ws = static_cast<char *>(ws);
+  c->ws_bytes = bytes;
+  const Layout &L = c->lay;
+  c->QB = reinterpret_cast<float *>(c->ws + L.QB);
+  c->KA = reinterpret_cast<float *>(c->ws + L.KA);
+  c->VA = reinterpret_cast<float *>(c->ws + L.VA);
+  c->VB = reinterpret_cast<float *>(c->ws + L.VB);
+  c->part = reinterpret_cast<float *>(c->ws + L.part);
+  c->xc = reinterpret_cast<float *>(c->ws + L.xc);
+  c->t1 = reinterpret_cast<float *>(c->ws + L.t1);
+  c->S = reinterpret_cast<float *>(c->ws + L.S);
+  c->wv = reinterpret_cast<float *>(c->ws + L.wv);
+  c->meanp = reinterpret_cast<double *>(c->ws + L.meanp);
+  c->redp = reinterpret_cast<double *>(c->ws + L.redp);
+  c->redout = reinterpret_cast<double *>(c->ws + L.redout);
+  c->ctrl = reinterpret_cast<Ctrl *>(c->ws + L.ctrl);
+  c->qstar = reinterpret_cast<float *>(c->ws + L.qstar);
+  c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
+  c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);
+  return VDS_OK;
+}
+
+vds_status vds_set_tuning(vds_ctx c, const vds_tuning *t) {
+  if (c == nullptr || t == nullptr) return VDS_ERR_ARG;
+  if (!pair_shape_ok(*t, c->ep.D)) return set_err(c, VDS_ERR_ARG, "invalid tuning");
+  c->tune = *t;
+  return VDS_OK;
+}
+
+vds_status vds_get_tuning(vds_ctx c, vds_tuning *t) {
+  if (c == nullptr || t == nullptr) return VDS_ERR_ARG;
+  *t = c->tune;
+  return VDS_OK;
+}
+
+vds_status vds_pair_sums(vds_ctx c, const float *q, const float *w, float *S, float *t1, float *t2) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q || !S || !t1 || !t2) return set_err(c, VDS_ERR_ARG, "null array");
+  evaluate(c, q, w, MODE_TERMS, false, nullptr, t1, t2, nullptr);
+  return hip_check(c, hipMemcpyAsync(S, c->S, sizeof(float) * c->prob.P, hipMemcpyDeviceToDevice, c->stream),
+                   "copy S");
+}
+
+vds_status vds_velocity(vds_ctx c, const float *q, const float *w, float *v, vds_diag *d) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q || !v) return set_err(c, VDS_ERR_ARG, "null array");
+  evaluate(c, q, w, MODE_VELOCITY, d != nullptr, nullptr, v, nullptr, nullptr);
+  st = hip_check(c, hipGetLastError(), "launch");
+  if (st != VDS_OK || d == nullptr) return st;
+  std::memset(d, 0, sizeof(*d));
+  return fetch_obs(c, d);
+}
+
+vds_status vds_step(vds_ctx c, float *q, const float *w, int32_t nsteps, vds_diag *d) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q) return set_err(c, VDS_ERR_ARG, "null state");
+  if (nsteps < 0) return set_err(c, VDS_ERR_ARG, "nsteps < 0");
+  const vds_problem &p = c->prob;
+  const int64_t nq = (int64_t)p.P * c->ep.D;
+  int total_iters = 0, last_iters = 0;
+  float last_resid = 0.f;
+  for (int s = 0; s < nsteps; ++s) {
+    if (p.scheme == VDS_EXPLICIT) {
+      evaluate(c, q, w, MODE_EXPLICIT, false, nullptr, q, nullptr, nullptr);
+      continue;
+    }
+    launch_qstar(c->ep, q, c->qstar, c->stream);
+    launch_ctrl_reset(c->ctrl, c->stream);
+    const int *done = &c->ctrl->done;
+    int m = 0;
+    Ctrl h{};
+    bool converged = false;
+    while (m < p.picard_max) {
+      const int batch = std::min(p.picard_batch, p.picard_max - m);
+      for (int b = 0; b < batch; ++b, ++m) {
+        const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
+        float *xout = c->xb[m & 1];
+        evaluate(c, xin, w, MODE_PICARD, false, c->qstar, xout, nullptr, done);
+        launch_picard_check(c->ctrl, (float)p.picard_rtol, m, c->stream);
+      }
+      st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream), "copy ctrl");
+      if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+      if (st != VDS_OK) return st;
+      if (h.done) {
+        converged = true;
+        break;
+      }
+    }
+    const int final_iter = converged ? h.conv_iter : m - 1;
+    st = hip_check(c,
+                   hipMemcpyAsync(q, c->xb[final_iter & 1], sizeof(float) * nq, hipMemcpyDeviceToDevice, c->stream),
+                   "copy state");
+    if (st != VDS_OK) return st;
+    last_iters = final_iter + 1;
+    total_iters += last_iters;
+    last_resid = h.last_resid;
+    if (!converged) {
+      if (d) {
+        d->steps = s + 1;
+        d->iters = total_iters;
+        d->last_iters = last_iters;
+        d->resid = last_resid;
+      }
+      return set_err(c, VDS_ERR_NOT_CONVERGED, "fixed-point iteration reached picard_max");
+    }
+  }
+  st = hip_check(c, hipGetLastError(), "launch");
+  if (st != VDS_OK) return st;
+  if (d != nullptr) {
+    std::memset(d, 0, sizeof(*d));
+    d->steps = nsteps;
+    d->iters = total_iters;
+    d->last_iters = last_iters;
+    d->resid = last_resid;
+    return stress_into(c, q, w, d->tau);
+  }
+  return VDS_OK;
+}
+
+vds_status vds_stress(vds_ctx c, const float *q, const float *w, double *tau) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q || !tau) return set_err(c, VDS_ERR_ARG, "null array");
+  return stress_into(c, q, w, tau);
+}
+
+vds_status vds_energy(vds_ctx c, const float *q, const float *w, double *F, double *diss, double *work) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q) return set_err(c, VDS_ERR_ARG, "null state");
+  evaluate(c, q, w, MODE_OBS_ONLY, true, nullptr, nullptr, nullptr, nullptr);
+  vds_diag d{};
+  st = fetch_obs(c, &d);
+  if (st != VDS_OK) return st;
+  if (F) *F = d.F;
+  if (diss) *diss = d.dissipation;
+  if (work) *work = d.work;
+  return VDS_OK;
+}
+
+vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float *y, int64_t ny, float *f) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q || !y || !f || ny < 0) return set_err(c, VDS_ERR_ARG, "bad arguments");
+  if (ny == 0) return VDS_OK;
+  const EvalParams &e = c->ep;
+  launch_mean_partials(e, q, w, c->meanp, nullptr, c->stream);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, nullptr, c->stream);
+  const float norm = (float)std::pow(2.0 * M_PI * c->prob.h * c->prob.h, -0.5 * e.D);
+  // foreign rows go through the Q-operand buffer in blocks of Ppad rows
+  for (int64_t r0 = 0; r0 < ny; r0 += e.Ppad) {
+    const int64_t nr = std::min<int64_t>(e.Ppad, ny - r0);
+    launch_density_rows(e, y + r0 * e.D, nr, c->meanp, c->nblk, c->QB, c->stream);
+    const int64_t nrb = round_up(nr, kRowAlign) / 16;
+    timed(c, VDS_TIMER_PAIR, (double)nr * (double)c->prob.P, [&] {
+      launch_pair_pass(c->tune, e.KK, e.D, c->QB, nrb, c->KA, c->VA, ncol_chunks(c), c->xc, false, c->part, e.Ppad,
+                       nullptr, c->stream);
+    });
+    launch_density_out(e, c->part, c->tune.col_splits, nr, norm, f + r0, c->stream);
+  }
+  return hip_check(c, hipGetLastError(), "launch");
+}
+
+vds_status vds_timing_enable(vds_ctx c, int32_t enable) {
+  if (c == nullptr) return VDS_ERR_ARG;
+  drain_timers(c);
+  for (auto &t : c->timers) {
+    t.ms = 0.0;
+    t.launches = 0;
+    t.work = 0.0;
+  }
+  c->timing = enable != 0;
+  return VDS_OK;
+}
+
+vds_status vds_timing_read(vds_ctx c, int32_t which, double *ms, int64_t *launches, double *work) {
+  if (c == nullptr || which < 0 || which >= VDS_TIMER_COUNT) return VDS_ERR_ARG;
+  drain_timers(c);
+  if (ms) *ms = c->timers[which].ms;
+  if (launches) *launches = c->timers[which].launches;
+  if (work) *work = c->timers[which].work;
+  return VDS_OK;
+}
+
+vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!q) return set_err(c, VDS_ERR_ARG, "null state");
+  const EvalParams &e = c->ep;
+  launch_mean_partials(e, q, w, c->meanp, nullptr, c->stream);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, nullptr, c->stream);
+  hipEvent_t a = get_event(c), b = get_event(c);
+  vds_tuning best = c->tune;
+  float best_ms = 1e30f;
+  const int splits_list[] = {1, 2, 4, 8, 16, 32};
+  const int rb_list[] = {1, 2, 4};
+  std::vector<vds_tuning> cands;
+  for (int rb : rb_list)
+    for (int sp : splits_list) cands.push_back(vds_tuning{VDS_PAIR_MFMA, rb, sp, 0});
+  for (int sp : splits_list) cands.push_back(vds_tuning{VDS_PAIR_VALU, 1, sp, 0});
+  const bool was_timing = c->timing;
+  c->timing = false;
+  for (const vds_tuning &t : cands) {
+    if (!pair_shape_ok(t, e.D)) continue;
+    c->tune = t;
+    pair_pass(c, c->VA, nullptr);  // warm-up
+    (void)hipEventRecord(a, c->stream);
+    const int reps = 3;
+    for (int r = 0; r < reps; ++r) pair_pass(c, c->VA, nullptr);
+    (void)hipEventRecord(b, c->stream);
+    st = hip_check(c, hipEventSynchronize(b), "autotune");
+    if (st != VDS_OK) break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  c->timing = was_timing;
+  c->event_pool.push_back(a);
+  c->event_pool.push_back(b);
+  c->tune = best;
+  return st;
+}
+
+}  // extern "C"

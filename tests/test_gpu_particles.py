@@ -1,0 +1,286 @@
+"""GPU parity of the particle scheme (kernel sums, velocity, steps, observables)
+against the FP64 oracle, through the C ABI.  Needs an MI355X and libvds.so.
+
+Tolerances (float32 GPU vs float64 oracle on the same float32 inputs):
+  kernel sums S: max relative 1e-5
+  Brownian b = term1 + term2 and velocity v: ||gpu - oracle||_2 / ||oracle||_2 <= 1e-5
+    (for v the denominator is max(||v||, ||(1/zeta)(A (x) I) grad Psi||), since
+    the total velocity can nearly vanish at steady state)
+  stress: relative Frobenius 1e-4; energy terms: 1e-5 of their magnitude
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import vds as ovds
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2603_12550_amd as pkg
+    return pkg
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(wl.to_f32(a)).cuda()
+
+
+def _ctx(pkg, nb, P, h, **kw):
+    return pkg.Context(nb, P, h, poison=True, **kw)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+TUNINGS = [(0, 1, 1), (0, 2, 8), (0, 4, 3), (1, 1, 1), (1, 1, 5)]
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 17, 63, 64, 300])
+@pytest.mark.parametrize("nb", [1, 3, 5])
+def test_pair_sums_brute_force_small(lib, P, nb):
+    q64 = wl.gaussian_bonds(100 + P, nb, P, 0.5)
+    q = wl.f32_as_f64(wl.to_f32(q64))
+    w64 = wl.random_weights(7 + P, P)
+    w = wl.f32_as_f64(wl.to_f32(w64))
+    h = 0.45
+    x = ovds.particle_major(q)
+    S_o, t1_o, t2_o = ovds.brownian_terms(x, w, h)
+    b_o = ovds.bond_major(t1_o + t2_o, nb)
+    ctx = _ctx(lib, nb, P, h, scheme="explicit")
+    for impl, rb, sp in TUNINGS:
+        _say(f"pair sums P={P} nb={nb} impl={impl} rb={rb} splits={sp}")
+        ctx.set_tuning(impl, rb, sp)
+        S, t1, t2 = ctx.pair_sums(_dev(q), _dev(w))
+        S, t1, t2 = S.cpu().numpy(), t1.cpu().numpy(), t2.cpu().numpy()
+        assert np.max(np.abs(S - S_o) / S_o) < 1e-5
+        b = t1.astype(np.float64) + t2
+        scale = max(np.linalg.norm(b_o), 1e-3 * math.sqrt(b_o.size) / h ** 2)
+        assert np.linalg.norm(b - b_o) / scale < 1e-5, (impl, rb, sp)
+        assert np.linalg.norm(t1 - ovds.bond_major(t1_o, nb)) / scale < 1e-5
+
+
+def test_uniform_weights_null_pointer_matches_explicit_uniform(lib):
+    P, nb, h = 500, 3, 0.4
+    q = wl.to_f32(wl.gaussian_bonds(5, nb, P, 1 / 3))
+    ctx = _ctx(lib, nb, P, h)
+    S1, a1, b1 = ctx.pair_sums(_dev(q))
+    S2, a2, b2 = ctx.pair_sums(_dev(q), _dev(np.full(P, 1.0 / P)))
+    assert np.allclose(S1.cpu().numpy(), S2.cpu().numpy(), rtol=1e-6)
+    assert np.allclose((a1 + b1).cpu().numpy(), (a2 + b2).cpu().numpy(), rtol=1e-5, atol=1e-5)
+
+
+def _velocity_check(lib, cfg, rows=None, tuning=None, threads=8):
+    P, nb = cfg["P"], cfg["nb"]
+    q32 = wl.to_f32(cfg["q0"])
+    q = wl.f32_as_f64(q32)
+    prob = ovds.problem_from(cfg)
+    w = ovds.uniform_weights(P)
+    ctx = _ctx(lib, nb, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], potential=cfg["potential"],
+               b_max=cfg["b_max"])
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    v, diag = ctx.velocity(_dev(q32), diag=True)
+    v = v.cpu().numpy().astype(np.float64)
+    x = ovds.particle_major(q)
+    if rows is None:
+        v_o = ovds.velocity(q, w, prob, threads=threads)
+        vg, spring = v, ovds.rouse_apply(ovds.rouse_matrix(nb), ovds.grad_potential(q, prob)) / prob.zeta
+    else:
+        S_all = ovds.density_sums(x, w, prob.h, threads=threads)
+        _, t1, t2 = ovds.brownian_terms(x, w, prob.h, rows=rows, S_all=S_all, threads=threads)
+        qs = q[:, rows, :]
+        g = prob.kT * ovds.bond_major(t1 + t2, nb) + ovds.grad_potential(qs, prob)
+        A = ovds.rouse_matrix(nb)
+        v_o = ovds.flow_term(qs, prob) - ovds.rouse_apply(A, g) / prob.zeta
+        vg = v[:, rows, :]
+        spring = ovds.rouse_apply(A, ovds.grad_potential(qs, prob)) / prob.zeta
+    denom = max(np.linalg.norm(v_o), np.linalg.norm(spring))
+    err = np.linalg.norm(vg - v_o) / denom
+    tau_o = ovds.stress(q, w, prob)
+    assert np.linalg.norm(diag["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
+    return err, diag, ctx
+
+
+def test_velocity_dumbbell_full_size(lib):
+    cfg = wl.dumbbell_shear()  # P = 2000, D = 3, h = 0.3
+    _say("velocity dumbbell P=2000")
+    err, diag, _ = _velocity_check(lib, cfg)
+    assert err < 1e-5, err
+
+
+def test_velocity_chain4_full_size_sampled_rows(lib):
+    cfg = wl.chain4_shear()  # P = 20000, D = 9, h = 0.4
+    rows = np.random.default_rng(0).choice(cfg["P"], 256, replace=False)
+    rows = np.concatenate([rows, [0, cfg["P"] - 1]])
+    _say("velocity chain4 P=20000 sampled rows")
+    err, _, _ = _velocity_check(lib, cfg, rows=rows)
+    assert err < 1e-5, err
+
+
+def test_velocity_fene_chain6_sampled_rows(lib):
+    cfg = wl.fene_chain6(P=6000)
+    rows = np.random.default_rng(1).choice(cfg["P"], 200, replace=False)
+    _say("velocity FENE chain6 P=6000")
+    err, _, _ = _velocity_check(lib, cfg, rows=rows)
+    assert err < 1e-5, err
+
+
+def test_velocity_all_tunings_agree(lib):
+    cfg = wl.chain4_shear(P=3000, seed=9)
+    for t in TUNINGS:
+        _say(f"velocity chain4 P=3000 tuning {t}")
+        err, _, _ = _velocity_check(lib, cfg, tuning=t)
+        assert err < 1e-5, (t, err)
+
+
+def test_energy_dissipation_work_match_oracle(lib):
+    cfg = wl.chain4_shear(P=1500, seed=3)
+    q32 = wl.to_f32(cfg["q0"])
+    q = wl.f32_as_f64(q32)
+    prob = ovds.problem_from(cfg)
+    w = ovds.uniform_weights(cfg["P"])
+    ctx = _ctx(lib, 3, cfg["P"], cfg["h"], H=cfg["H"], G=cfg["G"])
+    F, Dg, W = ctx.energy(_dev(q32))
+    F_o = ovds.free_energy(q, w, prob)
+    D_o, W_o = ovds.dissipation_and_work(q, w, prob)
+    # F sums terms of magnitude |kT log f| + Psi; compare on that scale
+    Sx = ovds.density_sums(ovds.particle_major(q), w, prob.h)
+    mag = (w * (np.abs(np.log(Sx)) + ovds.potential(q, prob))).sum()
+    assert abs(F - F_o) / mag < 1e-5
+    assert abs(Dg - D_o) / D_o < 1e-5
+    assert abs(W - W_o) / (abs(W_o) + 1e-3 * D_o) < 1e-4
+
+
+def test_implicit_steps_match_oracle_trajectory(lib):
+    cfg = wl.chain4_shear(P=3000, seed=12)
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    qo = wl.f32_as_f64(q32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    for s in range(5):
+        _say(f"implicit step {s} chain4 P=3000")
+        d = ctx.step(qg)
+        qo, m = ovds.step_implicit(qo, w, prob, threads=8)
+        assert 1 <= d["last_iters"] <= 10
+        assert _rel(qg.cpu().numpy(), qo) < 1e-5
+        tau_o = ovds.stress(qo, w, prob)
+        assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
+
+
+def test_implicit_dumbbell_trajectory_and_stress(lib):
+    cfg = wl.dumbbell_shear()
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    qo = wl.f32_as_f64(q32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 1, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    for s in range(6):
+        _say(f"implicit step {s} dumbbell P=2000")
+        d = ctx.step(qg)
+        qo, _ = ovds.step_implicit(qo, w, prob, threads=8)
+        assert _rel(qg.cpu().numpy(), qo) < 1e-5
+        tau_o = ovds.stress(qo, w, prob)
+        assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
+
+
+def test_explicit_steps_match_oracle_fene(lib):
+    cfg = wl.fene_chain6(P=700)
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    qo = wl.f32_as_f64(q32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 5, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme="explicit", potential="fene",
+               b_max=cfg["b_max"])
+    ctx.step(qg, nsteps=4)
+    for _ in range(4):
+        qo = ovds.step_explicit(qo, w, prob)
+    assert _rel(qg.cpu().numpy(), qo) < 1e-5
+
+
+def test_implicit_step_full_size_solves_the_implicit_equation(lib):
+    # chain4 at P = 20000: one implicit step on the GPU; on sampled rows the
+    # oracle checks (q+ - q*)/dt = u(q+) with q* = q + dt G q (Appendix A)
+    cfg = wl.chain4_shear()
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    q0 = wl.f32_as_f64(q32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    _say("implicit step chain4 P=20000")
+    d = ctx.step(qg)
+    assert 2 <= d["last_iters"] <= 8
+    qp = qg.cpu().numpy().astype(np.float64)
+    rows = np.random.default_rng(2).choice(P, 256, replace=False)
+    x = ovds.particle_major(qp)
+    S_all = ovds.density_sums(x, w, prob.h, threads=8)
+    _, t1, t2 = ovds.brownian_terms(x, w, prob.h, rows=rows, S_all=S_all, threads=8)
+    g = prob.kT * ovds.bond_major(t1 + t2, 3) + ovds.grad_potential(qp[:, rows], prob)
+    u = -ovds.rouse_apply(ovds.rouse_matrix(3), g) / prob.zeta
+    qstar = q0[:, rows] + prob.dt * ovds.flow_term(q0[:, rows], prob)
+    r = qp[:, rows] - qstar - prob.dt * u
+    assert np.linalg.norm(r) / np.linalg.norm(prob.dt * u) < 1e-3
+    tau_o = ovds.stress(qp, w, prob)
+    assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
+
+
+def test_density_at_grid_points(lib):
+    # Appendix A density on the {-2, 0, 2}^D grid (D = 6 here: 729 points)
+    nb, P, h = 2, 900, 0.5
+    q32 = wl.to_f32(wl.gaussian_bonds(17, nb, P, 1.0))
+    q = wl.f32_as_f64(q32)
+    grid = np.array(np.meshgrid(*[[-2.0, 0.0, 2.0]] * (3 * nb), indexing="ij")).reshape(3 * nb, -1).T
+    f_o = ovds.density_at(grid, q, ovds.uniform_weights(P), h)
+    ctx = _ctx(lib, nb, P, h)
+    f = ctx.density_at(_dev(q32), _dev(grid)).cpu().numpy()
+    assert np.linalg.norm(f - f_o) / np.linalg.norm(f_o) < 1e-5
+
+
+def test_runs_are_bitwise_deterministic(lib):
+    cfg = wl.chain4_shear(P=4000, seed=4)
+    q32 = wl.to_f32(cfg["q0"])
+    ctx = _ctx(lib, 3, cfg["P"], cfg["h"], H=cfg["H"], G=cfg["G"])
+    a = ctx.velocity(_dev(q32)).cpu().numpy()
+    b = ctx.velocity(_dev(q32)).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_autotune_picks_a_valid_shape(lib):
+    cfg = wl.chain4_shear(P=5000, seed=6)
+    q32 = wl.to_f32(cfg["q0"])
+    ctx = _ctx(lib, 3, cfg["P"], cfg["h"], H=cfg["H"], G=cfg["G"])
+    t = ctx.autotune(_dev(q32))
+    assert t["impl"] in (0, 1) and 1 <= t["col_splits"] <= 32
+    err, _, _ = _velocity_check(lib, cfg, tuning=(t["impl"], t["rows_per_wave"], t["col_splits"]))
+    assert err < 1e-5
+
+
+def test_not_converged_status(lib):
+    # a cap of one iteration cannot meet the tolerance
+    cfg = wl.chain4_shear(P=600, seed=8)
+    ctx = _ctx(lib, 3, cfg["P"], cfg["h"], G=cfg["G"], scheme="implicit", picard_max=1, picard_rtol=1e-9)
+    with pytest.raises(lib.VDSError) as ei:
+        ctx.step(_dev(cfg["q0"]))
+    assert ei.value.status == lib._vds.VDS_ERR_NOT_CONVERGED
