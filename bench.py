@@ -32,27 +32,58 @@ PEAK_HBM_GBS = 8000.0
 
 
 def flops_per_pair(D: int) -> int:
-    # dot product 2D, norm combine + clamp + scale 4, accumulate S 1, accumulate sum e x_J 2D - 1
+    """Algorithmic FLOP of one pair-evaluation: 2D for the distance dot product,
+    2 to combine the norms and scale, 2(D + 1) to accumulate e w and e w x_J
+    (plus one exp, not counted)."""
     return 4 * D + 4
 
 
-def cpu_baseline(cfg, sample_rows: int, threads: int):
+def cpu_baseline(cfg, threads: int):
+    """One implicit step of the FP64 oracle on the same state (all rows), timed."""
     from oracle import vds as ovds
     import workloads as wl
     q = wl.f32_as_f64(wl.to_f32(cfg["q0"]))
-    x = ovds.particle_major(q)
     P = cfg["P"]
     w = ovds.uniform_weights(P)
-    rows = np.arange(sample_rows)
-    S_rows = ovds.density_sums(x, w, cfg["h"], rows=rows, threads=threads)   # warm the pool / caches
-    S_all = np.concatenate([S_rows, np.ones(P - sample_rows)])                # pass B weights (values irrelevant to timing)
+    prob = ovds.problem_from(cfg)
     t0 = time.perf_counter()
-    ovds.brownian_terms(x, w, cfg["h"], rows=rows, S_all=S_all, threads=threads)
+    _, iters = ovds.step_implicit(q, w, prob, threads=threads)
     dt = time.perf_counter() - t0
-    pairs = 2.0 * sample_rows * P
+    pairs = 2.0 * P * P * iters
     return dict(value=pairs / dt, unit="pair-evals/s", cores=threads, kind="oracle",
-                sample=f"both kernel passes (term1 and term2) for {sample_rows} of {P} rows of the "
-                       f"P={P}, D=9 chain state, FP64 NumPy with {threads} threads: {pairs:.3g} pair-evals in {dt:.1f} s")
+                sample=f"one implicit step (fixed-point tolerance 1e-13, {iters} iterations, both kernel "
+                       f"passes per iteration over all rows) of the P={P}, D=9 chain workload, FP64 NumPy "
+                       f"row blocks on {threads} threads: {pairs:.3g} pair-evals in {dt:.1f} s")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2603_12550_amd", "csrc", "pair_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, tuning: dict, P: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
+    if it was taken on the current kernel source and the same launch shape."""
+    path = os.path.join(ROOT, "profiles", "pair_pass_chain4_P20000_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("pair_kernels_sha256_16") != kernel_source_hash() or rec.get("kernel") != kernel \
+            or rec.get("tuning") != tuning or rec.get("P") != P:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(nbytes: int = 1 << 29, reps: int = 5):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def main():
@@ -62,8 +93,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--P", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-rows", type=int, default=6000)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", type=str, default="", help="impl,rows_per_wave,col_splits (skips the autotuner)")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy of known size")
+    ap.add_argument("--sweep", action="store_true", help="only time every pair-kernel tuning and print a table")
     ap.add_argument("--t-end", action="store_true", help="also time the full 500-step run to t_end")
     args = ap.parse_args()
 
@@ -72,6 +104,10 @@ def main():
               "(the particle rows would shard by block with an all-gather of S between passes).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     import paper_2603_12550_amd as pkg
@@ -84,23 +120,42 @@ def main():
     ctx = pkg.Context(3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit",
                       picard_rtol=1e-6, picard_max=50, picard_batch=3)
     q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
-    if not args.no_autotune:
+    if args.sweep:
+        for impl, rbs in ((0, (1, 2, 4)), (1, (1,))):
+            for rb in rbs:
+                for sp in (1, 2, 4, 8, 16, 32):
+                    ctx.set_tuning(impl, rb, sp)
+                    q = q0.clone()
+                    ctx.step(q, nsteps=2)
+                    ctx.timing_enable(True)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    d = ctx.step(q, nsteps=5)
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - t0
+                    tim = ctx.timing_read(_vds.VDS_TIMER_PAIR)
+                    ctx.timing_enable(False)
+                    print(json.dumps({"impl": impl, "rows_per_wave": rb, "col_splits": sp,
+                                      "pair_avg_ms": tim["ms"] / max(1, tim["launches"]),
+                                      "step_ms": el * 1e3 / 5, "iters": d["iters"]}), flush=True)
+        return
+    if args.tuning:
+        ctx.set_tuning(*[int(v) for v in args.tuning.split(",")])
+    else:
         ctx.autotune(q0)
     tune = ctx.get_tuning()
     q = q0.clone()
 
-    for _ in range(args.warmup):
-        ctx.step(q)
+    if args.warmup:
+        ctx.step(q, nsteps=args.warmup)
     torch.cuda.synchronize()
 
     ctx.timing_enable(True)
-    iters = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        d = ctx.step(q)
-        iters += d["last_iters"]
+    d = ctx.step(q, nsteps=args.steps)
     torch.cuda.synchronize()
+    iters = d["iters"]
     elapsed = time.perf_counter() - t0
     tim = ctx.timing_read(_vds.VDS_TIMER_PAIR)
     ctx.timing_enable(False)
@@ -128,8 +183,10 @@ def main():
                                f"implicit Euler dt=1e-3, fixed-point rtol 1e-6",
                    "P": P, "D": D, "pair_tuning": tune,
                    "fixed_point_iterations": iters},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+        "roofline": {"bound": "mfma" if tune["impl"] == 0 else "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic("k_pair_mfma" if tune["impl"] == 0 else "k_pair_valu", tune, P),
                      "kernel": "k_pair_mfma" if tune["impl"] == 0 else "k_pair_valu",
                      "avg_launch_ms": avg_ms, "launches": tim["launches"],
                      "flop_per_launch": flop_launch, "flop_per_pair": flops_per_pair(D)},
@@ -146,7 +203,7 @@ def main():
 
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_rows, threads)
+        out["cpu_baseline"] = cpu_baseline(cfg, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -74,6 +74,20 @@ _sigs = {
     "vds_timing_enable": ([_P, C.c_int32], C.c_int),
     "vds_timing_read": ([_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
 }
+_sigs.update({
+    "vds_pod_workspace_bytes": ([C.c_int64, C.c_int32, C.c_int32], C.c_size_t),
+    "vds_pod_gram": ([_P, _P, C.c_int64, C.c_int32, _P, _P, C.c_size_t], C.c_int),
+    "vds_pod_basis": ([_P, _P, C.c_int64, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double), _P, C.c_size_t], C.c_int),
+    "vds_pod_map_workspace_bytes": ([C.POINTER(vds_problem), C.c_int32], C.c_size_t),
+    "vds_pod_project": ([_P, _P, C.c_int32, _P, _P, _P, C.c_size_t], C.c_int),
+    "vds_pod_reconstruct": ([_P, _P, C.c_int32, _P, _P, _P, C.c_size_t], C.c_int),
+    "vds_rom_workspace_bytes": ([C.POINTER(vds_problem), C.c_int32], C.c_size_t),
+    "vds_rom_create": ([_P, _P, C.c_int32, _P, C.c_size_t, C.POINTER(_P)], C.c_int),
+    "vds_rom_destroy": ([_P], None),
+    "vds_rom_operators": ([_P, _P, _P, _P, _P], C.c_int),
+    "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "vds_rom_stress": ([_P, _P, C.POINTER(C.c_double)], C.c_int),
+})
 for _name, (_args, _ret) in _sigs.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -198,11 +212,88 @@ class Context:
         _check(_lib.vds_energy(self.ctx, _ptr(q), _ptr(w), C.byref(F), C.byref(Dd), C.byref(W)), self.ctx)
         return F.value, Dd.value, W.value
 
+    # -- POD (Sections 1.3, 2.3, 3.1) --
+    def _pod_ws(self, m, ncols, R):
+        n = _lib.vds_pod_workspace_bytes(int(m), int(ncols), int(R))
+        if n == 0:
+            raise VDSError(VDS_ERR_ARG, "invalid POD sizes")
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def pod_gram(self, X):
+        """X: tensor (ncols, m) holding the column-major m x ncols snapshot matrix."""
+        ncols, m = X.shape
+        G = torch.empty((ncols, ncols), dtype=torch.float32, device=self.device)
+        ws = self._pod_ws(m, ncols, 1)
+        _check(_lib.vds_pod_gram(self.ctx, _ptr(X), m, ncols, _ptr(G), _ptr(ws), ws.numel()), self.ctx)
+        return G
+
+    def pod_basis(self, X, R):
+        """Returns U as a tensor (R, m) (column-major m x R) and all eigenvalues, descending."""
+        ncols, m = X.shape
+        U = torch.empty((R, m), dtype=torch.float32, device=self.device)
+        eig = (C.c_double * ncols)()
+        ws = self._pod_ws(m, ncols, R)
+        _check(_lib.vds_pod_basis(self.ctx, _ptr(X), m, ncols, int(R), _ptr(U), eig, _ptr(ws), ws.numel()), self.ctx)
+        return U, np.array(eig[:])
+
+    def _map_ws(self, R):
+        n = _lib.vds_pod_map_workspace_bytes(C.byref(self.prob), int(R))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def pod_project(self, U, q):
+        R = U.shape[0]
+        p = torch.empty((self.nb, R), dtype=torch.float32, device=self.device)
+        ws = self._map_ws(R)
+        _check(_lib.vds_pod_project(self.ctx, _ptr(U), R, _ptr(q), _ptr(p), _ptr(ws), ws.numel()), self.ctx)
+        return p
+
+    def pod_reconstruct(self, U, p):
+        R = U.shape[0]
+        q = self._state()
+        ws = self._map_ws(R)
+        _check(_lib.vds_pod_reconstruct(self.ctx, _ptr(U), R, _ptr(p), _ptr(q), _ptr(ws), ws.numel()), self.ctx)
+        return q
+
     def density_at(self, q, y, w=None):
         y = y.contiguous()
         f = torch.empty(y.shape[0], dtype=torch.float32, device=self.device)
         _check(_lib.vds_density_at(self.ctx, _ptr(q), _ptr(w), _ptr(y), int(y.shape[0]), _ptr(f)), self.ctx)
         return f
+
+
+class Rom:
+    """Galerkin reduced model (Section 2.4) of basis U (tensor (R, 3P)) on a Context."""
+
+    def __init__(self, ctx: Context, U):
+        self.ctx, self.U, self.R = ctx, U, int(U.shape[0])
+        n = _lib.vds_rom_workspace_bytes(C.byref(ctx.prob), self.R)
+        if n == 0:
+            raise VDSError(VDS_ERR_ARG, "invalid reduced-model sizes")
+        self.ws = torch.empty(n, dtype=torch.uint8, device=ctx.device)
+        h = C.c_void_p()
+        _check(_lib.vds_rom_create(ctx.ctx, _ptr(U), self.R, _ptr(self.ws), n, C.byref(h)), ctx.ctx)
+        self.rom = h
+
+    def __del__(self):
+        if getattr(self, "rom", None):
+            _lib.vds_rom_destroy(self.rom)
+            self.rom = None
+
+    def operators(self, p):
+        R = self.R
+        XH, XB1, XB2 = (torch.empty((R, R), dtype=torch.float32, device=self.ctx.device) for _ in range(3))
+        _check(_lib.vds_rom_operators(self.rom, _ptr(p), _ptr(XH), _ptr(XB1), _ptr(XB2)), self.ctx.ctx)
+        return XH, XB1, XB2
+
+    def run(self, p, nsteps, freeze_every):
+        tau = (C.c_double * 9)()
+        _check(_lib.vds_rom_run(self.rom, _ptr(p), int(nsteps), int(freeze_every), tau), self.ctx.ctx)
+        return np.array(tau[:]).reshape(3, 3)
+
+    def stress(self, p):
+        tau = (C.c_double * 9)()
+        _check(_lib.vds_rom_stress(self.rom, _ptr(p), tau), self.ctx.ctx)
+        return np.array(tau[:]).reshape(3, 3)
 
 
 # C names, re-exported for callers who drive the ABI directly

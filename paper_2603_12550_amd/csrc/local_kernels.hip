@@ -68,6 +68,21 @@ __device__ void load_mean(const EvalParams &p, const double *meanp, int nmeanp, 
   __syncthreads();
 }
 
+// The per-particle kernels below use 16 lanes per particle: lane n owns
+// component n of the configuration vector (n < D <= 15), so loads and stores
+// of a wave cover four particles' contiguous records and P/16 blocks fill the
+// chip.  Cross-component terms (norms, the 3x3 flow, bond neighbours) are
+// 16-wide shuffles.
+__device__ inline int64_t group_particle() { return ((int64_t)blockIdx.x * kRedBlock + threadIdx.x) >> 4; }
+__device__ inline int group_lane() { return threadIdx.x & 15; }
+__device__ inline float gshfl(float v, int n) { return __shfl(v, n, 16); }
+__device__ inline double gshfl(double v, int n) { return __shfl(v, n, 16); }
+__device__ inline float gsum(float v) {
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+  return v;
+}
+
 // Centre, pack Q/K operands and the pass-A V operand (weights w).
 __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *__restrict__ q,
                                                     const float *__restrict__ w, const double *__restrict__ meanp,
@@ -77,91 +92,74 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
   __shared__ float mean_sh[kMaxD];
   if (done != nullptr && *done) return;
   load_mean(p, meanp, nmeanp, mean_sh);
-  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  const int64_t I = group_particle();
+  const int n = group_lane();
   if (I >= p.Ppad) return;
   const bool real = I < p.P;
-  float x[kMaxD];
-  float nrm = 0.f;
-#pragma unroll
-  for (int a = 0; a < kMaxD; ++a) {
-    const int k = a / 3, al = a % 3;
-    x[a] = (real && a < p.D) ? q[((int64_t)k * p.P + I) * 3 + al] - mean_sh[a] : 0.f;
-    nrm = fmaf(x[a], x[a], nrm);
-  }
+  const float x = (real && n < p.D) ? q[((int64_t)(n / 3) * p.P + I) * 3 + (n % 3)] - mean_sh[n] : 0.f;
+  const float nrm = gsum(x * x);
   const float wi = real ? load_weight(w, I, p.uniform_w) : 0.f;
-  wv[I] = wi;
-  for (int a = 0; a < p.D; ++a) xc[I * p.D + a] = x[a];
-  const int alen = 4 * p.KK;
-  for (int k = 0; k < alen; ++k) {
-    float qa, ka;
-    if (!real) {
-      qa = 0.f;
-      ka = 0.f;
-    } else if (k < p.D) {
-      qa = x[k];
-      ka = 2.f * p.kappa * x[k];
-    } else if (k == p.D) {
-      qa = -p.kappa * nrm;
-      ka = 1.f;
-    } else if (k == p.D + 1) {
-      qa = 1.f;
-      ka = -p.kappa * nrm;
-    } else {
-      qa = 0.f;
-      ka = 0.f;
+  if (n == 0) wv[I] = wi;
+  if (n < p.D) xc[I * p.D + n] = x;
+  for (int k = n; k < 4 * p.KK; k += 16) {
+    float qa = 0.f, ka = 0.f;
+    if (real) {
+      if (k < p.D) {
+        qa = x;
+        ka = 2.f * p.kappa * x;
+      } else if (k == p.D) {
+        qa = -p.kappa * nrm;
+        ka = 1.f;
+      } else if (k == p.D + 1) {
+        qa = 1.f;
+        ka = -p.kappa * nrm;
+      }
     }
     QB[qk_index(I, k, p.KK)] = qa;
     KA[qk_index(I, k, p.KK)] = ka;
   }
-  for (int n = 0; n < 16; ++n) {
-    float v = 0.f;
-    if (n < p.D) v = wi * x[n];
-    else if (n == p.D) v = wi;
-    VA[v_index(I, n)] = v;
-  }
+  float v = 0.f;
+  if (n < p.D) v = wi * x;
+  else if (n == p.D) v = wi;
+  VA[v_index(I, n)] = v;
 }
 
-// Sum of the split partials of row I in FP64: o[n] for n <= D.
-__device__ inline void sum_splits(const EvalParams &p, const float *__restrict__ partial, int splits, int64_t I,
-                                  double (&o)[kMaxD + 1]) {
-#pragma unroll
-  for (int n = 0; n <= kMaxD; ++n) o[n] = 0.0;
-  for (int s = 0; s < splits; ++s) {
-    const float *src = partial + ((int64_t)s * p.Ppad + I) * 16;
-#pragma unroll
-    for (int n = 0; n <= kMaxD; ++n)
-      if (n <= p.D) o[n] += (double)src[n];
-  }
+// Component n of row I summed over the column splits, in FP64.
+__device__ inline double sum_splits(const EvalParams &p, const float *__restrict__ partial, int splits, int64_t I,
+                                    int n) {
+  double o = 0.0;
+  for (int s = 0; s < splits; ++s) o += (double)partial[((int64_t)s * p.Ppad + I) * 16 + n];
+  return o;
 }
 
-// Pass-A finalisation: S_I = sum_J w_J e_IJ, term1_I = -(1/h^2) sum_J w_J e_IJ (x_I - x_J) / S_I,
-// and the pass-B operand with weights w_J / S_J.
+// Pass-A finalisation: S_I = w_I + sum_{J != I} w_J e_IJ,
+// term1_I = -(1/h^2) sum_J w_J e_IJ (x_I - x_J) / S_I, and the pass-B operand
+// with weights w_J / S_J.
 __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, int splits,
                                                           const float *__restrict__ xc, const float *__restrict__ wv,
                                                           float *__restrict__ S, float *__restrict__ t1,
                                                           float *__restrict__ VB, const int *__restrict__ done) {
   if (done != nullptr && *done) return;
-  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  const int64_t I = group_particle();
+  const int n = group_lane();
   if (I >= p.Ppad) return;
   if (I >= p.P) {  // padding columns carry zero weight in pass B too
-    for (int n = 0; n < 16; ++n) VB[v_index(I, n)] = 0.f;
+    VB[v_index(I, n)] = 0.f;
     return;
   }
-  double o[kMaxD + 1];
-  sum_splits(p, partial, splits, I, o);
-  const double Si = o[p.D] + (double)wv[I];  // the pass left out the self term w_I e_II = w_I
-  S[I] = (float)Si;
-  const float wb = (float)((double)wv[I] / Si);
-  for (int a = 0; a < p.D; ++a) {
-    t1[I * p.D + a] = (float)(-(double)p.inv_h2 * o[a] / Si);
-    VB[v_index(I, a)] = wb * xc[I * p.D + a];
+  const double o = n <= p.D ? sum_splits(p, partial, splits, I, n) : 0.0;
+  const double wI = (double)wv[I];
+  const double Si = gshfl(o, p.D) + wI;  // the pass left out the self term w_I e_II = w_I
+  const float wb = (float)(wI / Si);
+  float v = 0.f;
+  if (n < p.D) {
+    t1[I * p.D + n] = (float)(-(double)p.inv_h2 * o / Si);
+    v = wb * xc[I * p.D + n];
+  } else if (n == p.D) {
+    S[I] = (float)Si;
+    v = wb;
   }
-  VB[v_index(I, p.D)] = wb;
-  for (int n = p.D + 1; n < 16; ++n) VB[v_index(I, n)] = 0.f;
-}
-
-__device__ inline void atomic_max_bits(unsigned *addr, float v) {
-  atomicMax(addr, __float_as_uint(fabsf(v)));
+  VB[v_index(I, n)] = v;
 }
 
 // Pass-B finalisation and everything local: term2, b = term1 + term2,
@@ -174,107 +172,76 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
                                                        const float *__restrict__ S, const float *__restrict__ wv,
                                                        const float *qin, const float *__restrict__ qstar,
                                                        float *out, float *out2, double *__restrict__ redp,
-                                                       Ctrl *ctrl, const int *__restrict__ done) {
+                                                       float *__restrict__ blockmax, const int *__restrict__ done) {
   __shared__ double sm[12][kRedBlock];
   if (done != nullptr && *done) return;
-  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
-  const bool real = I < p.P;
+  const int64_t I = group_particle();
+  const int n = group_lane();
+  const bool real = I < p.P;          // uniform over the 16 lanes of a particle
+  const bool comp = real && n < p.D;  // this lane owns a component
+  const int k = n / 3, al = n % 3, base = 3 * k;
+  const int64_t idx = ((int64_t)k * p.P + I) * 3 + al;
   double red[12];
 #pragma unroll
   for (int s = 0; s < 12; ++s) red[s] = 0.0;
   float resid = 0.f, xmax = 0.f;
 
-  if (real) {
-    double o[kMaxD + 1];
-    sum_splits(p, partial, splits, I, o);
-    float b[kMaxD], t2v[kMaxD];
-#pragma unroll
-    for (int a = 0; a < kMaxD; ++a) {
-      if (a < p.D) {
-        t2v[a] = (float)(-(double)p.inv_h2 * o[a]);
-        b[a] = t1[I * p.D + a] + t2v[a];
-      } else {
-        t2v[a] = 0.f;
-        b[a] = 0.f;
+  const double o = comp ? sum_splits(p, partial, splits, I, n) : 0.0;
+  const float t2v = (float)(-(double)p.inv_h2 * o);
+  const float t1v = comp ? t1[I * p.D + n] : 0.f;
+  const float b = t1v + t2v;
+  if (mode == MODE_TERMS) {
+    if (comp) {
+      out[idx] = t1v;
+      out2[idx] = t2v;
+    }
+  } else {
+    const float qv = comp ? qin[idx] : 0.f;
+    // the three components of this lane's bond
+    const float q0 = gshfl(qv, base), q1 = gshfl(qv, base + 1), q2 = gshfl(qv, base + 2);
+    const float r2 = q0 * q0 + q1 * q1 + q2 * q2;
+    const float H = k < p.nb ? p.H[k < kMaxNb ? k : 0] : 0.f;
+    float fac = H, psi = 0.f;
+    if (p.potential == VDS_FENE) {
+      const float sb = 1.f - r2 / p.b_max;
+      fac = H / sb;
+      psi = comp && al == 0 ? -0.5f * H * p.b_max * logf(sb) : 0.f;
+    } else {
+      psi = comp && al == 0 ? 0.5f * H * r2 : 0.f;
+    }
+    const float gp = comp ? fac * qv : 0.f;
+    const float g = comp ? p.kT * b + gp : 0.f;
+    // (A (x) I) g with A = tridiag(-1, 2, -1) over bonds
+    const float gm = gshfl(g, n >= 3 ? n - 3 : n), gpl = gshfl(g, n + 3 < 16 ? n + 3 : n);
+    float Ag = 2.f * g;
+    if (k > 0) Ag -= gm;
+    if (k + 1 < p.nb) Ag -= gpl;
+    const float flow = p.G[3 * (al % 3)] * q0 + p.G[3 * (al % 3) + 1] * q1 + p.G[3 * (al % 3) + 2] * q2;
+    const float u = -p.inv_zeta * Ag;
+    if (comp) {
+      if (mode == MODE_VELOCITY) {
+        out[idx] = flow + u;
+      } else if (mode == MODE_EXPLICIT) {
+        out[idx] = qv + p.dt * (flow + u);
+      } else if (mode == MODE_PICARD) {
+        const float xn = qstar[idx] + p.dt * u;
+        out[idx] = xn;
+        resid = fabsf(xn - qv);
+        xmax = fabsf(xn);
       }
     }
-    if (mode == MODE_TERMS) {
-      for (int a = 0; a < p.D; ++a) {
-        const int k = a / 3, al = a % 3;
-        out[((int64_t)k * p.P + I) * 3 + al] = t1[I * p.D + a];
-        out2[((int64_t)k * p.P + I) * 3 + al] = t2v[a];
-      }
-    } else {
-      float qv[kMaxD], g[kMaxD], psi = 0.f, gp[kMaxD];
-#pragma unroll
-      for (int a = 0; a < kMaxD; ++a) qv[a] = 0.f;
-      for (int a = 0; a < p.D; ++a) qv[a] = qin[((int64_t)(a / 3) * p.P + I) * 3 + (a % 3)];
-#pragma unroll
-      for (int k = 0; k < kMaxNb; ++k) {
-        if (k >= p.nb) break;
-        const float r2 = qv[3 * k] * qv[3 * k] + qv[3 * k + 1] * qv[3 * k + 1] + qv[3 * k + 2] * qv[3 * k + 2];
-        float fac = p.H[k];
-        if (p.potential == VDS_FENE) {
-          const float s = 1.f - r2 / p.b_max;
-          fac = p.H[k] / s;
-          psi += -0.5f * p.H[k] * p.b_max * logf(s);
-        } else {
-          psi += 0.5f * p.H[k] * r2;
-        }
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          gp[3 * k + al] = fac * qv[3 * k + al];
-          g[3 * k + al] = p.kT * b[3 * k + al] + gp[3 * k + al];
-        }
-      }
-      // (A (x) I) g with A = tridiag(-1, 2, -1)
-      float Ag[kMaxD];
-#pragma unroll
-      for (int k = 0; k < kMaxNb; ++k) {
-        if (k >= p.nb) break;
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          float v = 2.f * g[3 * k + al];
-          if (k > 0) v -= g[3 * (k - 1) + al];
-          if (k + 1 < p.nb) v -= g[3 * (k + 1) + al];
-          Ag[3 * k + al] = v;
-        }
-      }
-      for (int k = 0; k < p.nb; ++k) {
-        float flow[3];
-#pragma unroll
-        for (int al = 0; al < 3; ++al)
-          flow[al] = p.G[3 * al] * qv[3 * k] + p.G[3 * al + 1] * qv[3 * k + 1] + p.G[3 * al + 2] * qv[3 * k + 2];
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          const int a = 3 * k + al;
-          const int64_t idx = ((int64_t)k * p.P + I) * 3 + al;
-          const float u = -p.inv_zeta * Ag[a];
-          if (mode == MODE_VELOCITY) {
-            out[idx] = flow[al] + u;
-          } else if (mode == MODE_EXPLICIT) {
-            out[idx] = qv[a] + p.dt * (flow[al] + u);
-          } else if (mode == MODE_PICARD) {
-            const float xn = qstar[idx] + p.dt * u;
-            out[idx] = xn;
-            resid = fmaxf(resid, fabsf(xn - qv[a]));
-            xmax = fmaxf(xmax, fabsf(xn));
-          }
-        }
-        if (obs) {
-          const double wi = (double)wv[I];
-          for (int al = 0; al < 3; ++al) {
-            const int a = 3 * k + al;
-            red[RED_DISS] += wi * (double)g[a] * (double)Ag[a] * (double)p.inv_zeta;
-            red[RED_WORK] += wi * (double)g[a] * (double)flow[al];
-            for (int be = 0; be < 3; ++be)
-              red[RED_TAU + 3 * al + be] += (double)p.n * wi * (double)qv[a] * (double)gp[3 * k + be];
-          }
-        }
-      }
-      if (obs) {
+    if (obs) {
+      // stress column beta needs grad Psi of this bond's component beta
+      const float gp0 = gshfl(gp, base), gp1 = gshfl(gp, base + 1), gp2 = gshfl(gp, base + 2);
+      if (comp) {
         const double wi = (double)wv[I];
-        red[RED_F] = wi * ((double)p.kT * (log((double)S[I]) - (double)p.log_norm) + (double)psi);
+        red[RED_DISS] = wi * (double)g * (double)Ag * (double)p.inv_zeta;
+        red[RED_WORK] = wi * (double)g * (double)flow;
+        red[RED_TAU + 3 * al + 0] = (double)p.n * wi * (double)qv * (double)gp0;
+        red[RED_TAU + 3 * al + 1] = (double)p.n * wi * (double)qv * (double)gp1;
+        red[RED_TAU + 3 * al + 2] = (double)p.n * wi * (double)qv * (double)gp2;
+        red[RED_F] = wi * (double)psi;
+        if (n == 0) red[RED_F] += wi * (double)p.kT * (log((double)S[I]) - (double)p.log_norm);
       }
     }
   }
@@ -283,14 +250,26 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
     if (threadIdx.x < 12) redp[(int64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
   }
   if (mode == MODE_PICARD) {
-    // wave-level max, then one atomic per wave (max is order independent)
+    // block maxima of |dx| and |x| into per-block slots; the check kernel
+    // takes the max over blocks (no contended atomics)
+    __shared__ float smax[2][kRedBlock / 64];
     for (int off = 32; off > 0; off >>= 1) {
       resid = fmaxf(resid, __shfl_xor(resid, off));
       xmax = fmaxf(xmax, __shfl_xor(xmax, off));
     }
     if ((threadIdx.x & 63) == 0) {
-      atomic_max_bits(&ctrl->resid, resid);
-      atomic_max_bits(&ctrl->xmax, xmax);
+      smax[0][threadIdx.x >> 6] = resid;
+      smax[1][threadIdx.x >> 6] = xmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float r = 0.f, x = 0.f;
+      for (int i = 0; i < kRedBlock / 64; ++i) {
+        r = fmaxf(r, smax[0][i]);
+        x = fmaxf(x, smax[1][i]);
+      }
+      blockmax[2 * blockIdx.x] = r;
+      blockmax[2 * blockIdx.x + 1] = x;
     }
   }
 }
@@ -316,26 +295,40 @@ __global__ __launch_bounds__(kRedBlock) void k_qstar(EvalParams p, const float *
     qstar[i * 3 + al] = q[i * 3 + al] + p.dt * (p.G[3 * al] * a + p.G[3 * al + 1] * b + p.G[3 * al + 2] * c);
 }
 
-__global__ void k_picard_check(Ctrl *ctrl, float rtol, int iter) {
-  if (threadIdx.x != 0 || ctrl->done) return;
-  const float r = __uint_as_float(ctrl->resid);
-  const float xm = __uint_as_float(ctrl->xmax);
-  ctrl->last_resid = r;
+// Convergence test of the fixed-point iteration: max over the combine kernel's
+// block maxima, then max|dx| <= rtol * max(1, max|x|).
+__global__ __launch_bounds__(kRedBlock) void k_picard_check(Ctrl *ctrl, const float *__restrict__ blockmax, int nblk,
+                                                            float rtol, int iter) {
+  __shared__ float sr[kRedBlock], sx[kRedBlock];
+  if (ctrl->done) return;
+  float r = 0.f, x = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
+    r = fmaxf(r, blockmax[2 * b]);
+    x = fmaxf(x, blockmax[2 * b + 1]);
+  }
+  sr[threadIdx.x] = r;
+  sx[threadIdx.x] = x;
+  __syncthreads();
+  for (int st = kRedBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sr[threadIdx.x] = fmaxf(sr[threadIdx.x], sr[threadIdx.x + st]);
+      sx[threadIdx.x] = fmaxf(sx[threadIdx.x], sx[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  ctrl->last_resid = sr[0];
   ctrl->checked = iter + 1;
-  if (r <= rtol * fmaxf(1.f, xm)) {
+  if (sr[0] <= rtol * fmaxf(1.f, sx[0])) {
     ctrl->done = 1;
     ctrl->conv_iter = iter;
   }
-  ctrl->resid = 0u;
-  ctrl->xmax = 0u;
 }
 
 __global__ void k_ctrl_reset(Ctrl *ctrl) {
   if (threadIdx.x != 0) return;
   ctrl->done = 0;
   ctrl->conv_iter = -1;
-  ctrl->resid = 0u;
-  ctrl->xmax = 0u;
   ctrl->last_resid = 0.f;
   ctrl->checked = 0;
 }
@@ -408,17 +401,17 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 }
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
                  float *wv, float *QB, float *KA, float *VA, const int *done, hipStream_t s) {
-  k_prep<<<nblocks(p.Ppad), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, done);
+  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, done);
 }
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {
-  k_finalize_a<<<nblocks(p.Ppad), kRedBlock, 0, s>>>(p, partial, splits, xc, wv, S, t1, VB, done);
+  k_finalize_a<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, partial, splits, xc, wv, S, t1, VB, done);
 }
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *qstar,
-                    float *out, float *out2, double *redp, Ctrl *ctrl, const int *done, hipStream_t s) {
-  k_combine<<<nblocks(p.P), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, qstar,
-                                               out, out2, redp, ctrl, done);
+                    float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s) {
+  k_combine<<<nblocks(p.P * 16), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, qstar,
+                                                    out, out2, redp, blockmax, done);
 }
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s) {
   k_reduce_final<<<1, 64, 0, s>>>(redp, nblk, nslots, out, done);
@@ -426,8 +419,8 @@ void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, 
 void launch_qstar(const EvalParams &p, const float *q, float *qstar, hipStream_t s) {
   k_qstar<<<nblocks((int64_t)p.nb * p.P), kRedBlock, 0, s>>>(p, q, qstar);
 }
-void launch_picard_check(Ctrl *ctrl, float rtol, int iter, hipStream_t s) {
-  k_picard_check<<<1, 64, 0, s>>>(ctrl, rtol, iter);
+void launch_picard_check(Ctrl *ctrl, const float *blockmax, int nblk, float rtol, int iter, hipStream_t s) {
+  k_picard_check<<<1, kRedBlock, 0, s>>>(ctrl, blockmax, nblk, rtol, iter);
 }
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s) { k_ctrl_reset<<<1, 64, 0, s>>>(ctrl); }
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s) {

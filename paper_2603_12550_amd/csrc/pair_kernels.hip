@@ -41,31 +41,32 @@ namespace vds {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFlush = 4;  // chunks per FP32 accumulation group
+constexpr int kFlush = 8;  // chunks per FP32 accumulation group
 
 template <int KK, int RB>
-__global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB, int64_t nrow_blocks,
+__global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB, int nrow_blocks,
                                                    const float *__restrict__ KA, const float4 *__restrict__ VB,
-                                                   int64_t ncol_chunks, int64_t chunks_per_split,
+                                                   int ncol_chunks, int chunks_per_split,
                                                    const float *__restrict__ xc, int D, int exclude_self,
                                                    float *__restrict__ partial, int64_t part_stride_rows,
                                                    const int *__restrict__ done) {
   if (done != nullptr && *done) return;
   const int lane = threadIdx.x & 63;
+  // wave index as a scalar so that row-block tests compile to scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rb0 = ((int)blockIdx.x * 4 + wave) * RB;
+  if (rb0 >= nrow_blocks) return;  // no barriers below: a wave may leave alone
+  const int c0 = (int)blockIdx.y * chunks_per_split;
+  const int c1 = min(ncol_chunks, c0 + chunks_per_split);
   // position of the self pair inside a diagonal 16x16 tile, per element i
   const int diag_i = (lane & 15) - 4 * (lane >> 4);  // in 0..3 when this lane holds one
-  const int wave = threadIdx.x >> 6;
-  const int64_t rb0 = ((int64_t)blockIdx.x * 4 + wave) * RB;
-  if (rb0 >= nrow_blocks) return;  // no barriers below: a wave may leave alone
-  const int64_t c0 = (int64_t)blockIdx.y * chunks_per_split;
-  const int64_t c1 = min(ncol_chunks, c0 + chunks_per_split);
 
   float qv[RB][KK];
 #pragma unroll
   for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk)
-      qv[r][kk] = (rb0 + r < nrow_blocks) ? QB[((rb0 + r) * KK + kk) * 64 + lane] : 0.f;
+      qv[r][kk] = (rb0 + r < nrow_blocks) ? QB[((int64_t)(rb0 + r) * KK + kk) * 64 + lane] : 0.f;
 
   double tot[RB][4];
 #pragma unroll
@@ -77,11 +78,11 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
   float4 vb;
   if (c0 < c1) {
 #pragma unroll
-    for (int kk = 0; kk < KK; ++kk) ka[kk] = KA[(c0 * KK + kk) * 64 + lane];
-    vb = VB[c0 * 64 + lane];
+    for (int kk = 0; kk < KK; ++kk) ka[kk] = KA[((int64_t)c0 * KK + kk) * 64 + lane];
+    vb = VB[(int64_t)c0 * 64 + lane];
   }
-  for (int64_t c = c0; c < c1;) {
-    const int64_t cg_end = min(c1, c + kFlush);
+  for (int c = c0; c < c1;) {
+    const int cg_end = min(c1, c + kFlush);
     floatx4 acc[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[r] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -89,21 +90,23 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
       // prefetch the next chunk's operands while this one computes
       float kn[KK];
       float4 vn;
-      const int64_t cn = (c + 1 < c1) ? c + 1 : c;
+      const int cn = (c + 1 < c1) ? c + 1 : c;
 #pragma unroll
-      for (int kk = 0; kk < KK; ++kk) kn[kk] = KA[(cn * KK + kk) * 64 + lane];
-      vn = VB[cn * 64 + lane];
+      for (int kk = 0; kk < KK; ++kk) kn[kk] = KA[((int64_t)cn * KK + kk) * 64 + lane];
+      vn = VB[(int64_t)cn * 64 + lane];
 
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         floatx4 t = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ka[kk], qv[r][kk], t, 0, 0, 0);
-        float e0 = __builtin_amdgcn_exp2f(fminf(t[0], 0.f));
-        float e1 = __builtin_amdgcn_exp2f(fminf(t[1], 0.f));
-        float e2 = __builtin_amdgcn_exp2f(fminf(t[2], 0.f));
-        float e3 = __builtin_amdgcn_exp2f(fminf(t[3], 0.f));
-        if (exclude_self && c == rb0 + r) {  // wave-uniform: the diagonal tile
+        // e = 2^t clamped to [0, 1] by the instruction's output clamp: the same as
+        // clamping the expanded squared distance at zero
+        float e0 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[0]), 0.f, 1.f);
+        float e1 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[1]), 0.f, 1.f);
+        float e2 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[2]), 0.f, 1.f);
+        float e3 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[3]), 0.f, 1.f);
+        if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
           e0 = diag_i == 0 ? 0.f : e0;
           e1 = diag_i == 1 ? 0.f : e1;
           e2 = diag_i == 2 ? 0.f : e2;
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double s = __shfl(tot[r][i], src);
-      const int64_t row = (rb0 + r) * 16 + 4 * (lane >> 4) + i;
+      const int64_t row = (int64_t)(rb0 + r) * 16 + 4 * (lane >> 4) + i;
       double v = 0.0;
       if (n < D) v = (double)xc[row * D + n] * s - tot[r][i];
       else if (n == D) v = s;
@@ -239,8 +242,8 @@ bool pair_shape_ok(const vds_tuning &t, int D) {
 }
 
 template <int KK>
-static void launch_mfma_kk(int rb, dim3 grid, const float *QB, int64_t nrb, const float *KA, const float *VB,
-                           int64_t ncc, int64_t cps, const float *xc, int D, int ex, float *partial, int64_t stride,
+static void launch_mfma_kk(int rb, dim3 grid, const float *QB, int nrb, const float *KA, const float *VB,
+                           int ncc, int cps, const float *xc, int D, int ex, float *partial, int64_t stride,
                            const int *done, hipStream_t s) {
   const float4 *vb = reinterpret_cast<const float4 *>(VB);
   switch (rb) {
@@ -260,10 +263,10 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
     const int rb = t.rows_per_wave;
     dim3 grid((unsigned)((nrow_blocks + 4 * rb - 1) / (4 * rb)), (unsigned)splits);
     switch (KK) {
-      case 2: launch_mfma_kk<2>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
-      case 3: launch_mfma_kk<3>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
-      case 4: launch_mfma_kk<4>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
-      default: launch_mfma_kk<5>(rb, grid, QB, nrow_blocks, KA, VB, ncol_chunks, cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      case 2: launch_mfma_kk<2>(rb, grid, QB, (int)nrow_blocks, KA, VB, (int)ncol_chunks, (int)cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      case 3: launch_mfma_kk<3>(rb, grid, QB, (int)nrow_blocks, KA, VB, (int)ncol_chunks, (int)cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      case 4: launch_mfma_kk<4>(rb, grid, QB, (int)nrow_blocks, KA, VB, (int)ncol_chunks, (int)cps, xc, D, ex, partial, part_stride_rows, done, s); break;
+      default: launch_mfma_kk<5>(rb, grid, QB, (int)nrow_blocks, KA, VB, (int)ncol_chunks, (int)cps, xc, D, ex, partial, part_stride_rows, done, s); break;
     }
   } else {
     const int64_t nrows = nrow_blocks * 16;

@@ -1,0 +1,529 @@
+// Galerkin reduced model of the particle scheme (C ABI of include/vds_pod.h).
+//
+// Per freeze: reconstruct q~ = U p, run the two kernel passes at q~ for
+// S = Z w and T = Z (w/S), form Y = Z [w U_a | (w/S) U_a]_a with the kernel
+// matrix generated tile by tile on MFMA (never stored), then contract with the
+// mode blocks into X^B1 and X^B2.  Between freezes a single workgroup takes the
+// explicit Euler steps of the reduced equation.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "vds_ctx.h"
+#include "vds_linalg.h"
+#include "vds_pod.h"
+
+using namespace vds;
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kMaxR = 1024;
+constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the kernel-GEMM
+constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
+
+struct RomLayout {
+  size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, total;
+  int NB16;
+  int64_t ldy;
+};
+
+RomLayout rom_layout(const vds_problem &p, int R) {
+  RomLayout L{};
+  const int64_t P = p.P, Ppad = round_up(P, kRowAlign);
+  const int ncols = 2 * 3 * R;
+  L.NB16 = (ncols + 15) / 16;
+  L.ldy = (int64_t)L.NB16 * 16;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += (b + 255) / 256 * 256;
+    return o;
+  };
+  L.Ude = take(sizeof(float) * 3 * (size_t)R * P);
+  L.Mbig = take(sizeof(float) * 9 * (size_t)R * R);
+  L.XH = take(sizeof(float) * R * R);
+  L.I1 = take(sizeof(float) * R * R);
+  L.XB1 = take(sizeof(float) * R * R);
+  L.XB2 = take(sizeof(float) * R * R);
+  L.XB = take(sizeof(float) * R * R);
+  L.Bsw = take(sizeof(float) * (size_t)Ppad * L.ldy);
+  L.Y = take(sizeof(float) * (size_t)Ppad * L.ldy);
+  L.qt = take(sizeof(float) * (size_t)p.nb * P * 3);
+  L.T = take(sizeof(float) * Ppad);
+  L.invS = take(sizeof(float) * Ppad);
+  const int64_t m = 3 * P;
+  const size_t part = std::max({sizeof(float) * (size_t)gemm_splits(3 * R, 3 * R, P) * 9 * R * R,
+                                sizeof(float) * (size_t)gemm_splits(R, R, P) * R * R,
+                                sizeof(float) * (size_t)m * p.nb});
+  L.part = take(part);
+  L.red = take(sizeof(double) * 16);
+  L.total = off;
+  return L;
+}
+
+// Ude[a][s][I] = U[s m + 3 I + a]: the mode blocks U_a, K-contiguous over I.
+__global__ void k_deinterleave(const float *__restrict__ U, int64_t P, int R, float *__restrict__ Ude) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= 3 * (int64_t)R * P) return;
+  const int64_t I = t % P;
+  const int64_t rest = t / P;
+  const int s = (int)(rest % R), a = (int)(rest / R);
+  Ude[t] = U[(int64_t)s * 3 * P + 3 * I + a];
+}
+
+// X^H = sum_ab G_ab M_ab and I1 = sum_a M_aa from Mbig[(a R + s)][(b R + t)].
+__global__ void k_hydro(const float *__restrict__ Mbig, int R, EvalParams p, float *__restrict__ XH,
+                        float *__restrict__ I1) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)R * R) return;
+  const int s = (int)(t / R), u = (int)(t % R);
+  const int64_t ld = 3 * (int64_t)R;
+  float h = 0.f, id = 0.f;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const float m = Mbig[(a * (int64_t)R + s) * ld + b * R + u];
+      h += p.G[3 * a + b] * m;
+      if (a == b) id += m;
+    }
+  XH[t] = h;
+  I1[t] = id;
+}
+
+// T_I = w_I / S_I + sum_{K != I} (w_K / S_K) e_IK from the pass-B partials, and 1/S.
+__global__ void k_rom_scalars(const float *__restrict__ part, int splits, int64_t Ppad, int64_t P, int D,
+                              const float *__restrict__ S, const float *__restrict__ wv, float *__restrict__ T,
+                              float *__restrict__ invS) {
+  const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (I >= Ppad) return;
+  if (I >= P) {
+    T[I] = 0.f;
+    invS[I] = 0.f;
+    return;
+  }
+  double o = 0.0;
+  for (int s = 0; s < splits; ++s) o += (double)part[((int64_t)s * Ppad + I) * 16 + D];
+  const double Si = (double)S[I];
+  T[I] = (float)(o + (double)wv[I] / Si);
+  invS[I] = (float)(1.0 / Si);
+}
+
+// Kernel-GEMM right operand B[J][col], col = h dR + a R + t:
+// (h = 0: w_J, h = 1: w_J / S_J) * U_a[t][J], in the swizzled MFMA layout
+// Bsw[((c NB16 + nbk) 64 + lane) 4 + i] = B[16 c + 4 (lane / 16) + i][16 nbk + lane % 16].
+__global__ void k_rom_bsw(const float *__restrict__ Ude, const float *__restrict__ wv, const float *__restrict__ invS,
+                          int64_t P, int64_t Ppad, int R, int NB16, float *__restrict__ Bsw) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t ldy = (int64_t)NB16 * 16;
+  if (t >= Ppad * ldy) return;
+  const int64_t J = t / ldy;
+  const int col = (int)(t % ldy);
+  const int dR = 3 * R;
+  float v = 0.f;
+  if (J < P && col < 2 * dR) {
+    const int h = col / dR, rem = col % dR, a = rem / R, tt = rem % R;
+    const float wgt = h == 0 ? wv[J] : wv[J] * invS[J];
+    v = wgt * Ude[((int64_t)a * R + tt) * P + J];
+  }
+  const int64_t c = J >> 4;
+  const int jj = (int)(J & 15);
+  const int lane = 16 * (jj >> 2) + (col & 15);
+  const int nbk = col >> 4;
+  Bsw[((c * NB16 + nbk) * 64 + lane) * 4 + (jj & 3)] = v;
+}
+
+// Y[I][col] = sum_J Z_IJ B[J][col], Z_IJ = exp(-|x_I - x_J|^2 / 2h^2) (Z_II = 1),
+// from the Q/K operands of the pair kernels.  One 16-row block per wavefront,
+// kNBG 16-column output blocks per workgroup; FP32 accumulation flushed to FP64.
+template <int KK>
+__global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ QB, const float *__restrict__ KA,
+                                                     int nrow_blocks, int ncol_chunks,
+                                                     const float4 *__restrict__ Bsw, int NB16,
+                                                     float *__restrict__ Y, int64_t ldy) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rb = (int)blockIdx.x * 4 + wave;
+  if (rb >= nrow_blocks) return;
+  const int nb0 = (int)blockIdx.y * kNBG;
+  const int nbn = min(kNBG, NB16 - nb0);
+  const int diag_i = (lane & 15) - 4 * (lane >> 4);
+  float qv[KK];
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) qv[kk] = QB[((int64_t)rb * KK + kk) * 64 + lane];
+  double tot[kNBG][4];
+#pragma unroll
+  for (int g = 0; g < kNBG; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[g][i] = 0.0;
+
+  for (int c = 0; c < ncol_chunks;) {
+    const int cg_end = min(ncol_chunks, c + kKgFlush);
+    floatx4 acc[kNBG];
+#pragma unroll
+    for (int g = 0; g < kNBG; ++g) acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; c < cg_end; ++c) {
+      floatx4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk)
+        t = __builtin_amdgcn_mfma_f32_16x16x4f32(KA[((int64_t)c * KK + kk) * 64 + lane], qv[kk], t, 0, 0, 0);
+      float e0 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[0]), 0.f, 1.f);
+      float e1 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[1]), 0.f, 1.f);
+      float e2 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[2]), 0.f, 1.f);
+      float e3 = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(t[3]), 0.f, 1.f);
+      if (c == rb) {  // the self pair has Z_II = K_h(0) = 1 exactly
+        e0 = diag_i == 0 ? 1.f : e0;
+        e1 = diag_i == 1 ? 1.f : e1;
+        e2 = diag_i == 2 ? 1.f : e2;
+        e3 = diag_i == 3 ? 1.f : e3;
+      }
+      const float4 *bp = Bsw + ((int64_t)c * NB16 + nb0) * 64 + lane;
+#pragma unroll
+      for (int g = 0; g < kNBG; ++g) {
+        if (g < nbn) {
+          const float4 b = bp[(int64_t)g * 64];
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(e0, b.x, acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(e1, b.y, acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(e2, b.z, acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(e3, b.w, acc[g], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kNBG; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tot[g][i] += (double)acc[g][i];
+  }
+#pragma unroll
+  for (int g = 0; g < kNBG; ++g) {
+    if (g >= nbn) break;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = (int64_t)rb * 16 + 4 * (lane >> 4) + i;
+      Y[row * ldy + (int64_t)(nb0 + g) * 16 + (lane & 15)] = (float)tot[g][i];
+    }
+  }
+}
+
+__global__ void k_fill_scaled(const float *__restrict__ src, float a, int64_t n, float *__restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) dst[t] = a * src[t];
+}
+
+__global__ void k_add(const float *__restrict__ a, const float *__restrict__ b, int64_t n, float *__restrict__ c) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) c[t] = a[t] + b[t];
+}
+
+// Explicit Euler on the reduced state p[k][s] (eq. model_DymReduced):
+// dp_k/dt = X^H p_k - (kT/zeta) sum_j A_kj X^B p_j - (1/zeta) sum_j A_kj H_j p_j.
+// One workgroup; p in LDS; each wavefront takes whole rows of X^H / X^B.
+__global__ __launch_bounds__(1024) void k_rom_steps(const float *__restrict__ XH, const float *__restrict__ XB,
+                                                    float *__restrict__ p, int nb, int R, int nsteps, EvalParams ep) {
+  __shared__ float ps[kMaxNb][kMaxR];
+  __shared__ float y[kMaxNb][kMaxR];
+  __shared__ float z[kMaxNb][kMaxR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int t = tid; t < nb * R; t += blockDim.x) ps[t / R][t % R] = p[t];
+  __syncthreads();
+  const float ktz = ep.kT * ep.inv_zeta;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int row = wave; row < 2 * R; row += nw) {
+      const float *M = row < R ? XH + (int64_t)row * R : XB + (int64_t)(row - R) * R;
+      float acc[kMaxNb];
+#pragma unroll
+      for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
+      for (int u = lane; u < R; u += 64) {
+        const float m = M[u];
+#pragma unroll
+        for (int k = 0; k < kMaxNb; ++k)
+          if (k < nb) acc[k] = fmaf(m, ps[k][u], acc[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxNb; ++k) {
+        float v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        acc[k] = v;
+      }
+      if (lane == 0) {
+        for (int k = 0; k < nb; ++k) {
+          if (row < R) y[k][row] = acc[k];
+          else z[k][row - R] = acc[k];
+        }
+      }
+    }
+    __syncthreads();
+    float pn[kMaxNb * kMaxR / 1024 + 1];
+    int cnt = 0;
+    for (int t = tid; t < nb * R; t += blockDim.x, ++cnt) {
+      const int k = t / R, s = t % R;
+      float az = 2.f * z[k][s], ah = 2.f * ep.H[k] * ps[k][s];
+      if (k > 0) {
+        az -= z[k - 1][s];
+        ah -= ep.H[k - 1] * ps[k - 1][s];
+      }
+      if (k + 1 < nb) {
+        az -= z[k + 1][s];
+        ah -= ep.H[k + 1] * ps[k + 1][s];
+      }
+      pn[cnt] = ps[k][s] + ep.dt * (y[k][s] - ktz * az - ep.inv_zeta * ah);
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int t = tid; t < nb * R; t += blockDim.x, ++cnt) ps[t / R][t % R] = pn[cnt];
+    __syncthreads();
+  }
+  for (int t = tid; t < nb * R; t += blockDim.x) p[t] = ps[t / R][t % R];
+}
+
+// tau_ab = (n / P) sum_k H_k p_k^T M_ab p_k (uniform weights), FP64 sums.
+__global__ __launch_bounds__(256) void k_rom_stress(const float *__restrict__ Mbig, const float *__restrict__ p, int nb,
+                                                    int R, EvalParams ep, double *__restrict__ out) {
+  __shared__ double sm[256];
+  const int ab = blockIdx.x;  // 0..8
+  const int a = ab / 3, b = ab % 3;
+  const int64_t ld = 3 * (int64_t)R;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < (int64_t)R * R; t += 256) {
+    const int s = (int)(t / R), u = (int)(t % R);
+    const double m = Mbig[(a * (int64_t)R + s) * ld + b * R + u];
+    for (int k = 0; k < nb; ++k) acc += (double)ep.H[k] * (double)p[k * R + s] * m * (double)p[k * R + u];
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[ab] = sm[0] * (double)ep.n / (double)ep.P;
+}
+
+inline unsigned nblk256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+struct vds_rom_s {
+  vds_ctx ctx = nullptr;
+  const float *U = nullptr;
+  int R = 0;
+  RomLayout L{};
+  char *ws = nullptr;
+  float *Ude, *Mbig, *XH, *I1, *XB1, *XB2, *XB, *Bsw, *Y, *qt, *T, *invS, *part;
+  double *red;
+};
+
+namespace {
+
+vds_status rom_gemm(vds_rom r, GemmShape g, double flops) {
+  timed(r->ctx, VDS_TIMER_GEMM, flops, [&] { launch_gemm(g, r->part, r->ctx->stream); });
+  return VDS_OK;
+}
+
+// X^B1, X^B2 (and X^B = X^B1 + X^B2) at q~ = U p.
+vds_status freeze(vds_rom r, const float *p) {
+  vds_ctx c = r->ctx;
+  const int R = r->R;
+  const int64_t P = c->prob.P, Ppad = c->ep.Ppad, m = 3 * P;
+  const RomLayout &L = r->L;
+  hipStream_t s = c->stream;
+  // q~ = U p
+  {
+    GemmShape g;
+    g.M = (int)m;
+    g.N = c->prob.nb;
+    g.K = R;
+    g.A = r->U;
+    g.lda = m;
+    g.a_mn = true;
+    g.B = p;
+    g.ldb = R;
+    g.C = r->qt;
+    g.ldc = m;
+    g.c_colmajor = true;
+    timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] { launch_gemm(g, r->part, s); });
+  }
+  // S and T at q~ (uniform weights), Q/K operands for Z
+  eval_pass_a(c, r->qt, nullptr, nullptr);
+  eval_pass_b(c, nullptr);
+  k_rom_scalars<<<nblk256(Ppad), 256, 0, s>>>(c->part, c->tune.col_splits, Ppad, P, c->ep.D, c->S, c->wv, r->T,
+                                              r->invS);
+  k_rom_bsw<<<nblk256(Ppad * L.ldy), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, L.NB16, r->Bsw);
+  // Y = Z B
+  {
+    const int nrb = (int)(Ppad / 16), ncc = (int)((P + 15) / 16);
+    dim3 grid((unsigned)((nrb + 3) / 4), (unsigned)((L.NB16 + kNBG - 1) / kNBG));
+    const float4 *b4 = reinterpret_cast<const float4 *>(r->Bsw);
+    const double flops = 2.0 * (double)P * P * 2 * 3 * R;
+    timed(c, VDS_TIMER_KGEMM, flops, [&] {
+      switch (c->ep.KK) {
+        case 2: k_kernel_gemm<2><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, b4, L.NB16, r->Y, L.ldy); break;
+        case 3: k_kernel_gemm<3><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, b4, L.NB16, r->Y, L.ldy); break;
+        case 4: k_kernel_gemm<4><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, b4, L.NB16, r->Y, L.ldy); break;
+        default: k_kernel_gemm<5><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, b4, L.NB16, r->Y, L.ldy); break;
+      }
+    });
+  }
+  const float ih2 = c->ep.inv_h2;
+  const int64_t RR = (int64_t)R * R;
+  // X^B1 = -(1/h^2) I1 + (1/h^2) sum_a U_a^T diag(1/S) Y1_a
+  k_fill_scaled<<<nblk256(RR), 256, 0, s>>>(r->I1, -ih2, RR, r->XB1);
+  {
+    GemmShape g;
+    g.M = R;
+    g.N = R;
+    g.K = P;
+    g.nbatch = 3;
+    g.A = r->Ude;
+    g.lda = P;
+    g.sA = (int64_t)R * P;
+    g.B = r->Y;
+    g.ldb = L.ldy;
+    g.sB = R;
+    g.b_mn = true;
+    g.scale = r->invS;
+    g.alpha = ih2;
+    g.C = r->XB1;
+    g.ldc = R;
+    g.accumulate = true;
+    g.splits = gemm_splits(R, R, P);
+    rom_gemm(r, g, 2.0 * 3 * RR * P);
+  }
+  // X^B2 = -(1/h^2) sum_a U_a^T diag(T) U_a + (1/h^2) sum_a U_a^T Y2_a
+  {
+    GemmShape g;
+    g.M = R;
+    g.N = R;
+    g.K = P;
+    g.nbatch = 3;
+    g.A = r->Ude;
+    g.lda = P;
+    g.sA = (int64_t)R * P;
+    g.B = r->Ude;
+    g.ldb = P;
+    g.sB = (int64_t)R * P;
+    g.scale = r->T;
+    g.alpha = -ih2;
+    g.C = r->XB2;
+    g.ldc = R;
+    g.splits = gemm_splits(R, R, P);
+    rom_gemm(r, g, 2.0 * 3 * RR * P);
+    g.B = r->Y + 3 * R;
+    g.ldb = L.ldy;
+    g.sB = R;
+    g.b_mn = true;
+    g.scale = nullptr;
+    g.alpha = ih2;
+    g.accumulate = true;
+    rom_gemm(r, g, 2.0 * 3 * RR * P);
+  }
+  k_add<<<nblk256(RR), 256, 0, s>>>(r->XB1, r->XB2, RR, r->XB);
+  return hip_check(c, hipGetLastError(), "reduced operators");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vds_rom_workspace_bytes(const vds_problem *prob, int32_t R) {
+  if (prob == nullptr || prob->P < 1 || prob->nb < 1 || R < 1 || R > kMaxR || R > 3 * prob->P) return 0;
+  return rom_layout(*prob, R).total;
+}
+
+vds_status vds_rom_create(vds_ctx c, const float *U, int32_t R, void *ws, size_t bytes, vds_rom *out) {
+  vds_status st = ready(c);
+  if (st != VDS_OK) return st;
+  if (!U || !ws || !out || R < 1 || R > kMaxR || R > 3 * c->prob.P)
+    return set_err(c, VDS_ERR_ARG, "bad arguments (1 <= R <= min(1024, 3P))");
+  if (c->prob.potential != VDS_HOOKEAN)
+    return set_err(c, VDS_ERR_ARG, "the reduced spring term is exact only for Hookean springs");
+  const RomLayout L = rom_layout(c->prob, R);
+  if (bytes < L.total) return set_err(c, VDS_ERR_NOMEM, "reduced-model workspace too small");
+  vds_rom r = new (std::nothrow) vds_rom_s();
+  if (r == nullptr) return set_err(c, VDS_ERR_NOMEM, "host allocation failed");
+  r->ctx = c;
+  r->U = U;
+  r->R = R;
+  r->L = L;
+  r->ws = static_cast<char *>(ws);
+  auto f = [&](size_t o) { return reinterpret_cast<float *>(r->ws + o); };
+  r->Ude = f(L.Ude);
+  r->Mbig = f(L.Mbig);
+  r->XH = f(L.XH);
+  r->I1 = f(L.I1);
+  r->XB1 = f(L.XB1);
+  r->XB2 = f(L.XB2);
+  r->XB = f(L.XB);
+  r->Bsw = f(L.Bsw);
+  r->Y = f(L.Y);
+  r->qt = f(L.qt);
+  r->T = f(L.T);
+  r->invS = f(L.invS);
+  r->part = f(L.part);
+  r->red = reinterpret_cast<double *>(r->ws + L.red);
+  const int64_t P = c->prob.P;
+  hipStream_t s = c->stream;
+  k_deinterleave<<<nblk256(3 * (int64_t)R * P), 256, 0, s>>>(U, P, R, r->Ude);
+  GemmShape g;
+  g.M = 3 * R;
+  g.N = 3 * R;
+  g.K = P;
+  g.A = r->Ude;
+  g.lda = P;
+  g.B = r->Ude;
+  g.ldb = P;
+  g.C = r->Mbig;
+  g.ldc = 3 * R;
+  g.splits = gemm_splits(3 * R, 3 * R, P);
+  rom_gemm(r, g, 2.0 * 9.0 * R * R * P);
+  k_hydro<<<nblk256((int64_t)R * R), 256, 0, s>>>(r->Mbig, R, c->ep, r->XH, r->I1);
+  st = hip_check(c, hipGetLastError(), "reduced model setup");
+  if (st != VDS_OK) {
+    delete r;
+    return st;
+  }
+  *out = r;
+  return VDS_OK;
+}
+
+void vds_rom_destroy(vds_rom r) { delete r; }
+
+vds_status vds_rom_operators(vds_rom r, const float *p, float *XH, float *XB1, float *XB2) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  vds_ctx c = r->ctx;
+  if (!p) return set_err(c, VDS_ERR_ARG, "null p");
+  vds_status st = freeze(r, p);
+  if (st != VDS_OK) return st;
+  const size_t b = sizeof(float) * r->R * r->R;
+  if (XH) st = hip_check(c, hipMemcpyAsync(XH, r->XH, b, hipMemcpyDeviceToDevice, c->stream), "copy");
+  if (XB1 && st == VDS_OK) st = hip_check(c, hipMemcpyAsync(XB1, r->XB1, b, hipMemcpyDeviceToDevice, c->stream), "copy");
+  if (XB2 && st == VDS_OK) st = hip_check(c, hipMemcpyAsync(XB2, r->XB2, b, hipMemcpyDeviceToDevice, c->stream), "copy");
+  return st;
+}
+
+vds_status vds_rom_stress(vds_rom r, const float *p, double *tau) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  vds_ctx c = r->ctx;
+  if (!p || !tau) return set_err(c, VDS_ERR_ARG, "null argument");
+  k_rom_stress<<<9, 256, 0, c->stream>>>(r->Mbig, p, c->prob.nb, r->R, c->ep, r->red);
+  vds_status st = hip_check(c, hipMemcpyAsync(tau, r->red, sizeof(double) * 9, hipMemcpyDeviceToHost, c->stream), "copy");
+  if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+  return st;
+}
+
+vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  vds_ctx c = r->ctx;
+  if (!p || nsteps < 0 || freeze_every < 1) return set_err(c, VDS_ERR_ARG, "bad arguments");
+  for (int s0 = 0; s0 < nsteps; s0 += freeze_every) {
+    vds_status st = freeze(r, p);
+    if (st != VDS_OK) return st;
+    const int n = std::min(freeze_every, nsteps - s0);
+    k_rom_steps<<<1, 1024, 0, c->stream>>>(r->XH, r->XB, p, c->prob.nb, r->R, n, c->ep);
+  }
+  vds_status st = hip_check(c, hipGetLastError(), "reduced steps");
+  if (st != VDS_OK) return st;
+  if (tau) return vds_rom_stress(r, p, tau);
+  return hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+}
+
+}  // extern "C"

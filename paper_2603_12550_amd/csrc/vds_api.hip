@@ -5,48 +5,67 @@
 #include <cstring>
 #include <new>
 
+#include "vds_ctx.h"
 #include "vds_internal.h"
 
 using namespace vds;
 
 namespace {
-
 thread_local std::string g_create_error;
-
-struct Layout {
-  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, qstar, xb0, xb1, total;
-};
-
-struct TimerAcc {
-  double ms = 0.0;
-  int64_t launches = 0;
-  double work = 0.0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  std::vector<double> pending_work;
-};
-
 }  // namespace
 
-struct vds_ctx_s {
-  vds_problem prob{};
-  std::vector<double> H;
-  hipStream_t stream = nullptr;
-  EvalParams ep{};
-  vds_tuning tune{VDS_PAIR_MFMA, 2, 8, 0};
-  Layout lay{};
-  char *ws = nullptr;
-  size_t ws_bytes = 0;
-  std::string err;
-  bool timing = false;
-  TimerAcc timers[VDS_TIMER_COUNT];
-  std::vector<hipEvent_t> event_pool;
+namespace vds {
 
-  // workspace views
-  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *qstar, *xb[2];
-  double *meanp, *redp, *redout;
-  Ctrl *ctrl;
-  int nblk;  // blocks of the O(P) kernels over real particles
-};
+vds_status set_err(vds_ctx c, vds_status st, const std::string &m) {
+  if (c) c->err = m;
+  return st;
+}
+
+vds_status hip_check(vds_ctx c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return VDS_OK;
+  return set_err(c, VDS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+vds_status ready(vds_ctx c) {
+  if (c == nullptr) return VDS_ERR_ARG;
+  if (c->ws == nullptr) return set_err(c, VDS_ERR_STATE, "no workspace bound");
+  return VDS_OK;
+}
+
+hipEvent_t get_event(vds_ctx c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+int64_t ncol_chunks(const vds_ctx c) { return (c->prob.P + 15) / 16; }
+
+// One pair pass over all particle rows with the V operand `V`.
+void pair_pass(vds_ctx c, const float *V, const int *done) {
+  const int64_t nrb = c->ep.Ppad / 16;
+  const double pairs = (double)c->prob.P * (double)c->prob.P;
+  timed(c, VDS_TIMER_PAIR, pairs, [&] {
+    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->QB, nrb, c->KA, V, ncol_chunks(c), c->xc, true, c->part, c->ep.Ppad,
+                     done, c->stream);
+  });
+}
+
+void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done) {
+  const EvalParams &e = c->ep;
+  launch_mean_partials(e, q, w, c->meanp, done, c->stream);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, done, c->stream);
+  pair_pass(c, c->VA, done);
+  launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
+}
+
+void eval_pass_b(vds_ctx c, const int *done) { pair_pass(c, c->VB, done); }
+
+}  // namespace vds
 
 namespace {
 
@@ -81,7 +100,8 @@ Layout make_layout(const vds_problem &p) {
   const int64_t Ppad = round_up(p.P, kRowAlign);
   const int D = 3 * p.nb;
   const int KK = (D + 2 + 3) / 4;
-  const int64_t nblk = (p.P + kRedBlock - 1) / kRedBlock;
+  // per-particle kernels run either one thread or 16 lanes per particle
+  const int64_t nblk = (p.P * 16 + kRedBlock - 1) / kRedBlock;
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -102,6 +122,7 @@ Layout make_layout(const vds_problem &p) {
   L.redp = take(sizeof(double) * nblk * 16);
   L.redout = take(sizeof(double) * 16);
   L.ctrl = take(sizeof(Ctrl));
+  L.blockmax = take(sizeof(float) * 2 * nblk);
   L.qstar = take(sizeof(float) * p.P * D);
   L.xb0 = take(sizeof(float) * p.P * D);
   L.xb1 = take(sizeof(float) * p.P * D);
@@ -130,48 +151,7 @@ void fill_params(vds_ctx c) {
   e.uniform_w = (float)(1.0 / (double)p.P);
   e.log_norm = (float)(0.5 * e.D * std::log(2.0 * M_PI * p.h * p.h));
   c->nblk = (int)((p.P + kRedBlock - 1) / kRedBlock);
-}
-
-vds_status set_err(vds_ctx c, vds_status st, const std::string &m) {
-  if (c) c->err = m;
-  return st;
-}
-
-vds_status hip_check(vds_ctx c, hipError_t e, const char *what) {
-  if (e == hipSuccess) return VDS_OK;
-  return set_err(c, VDS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-vds_status ready(vds_ctx c) {
-  if (c == nullptr) return VDS_ERR_ARG;
-  if (c->ws == nullptr) return set_err(c, VDS_ERR_STATE, "no workspace bound");
-  return VDS_OK;
-}
-
-hipEvent_t get_event(vds_ctx c) {
-  if (!c->event_pool.empty()) {
-    hipEvent_t e = c->event_pool.back();
-    c->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  (void)hipEventCreate(&e);
-  return e;
-}
-
-// Times `fn` with an event pair on the context stream when timing is on.
-template <class F>
-void timed(vds_ctx c, int which, double work, F &&fn) {
-  if (!c->timing) {
-    fn();
-    return;
-  }
-  hipEvent_t a = get_event(c), b = get_event(c);
-  (void)hipEventRecord(a, c->stream);
-  fn();
-  (void)hipEventRecord(b, c->stream);
-  c->timers[which].pending.emplace_back(a, b);
-  c->timers[which].pending_work.push_back(work);
+  c->nblk_comb = (int)((p.P * 16 + kRedBlock - 1) / kRedBlock);
 }
 
 void drain_timers(vds_ctx c) {
@@ -191,30 +171,15 @@ void drain_timers(vds_ctx c) {
   }
 }
 
-int64_t ncol_chunks(const vds_ctx c) { return (c->prob.P + 15) / 16; }
-
-// One pair pass over all particle rows with the V operand `V`.
-void pair_pass(vds_ctx c, const float *V, const int *done) {
-  const int64_t nrb = c->ep.Ppad / 16;
-  const double pairs = (double)c->prob.P * (double)c->prob.P;
-  timed(c, VDS_TIMER_PAIR, pairs, [&] {
-    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->QB, nrb, c->KA, V, ncol_chunks(c), c->xc, true, c->part, c->ep.Ppad,
-                     done, c->stream);
-  });
-}
-
 // Prep + pass A + finalize A + pass B + combine(mode).
 void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, const float *qstar, float *out,
               float *out2, const int *done) {
   const EvalParams &e = c->ep;
-  launch_mean_partials(e, q, w, c->meanp, done, c->stream);
-  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, done, c->stream);
-  pair_pass(c, c->VA, done);
-  launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
-  pair_pass(c, c->VB, done);
+  eval_pass_a(c, q, w, done);
+  eval_pass_b(c, done);
   launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, qstar, out, out2, c->redp,
-                 c->ctrl, done, c->stream);
-  if (obs) launch_reduce_final(c->redp, c->nblk, 12, c->redout, done, c->stream);
+                 c->blockmax, done, c->stream);
+  if (obs) launch_reduce_final(c->redp, c->nblk_comb, 12, c->redout, done, c->stream);
 }
 
 vds_status fetch_obs(vds_ctx c, vds_diag *d) {
@@ -322,6 +287,7 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->redp = reinterpret_cast<double *>(c->ws + L.redp);
   c->redout = reinterpret_cast<double *>(c->ws + L.redout);
   c->ctrl = reinterpret_cast<Ctrl *>(c->ws + L.ctrl);
+  c->blockmax = reinterpret_cast<float *>(c->ws + L.blockmax);
   c->qstar = reinterpret_cast<float *>(c->ws + L.qstar);
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
   c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);
@@ -387,7 +353,7 @@ vds_status vds_step(vds_ctx c, float *q, const float *w, int32_t nsteps, vds_dia
         const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
         float *xout = c->xb[m & 1];
         evaluate(c, xin, w, MODE_PICARD, false, c->qstar, xout, nullptr, done);
-        launch_picard_check(c->ctrl, (float)p.picard_rtol, m, c->stream);
+        launch_picard_check(c->ctrl, c->blockmax, c->nblk_comb, (float)p.picard_rtol, m, c->stream);
       }
       st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream), "copy ctrl");
       if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");

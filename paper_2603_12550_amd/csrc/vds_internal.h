@@ -25,11 +25,8 @@ enum { RED_F = 0, RED_DISS = 1, RED_WORK = 2, RED_TAU = 3 };
 struct Ctrl {
   int done;           // set once the iteration has converged
   int conv_iter;      // iteration index (0-based) that converged
-  unsigned resid;     // max |x_new - x_old| as float bits (non-negative floats order as uints)
-  unsigned xmax;      // max |x_new| as float bits
-  float last_resid;   // residual of the last checked iteration
+  float last_resid;   // max |x_new - x_old| of the last checked iteration
   int checked;        // iterations checked so far in this step
-  int pad[2];
 };
 
 // Kernel-side description of one evaluation.
@@ -69,10 +66,10 @@ void launch_finalize_a(const EvalParams &p, const float *partial, int splits, co
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *qstar,
-                    float *out, float *out2, double *redp, Ctrl *ctrl, const int *done, hipStream_t s);
+                    float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s);
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s);
 void launch_qstar(const EvalParams &p, const float *q, float *qstar, hipStream_t s);
-void launch_picard_check(Ctrl *ctrl, float rtol, int iter, hipStream_t s);
+void launch_picard_check(Ctrl *ctrl, const float *blockmax, int nblk, float rtol, int iter, hipStream_t s);
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s);
 void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,

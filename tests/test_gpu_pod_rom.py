@@ -1,0 +1,219 @@
+"""GPU parity of the POD offline phase, the POD maps and the Galerkin reduced
+model against the FP64 oracle, through the C ABI.
+
+Tolerances (float32 GPU vs float64 oracle):
+  Gram matrix: relative Frobenius 1e-6 (FP32 products, fixed-order FP32 split sums).
+  Eigenvalues: relative 1e-4 for lambda_i >= 1e-4 lambda_1 (FP32 Gram, FP64 eigensolve;
+    smaller eigenvalues are below the FP32 Gram's resolution and are not compared).
+  Basis: U^T U = I to 1e-5; the sine of the largest principal angle to the oracle's
+    leading modes <= 1e-3 where the eigen-gap exceeds 1e-3 lambda_1; the discarded
+    energy ||X - U U^T X||_F^2 equals sum_{i > R} lambda_i to 1e-5 of sum lambda.
+  Reduced operators X^H, X^B1, X^B2: relative Frobenius 1e-4; the reduced trajectory
+    and its stress: relative 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import pod as opod
+from oracle import rom as orom
+from oracle import vds as ovds
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2603_12550_amd as pkg
+    return pkg
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(wl.to_f32(a)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_pod_gram_matches_exact_products(lib):
+    rng = np.random.default_rng(0)
+    m, n = 5003, 70
+    X = wl.to_f32(rng.standard_normal((n, m)))          # column-major m x n
+    ctx = lib.Context(1, 10, 0.5, poison=True)
+    G = _np(ctx.pod_gram(_dev(X)))
+    X64 = X.astype(np.float64)
+    assert _rel(G, X64 @ X64.T) < 1e-6
+
+
+def test_pod_basis_recovers_known_factors(lib):
+    rng = np.random.default_rng(1)
+    m, n, R = 3000, 40, 8
+    Q, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    W, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    sig = np.geomspace(10.0, 0.1, n)
+    Xm = Q @ np.diag(sig) @ W.T                         # m x n
+    X32 = wl.to_f32(Xm.T)
+    ctx = lib.Context(1, 1000, 0.5, poison=True)
+    U, eig = ctx.pod_basis(_dev(X32), R)
+    U = _np(U).T                                         # m x R
+    Xr = X32.astype(np.float64).T
+    _, lam_o = opod.pod_basis(Xr, R)
+    big = lam_o >= 1e-4 * lam_o[0]
+    assert np.max(np.abs(eig[big] - lam_o[big]) / lam_o[big]) < 1e-4
+    assert np.abs(U.T @ U - np.eye(R)).max() < 1e-5
+    assert opod.subspace_distance(U, Q[:, :R]) < 1e-3
+
+
+def _gpu_snapshots(lib, cfg, every, count, scheme="implicit"):
+    import torch
+    P, nb = cfg["P"], cfg["nb"]
+    ctx = lib.Context(nb, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme=scheme, poison=True)
+    q = _dev(cfg["q0"])
+    snaps = [q.clone()]
+    for _ in range(count - 1):
+        ctx.step(q, nsteps=every)
+        snaps.append(q.clone())
+    X = torch.stack(snaps).reshape(count * nb, 3 * P).contiguous()   # columns (l, k)
+    return ctx, X, snaps
+
+
+def test_pod_basis_on_vds_snapshots_vs_oracle_svd(lib):
+    cfg = wl.chain4_shear(P=1000, seed=7)
+    _say("POD on chain4 P=1000 snapshots")
+    ctx, X, _ = _gpu_snapshots(lib, cfg, every=10, count=30)
+    R = 20
+    U, eig = ctx.pod_basis(X, R)
+    U = _np(U).T
+    Xr = _np(X).T                                        # m x ncols
+    U_o, lam_o = opod.pod_basis(Xr, R)
+    big = lam_o >= 1e-4 * lam_o[0]
+    assert np.max(np.abs(eig[big] - lam_o[big]) / lam_o[big]) < 1e-4
+    assert np.abs(U.T @ U - np.eye(R)).max() < 1e-5
+    # leading modes separated by a clear gap from the next one
+    gaps = lam_o[:R] - lam_o[1:R + 1]
+    k = max(i + 1 for i in range(R) if gaps[i] > 1e-3 * lam_o[0] and lam_o[i] > 1e-4 * lam_o[0])
+    assert opod.subspace_distance(U[:, :k], U_o[:, :k]) < 1e-3
+    E = Xr - U @ (U.T @ Xr)
+    assert abs((E * E).sum() - lam_o[R:].sum()) < 1e-5 * lam_o.sum()
+
+
+def test_project_and_reconstruct(lib):
+    rng = np.random.default_rng(2)
+    P, nb, R = 700, 3, 25
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, R)))
+    U32 = wl.to_f32(U.T)
+    q32 = wl.to_f32(wl.gaussian_bonds(3, nb, P, 1 / 3))
+    ctx = lib.Context(nb, P, 0.4, poison=True)
+    p = ctx.pod_project(_dev(U32), _dev(q32))
+    Uf = U32.astype(np.float64).T
+    p_o = opod.project(Uf, q32.astype(np.float64))
+    assert _rel(_np(p), p_o) < 1e-6
+    qt = ctx.pod_reconstruct(_dev(U32), p)
+    assert _rel(_np(qt), opod.reconstruct(Uf, _np(p), P)) < 1e-6
+
+
+def _small_rom_case(P=300, R=12, seed=5):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, R)))
+    U32 = wl.to_f32(U.T)
+    q = wl.gaussian_bonds(seed, 3, P, 1 / 3)
+    Uf = U32.astype(np.float64).T
+    p32 = wl.to_f32(opod.project(Uf, wl.f32_as_f64(wl.to_f32(q))))
+    prob = ovds.Problem(nb=3, h=0.5, dt=1e-3, G=wl.shear_gradient(1.0))
+    return U32, Uf, p32, prob
+
+
+def test_rom_operators_small_vs_oracle(lib):
+    P, R = 300, 12
+    U32, Uf, p32, prob = _small_rom_case(P, R)
+    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    rom = lib.Rom(ctx, _dev(U32))
+    XH, XB1, XB2 = (_np(t) for t in rom.operators(_dev(p32)))
+    qt = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    XH_o = orom.hydro(Uf, prob.G, P)
+    XB1_o, XB2_o = orom.brownian(Uf, qt, ovds.uniform_weights(P), prob.h)
+    assert _rel(XH, XH_o) < 1e-5
+    assert _rel(XB1, XB1_o) < 1e-4
+    assert _rel(XB2, XB2_o) < 1e-4
+
+
+def test_rom_run_small_vs_oracle(lib):
+    P, R = 300, 12
+    U32, Uf, p32, prob = _small_rom_case(P, R, seed=6)
+    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    rom = lib.Rom(ctx, _dev(U32))
+    p = _dev(p32)
+    tau = rom.run(p, nsteps=30, freeze_every=10)
+    q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    w = ovds.uniform_weights(P)
+    p_o = orom.rom_run(Uf, q0, w, prob, 30, 10)
+    assert _rel(_np(p), p_o) < 1e-4
+    tau_o = orom.reduced_stress(Uf, p_o, w, prob, P)
+    assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
+
+
+def test_full_rank_rom_equals_full_explicit_scheme(lib):
+    # R = P d with an orthogonal U and a freeze every step: the reduced model is the
+    # full explicit scheme in another basis (Section 2.4 approximations are exact)
+    P = 40
+    rng = np.random.default_rng(8)
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, 3 * P)))
+    U32 = wl.to_f32(U.T)
+    Uf = U32.astype(np.float64).T
+    cfg = wl.dumbbell_shear(P=P, seed=9)
+    q32 = wl.to_f32(cfg["q0"])
+    ctx = lib.Context(1, P, 0.5, G=cfg["G"], dt=1e-3, scheme="explicit", poison=True)
+    rom = lib.Rom(ctx, _dev(U32))
+    p = ctx.pod_project(_dev(U32), _dev(q32))
+    rom.run(p, nsteps=5, freeze_every=1)
+    qg = _dev(q32)
+    ctx.step(qg, nsteps=5)
+    assert _rel(_np(ctx.pod_reconstruct(_dev(U32), p)), _np(qg)) < 1e-4
+
+
+def test_rom_operators_match_projected_kernel_terms_full_size(lib):
+    # chain4 at P = 20000 with a POD basis of rank 180: at q~ = U p the frozen
+    # operators reproduce the projected kernel terms exactly,
+    # X^B1 p_j = U^T term1_j(q~), X^B2 p_j = U^T term2_j(q~), X^H p_j = U^T (G q~_j)
+    import torch
+    cfg = wl.chain4_shear()
+    _say("POD basis chain4 P=20000, 61 snapshots")
+    ctx, X, snaps = _gpu_snapshots(lib, cfg, every=1, count=61)
+    R = 180
+    U, eig = ctx.pod_basis(X, R)
+    p = ctx.pod_project(U, snaps[0])
+    qt = ctx.pod_reconstruct(U, p)
+    _say("reduced operators chain4 P=20000 R=180")
+    rom = lib.Rom(ctx, U)
+    XH, XB1, XB2 = (_np(t) for t in rom.operators(p))
+    S, t1, t2 = ctx.pair_sums(qt)
+    Un = _np(U)                                   # R x m
+    pn = _np(p)
+    t1n, t2n, qtn = _np(t1), _np(t2), _np(qt)
+    G = cfg["G"]
+    for j in range(3):
+        lhs1 = XB1 @ pn[j]
+        rhs1 = Un @ t1n[j].reshape(-1)
+        lhs2 = XB2 @ pn[j]
+        rhs2 = Un @ t2n[j].reshape(-1)
+        lhsH = XH @ pn[j]
+        rhsH = Un @ (qtn[j] @ G.T).reshape(-1)
+        assert _rel(lhs1, rhs1) < 1e-4, j
+        assert _rel(lhs2, rhs2) < 1e-4, j
+        assert _rel(lhsH, rhsH) < 1e-4, j
+    assert np.abs(Un @ Un.T - np.eye(R)).max() < 1e-4
