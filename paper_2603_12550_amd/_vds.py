@@ -88,6 +88,19 @@ _sigs.update({
     "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_stress": ([_P, _P, C.POINTER(C.c_double)], C.c_int),
 })
+_sigs.update({
+    "vds_batch_workspace_bytes": ([C.c_int32, C.POINTER(C.c_int64), C.c_int32], C.c_size_t),
+    "vds_batch_create": ([C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                          C.POINTER(vds_problem), C.POINTER(C.c_double), _P, C.POINTER(_P)], C.c_int),
+    "vds_batch_bind_workspace": ([_P, _P, C.c_size_t], C.c_int),
+    "vds_batch_destroy": ([_P], None),
+    "vds_batch_last_error": ([_P], C.c_char_p),
+    "vds_batch_state_offset": ([_P, C.c_int32], C.c_int64),
+    "vds_batch_set_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "vds_batch_get_tuning": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "vds_batch_autotune": ([_P, _P], C.c_int),
+    "vds_batch_step": ([_P, _P, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+})
 for _name, (_args, _ret) in _sigs.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -294,6 +307,69 @@ class Rom:
         tau = (C.c_double * 9)()
         _check(_lib.vds_rom_stress(self.rom, _ptr(p), tau), self.ctx.ctx)
         return np.array(tau[:]).reshape(3, 3)
+
+
+def _bcheck(status, b=None):
+    if status != VDS_OK:
+        msg = _lib.vds_batch_last_error(b)
+        raise VDSError(status, msg.decode() if msg else "")
+
+
+class Batch:
+    """Independent ensembles advanced together (include/vds_batch.h); the state
+    is one packed float32 device tensor of the ensembles' [nb][P_b][3] blocks."""
+
+    def __init__(self, P, h, G, nb=3, H=None, kT=1.0, zeta=4.0, n=1.0, dt=1e-3, potential="hookean", b_max=0.0,
+                 stream=None, device="cuda", poison=False):
+        self.P = np.asarray(P, dtype=np.int64)
+        self.nens, self.nb = len(self.P), int(nb)
+        self.device = torch.device(device)
+        Parr = (C.c_int64 * self.nens)(*[int(v) for v in self.P])
+        harr = (C.c_double * self.nens)(*[float(v) for v in np.asarray(h, dtype=np.float64)])
+        Garr = (C.c_double * (9 * self.nens))(*[float(v) for v in np.asarray(G, dtype=np.float64).reshape(-1)])
+        H = np.ones(self.nb) if H is None else np.asarray(H, dtype=np.float64)
+        Harr = (C.c_double * self.nb)(*[float(v) for v in H])
+        common = make_problem(nb, 1, 1.0, dt=dt, kT=kT, zeta=zeta, n=n, potential=potential, b_max=b_max,
+                              scheme="explicit")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = C.c_void_p()
+        _bcheck(_lib.vds_batch_create(self.nens, Parr, harr, Garr, C.byref(common), Harr,
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(b)))
+        self.b = b
+        nbytes = _lib.vds_batch_workspace_bytes(self.nens, Parr, self.nb)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if poison:
+            self.ws.fill_(255)
+        _bcheck(_lib.vds_batch_bind_workspace(self.b, _ptr(self.ws), nbytes), self.b)
+        self.offsets = [int(_lib.vds_batch_state_offset(self.b, e)) for e in range(self.nens + 1)]
+
+    def __del__(self):
+        if getattr(self, "b", None):
+            _lib.vds_batch_destroy(self.b)
+            self.b = None
+
+    def pack(self, states):
+        return torch.cat([s.reshape(-1) for s in states]).contiguous()
+
+    def unpack(self, q):
+        return [q[self.offsets[e]:self.offsets[e + 1]].reshape(self.nb, int(self.P[e]), 3) for e in range(self.nens)]
+
+    def set_tuning(self, rows_per_wave=2, grid=1024, use_graph=True):
+        _bcheck(_lib.vds_batch_set_tuning(self.b, int(rows_per_wave), int(grid), 1 if use_graph else 0), self.b)
+
+    def get_tuning(self):
+        rb, g, u = C.c_int32(), C.c_int32(), C.c_int32()
+        _bcheck(_lib.vds_batch_get_tuning(self.b, C.byref(rb), C.byref(g), C.byref(u)), self.b)
+        return dict(rows_per_wave=rb.value, grid=g.value, use_graph=u.value)
+
+    def autotune(self, q):
+        _bcheck(_lib.vds_batch_autotune(self.b, _ptr(q)), self.b)
+        return self.get_tuning()
+
+    def step(self, q, nsteps=1, stress=False):
+        tau = (C.c_double * (9 * self.nens))() if stress else None
+        _bcheck(_lib.vds_batch_step(self.b, _ptr(q), int(nsteps), tau), self.b)
+        return np.array(tau[:]).reshape(self.nens, 3, 3) if stress else None
 
 
 # C names, re-exported for callers who drive the ABI directly

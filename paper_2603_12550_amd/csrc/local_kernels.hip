@@ -41,12 +41,12 @@ __device__ inline int64_t v_index(int64_t J, int n) {
 }
 
 // Partial sums of w_I x_I (FP64) per block, for the weighted centring.
-__global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const float *__restrict__ q,
-                                                             const float *__restrict__ w, double *__restrict__ meanp,
-                                                             const int *__restrict__ done) {
+// Bodies take the block index `lb` within the problem (one ensemble) so that
+// the batched step can run them per ensemble.
+__device__ void mean_partials_body(const EvalParams &p, int64_t lb, const float *__restrict__ q,
+                                   const float *__restrict__ w, double *__restrict__ meanp) {
   __shared__ double sm[kMaxD][kRedBlock];
-  if (done != nullptr && *done) return;
-  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  const int64_t I = lb * kRedBlock + threadIdx.x;
   double v[kMaxD];
   const double wi = I < p.P ? (double)load_weight(w, I, p.uniform_w) : 0.0;
 #pragma unroll
@@ -55,7 +55,14 @@ __global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const
     v[a] = (I < p.P && a < p.D) ? wi * (double)q[((int64_t)k * p.P + I) * 3 + al] : 0.0;
   }
   block_sum<kMaxD>(v, sm);
-  if (threadIdx.x < kMaxD) meanp[(int64_t)blockIdx.x * 16 + threadIdx.x] = v[threadIdx.x];
+  if (threadIdx.x < kMaxD) meanp[lb * 16 + threadIdx.x] = v[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const float *__restrict__ q,
+                                                             const float *__restrict__ w, double *__restrict__ meanp,
+                                                             const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  mean_partials_body(p, blockIdx.x, q, w, meanp);
 }
 
 // Sum of the centring partials, computed identically by every block.
@@ -73,7 +80,7 @@ __device__ void load_mean(const EvalParams &p, const double *meanp, int nmeanp, 
 // of a wave cover four particles' contiguous records and P/16 blocks fill the
 // chip.  Cross-component terms (norms, the 3x3 flow, bond neighbours) are
 // 16-wide shuffles.
-__device__ inline int64_t group_particle() { return ((int64_t)blockIdx.x * kRedBlock + threadIdx.x) >> 4; }
+__device__ inline int64_t group_particle(int64_t lb) { return (lb * kRedBlock + threadIdx.x) >> 4; }
 __device__ inline int group_lane() { return threadIdx.x & 15; }
 __device__ inline float gshfl(float v, int n) { return __shfl(v, n, 16); }
 __device__ inline double gshfl(double v, int n) { return __shfl(v, n, 16); }
@@ -84,15 +91,13 @@ __device__ inline float gsum(float v) {
 }
 
 // Centre, pack Q/K operands and the pass-A V operand (weights w).
-__global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *__restrict__ q,
-                                                    const float *__restrict__ w, const double *__restrict__ meanp,
-                                                    int nmeanp, float *__restrict__ xc, float *__restrict__ wv,
-                                                    float *__restrict__ QB, float *__restrict__ KA,
-                                                    float *__restrict__ VA, const int *__restrict__ done) {
+__device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
+                          const double *__restrict__ meanp, int nmeanp, float *__restrict__ xc,
+                          float *__restrict__ wv, float *__restrict__ QB, float *__restrict__ KA,
+                          float *__restrict__ VA) {
   __shared__ float mean_sh[kMaxD];
-  if (done != nullptr && *done) return;
   load_mean(p, meanp, nmeanp, mean_sh);
-  const int64_t I = group_particle();
+  const int64_t I = group_particle(lb);
   const int n = group_lane();
   if (I >= p.Ppad) return;
   const bool real = I < p.P;
@@ -124,6 +129,15 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
   VA[v_index(I, n)] = v;
 }
 
+__global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *__restrict__ q,
+                                                    const float *__restrict__ w, const double *__restrict__ meanp,
+                                                    int nmeanp, float *__restrict__ xc, float *__restrict__ wv,
+                                                    float *__restrict__ QB, float *__restrict__ KA,
+                                                    float *__restrict__ VA, const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA);
+}
+
 // Component n of row I summed over the column splits, in FP64.
 __device__ inline double sum_splits(const EvalParams &p, const float *__restrict__ partial, int splits, int64_t I,
                                     int n) {
@@ -135,12 +149,10 @@ __device__ inline double sum_splits(const EvalParams &p, const float *__restrict
 // Pass-A finalisation: S_I = w_I + sum_{J != I} w_J e_IJ,
 // term1_I = -(1/h^2) sum_J w_J e_IJ (x_I - x_J) / S_I, and the pass-B operand
 // with weights w_J / S_J.
-__global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, int splits,
-                                                          const float *__restrict__ xc, const float *__restrict__ wv,
-                                                          float *__restrict__ S, float *__restrict__ t1,
-                                                          float *__restrict__ VB, const int *__restrict__ done) {
-  if (done != nullptr && *done) return;
-  const int64_t I = group_particle();
+__device__ void finalize_a_body(const EvalParams &p, int64_t lb, const float *__restrict__ partial, int splits,
+                                const float *__restrict__ xc, const float *__restrict__ wv, float *__restrict__ S,
+                                float *__restrict__ t1, float *__restrict__ VB) {
+  const int64_t I = group_particle(lb);
   const int n = group_lane();
   if (I >= p.Ppad) return;
   if (I >= p.P) {  // padding columns carry zero weight in pass B too
@@ -162,20 +174,25 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const fl
   VB[v_index(I, n)] = v;
 }
 
+__global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, int splits,
+                                                          const float *__restrict__ xc, const float *__restrict__ wv,
+                                                          float *__restrict__ S, float *__restrict__ t1,
+                                                          float *__restrict__ VB, const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  finalize_a_body(p, blockIdx.x, partial, splits, xc, wv, S, t1, VB);
+}
+
 // Pass-B finalisation and everything local: term2, b = term1 + term2,
 // g = kT b + grad Psi, u = -(1/zeta)(A (x) I) g, flow G q, and by mode the
 // terms, the velocity, an explicit update or a fixed-point update.  With `obs`
 // it also accumulates F_h, dissipation, work and stress in FP64.
-__global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, int obs,
-                                                       const float *__restrict__ partial, int splits,
-                                                       const float *__restrict__ xc, const float *__restrict__ t1,
-                                                       const float *__restrict__ S, const float *__restrict__ wv,
-                                                       const float *qin, const float *__restrict__ qstar,
-                                                       float *out, float *out2, double *__restrict__ redp,
-                                                       float *__restrict__ blockmax, const int *__restrict__ done) {
+__device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs, const float *__restrict__ partial,
+                             int splits, const float *__restrict__ xc, const float *__restrict__ t1,
+                             const float *__restrict__ S, const float *__restrict__ wv, const float *qin,
+                             const float *__restrict__ qstar, float *out, float *out2, double *__restrict__ redp,
+                             float *__restrict__ blockmax) {
   __shared__ double sm[12][kRedBlock];
-  if (done != nullptr && *done) return;
-  const int64_t I = group_particle();
+  const int64_t I = group_particle(lb);
   const int n = group_lane();
   const bool real = I < p.P;          // uniform over the 16 lanes of a particle
   const bool comp = real && n < p.D;  // this lane owns a component
@@ -247,7 +264,7 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
   }
   if (obs) {
     block_sum<12>(red, sm);
-    if (threadIdx.x < 12) redp[(int64_t)blockIdx.x * 16 + threadIdx.x] = red[threadIdx.x];
+    if (threadIdx.x < 12) redp[lb * 16 + threadIdx.x] = red[threadIdx.x];
   }
   if (mode == MODE_PICARD) {
     // block maxima of |dx| and |x| into per-block slots; the check kernel
@@ -268,10 +285,21 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
         r = fmaxf(r, smax[0][i]);
         x = fmaxf(x, smax[1][i]);
       }
-      blockmax[2 * blockIdx.x] = r;
-      blockmax[2 * blockIdx.x + 1] = x;
+      blockmax[2 * lb] = r;
+      blockmax[2 * lb + 1] = x;
     }
   }
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, int obs,
+                                                       const float *__restrict__ partial, int splits,
+                                                       const float *__restrict__ xc, const float *__restrict__ t1,
+                                                       const float *__restrict__ S, const float *__restrict__ wv,
+                                                       const float *qin, const float *__restrict__ qstar,
+                                                       float *out, float *out2, double *__restrict__ redp,
+                                                       float *__restrict__ blockmax, const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qstar, out, out2, redp, blockmax);
 }
 
 __global__ void k_reduce_final(const double *__restrict__ redp, int nblk, int nslots, double *__restrict__ out,
@@ -333,10 +361,10 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
   ctrl->checked = 0;
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_stress(EvalParams p, const float *__restrict__ q,
-                                                      const float *__restrict__ w, double *__restrict__ redp) {
+__device__ void stress_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
+                            double *__restrict__ redp) {
   __shared__ double sm[9][kRedBlock];
-  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  const int64_t I = lb * kRedBlock + threadIdx.x;
   double t[9];
 #pragma unroll
   for (int s = 0; s < 9; ++s) t[s] = 0.0;
@@ -353,7 +381,12 @@ __global__ __launch_bounds__(kRedBlock) void k_stress(EvalParams p, const float 
     }
   }
   block_sum<9>(t, sm);
-  if (threadIdx.x < 9) redp[(int64_t)blockIdx.x * 16 + threadIdx.x] = t[threadIdx.x];
+  if (threadIdx.x < 9) redp[lb * 16 + threadIdx.x] = t[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_stress(EvalParams p, const float *__restrict__ q,
+                                                      const float *__restrict__ w, double *__restrict__ redp) {
+  stress_body(p, blockIdx.x, q, w, redp);
 }
 
 // Foreign rows y[ny][D] (particle-major) as Q operands, centred like the particles.
@@ -389,6 +422,62 @@ __global__ __launch_bounds__(kRedBlock) void k_density_out(const float *__restri
   float s = 0.f;
   for (int sp = 0; sp < splits; ++sp) s += partial[((int64_t)sp * stride_rows + I) * 16 + D];
   f[I] = s * norm;
+}
+
+// ---- batched ensembles: the same bodies, per ensemble ----
+
+__global__ __launch_bounds__(kRedBlock) void k_batch_mean(BatchView b, const float *__restrict__ q,
+                                                          double *__restrict__ meanp) {
+  const EnsDesc &d = b.ens[b.blk256_ens[blockIdx.x]];
+  mean_partials_body(d.p, blockIdx.x - d.blk256, q + d.q_off, nullptr, meanp + (int64_t)d.blk256 * 16);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_batch_prep(BatchView b, const float *__restrict__ q,
+                                                          const double *__restrict__ meanp, float *__restrict__ xc,
+                                                          float *__restrict__ wv, float *__restrict__ QB,
+                                                          float *__restrict__ KA, float *__restrict__ VA) {
+  const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
+  const int64_t o = d.pad_off;
+  prep_body(d.p, blockIdx.x - d.blk16, q + d.q_off, nullptr, meanp + (int64_t)d.blk256 * 16,
+            (int)(d.p.Ppad / kRedBlock), xc + o * b.D, wv + o, QB + o * b.KK * 4, KA + o * b.KK * 4, VA + o * 16);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_batch_finalize_a(BatchView b, const float *__restrict__ partial,
+                                                                const float *__restrict__ xc,
+                                                                const float *__restrict__ wv, float *__restrict__ S,
+                                                                float *__restrict__ t1, float *__restrict__ VB) {
+  const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
+  const int64_t o = d.pad_off;
+  finalize_a_body(d.p, blockIdx.x - d.blk16, partial + o * 16, 1, xc + o * b.D, wv + o, S + o, t1 + o * b.D,
+                  VB + o * 16);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_batch_explicit(BatchView b, const float *__restrict__ partial,
+                                                              const float *__restrict__ xc,
+                                                              const float *__restrict__ t1,
+                                                              const float *__restrict__ S,
+                                                              const float *__restrict__ wv, float *q) {
+  const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
+  const int64_t o = d.pad_off;
+  combine_body(d.p, blockIdx.x - d.blk16, MODE_EXPLICIT, 0, partial + o * 16, 1, xc + o * b.D, t1 + o * b.D, S + o,
+               wv + o, q + d.q_off, nullptr, q + d.q_off, nullptr, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_batch_stress(BatchView b, const float *__restrict__ q,
+                                                            double *__restrict__ redp) {
+  const EnsDesc &d = b.ens[b.blk256_ens[blockIdx.x]];
+  stress_body(d.p, blockIdx.x - d.blk256, q + d.q_off, nullptr, redp + (int64_t)d.blk256 * 16);
+}
+
+__global__ void k_batch_stress_sum(const EnsDesc *__restrict__ ens, const double *__restrict__ redp,
+                                   double *__restrict__ tau) {
+  const EnsDesc &d = ens[blockIdx.x];
+  const int s = threadIdx.x;
+  if (s >= 9) return;
+  const int nb = (int)(d.p.Ppad / kRedBlock);
+  double acc = 0.0;
+  for (int i = 0; i < nb; ++i) acc += redp[((int64_t)d.blk256 + i) * 16 + s];
+  tau[(int64_t)blockIdx.x * 9 + s] = acc;
 }
 
 // ---- launchers ----
@@ -435,6 +524,28 @@ void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const 
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm, float *f,
                         hipStream_t s) {
   k_density_out<<<nblocks(ny), kRedBlock, 0, s>>>(partial, splits, p.Ppad, ny, p.D, norm, f);
+}
+
+void launch_batch_mean(const BatchView &b, const float *q, double *meanp, hipStream_t s) {
+  k_batch_mean<<<b.nblk256, kRedBlock, 0, s>>>(b, q, meanp);
+}
+void launch_batch_prep(const BatchView &b, const float *q, const double *meanp, float *xc, float *wv, float *QB,
+                       float *KA, float *VA, hipStream_t s) {
+  k_batch_prep<<<b.nblk16, kRedBlock, 0, s>>>(b, q, meanp, xc, wv, QB, KA, VA);
+}
+void launch_batch_finalize_a(const BatchView &b, const float *partial, const float *xc, const float *wv, float *S,
+                             float *t1, float *VB, hipStream_t s) {
+  k_batch_finalize_a<<<b.nblk16, kRedBlock, 0, s>>>(b, partial, xc, wv, S, t1, VB);
+}
+void launch_batch_explicit(const BatchView &b, const float *partial, const float *xc, const float *t1,
+                           const float *S, const float *wv, float *q, hipStream_t s) {
+  k_batch_explicit<<<b.nblk16, kRedBlock, 0, s>>>(b, partial, xc, t1, S, wv, q);
+}
+void launch_batch_stress(const BatchView &b, const float *q, double *redp, hipStream_t s) {
+  k_batch_stress<<<b.nblk256, kRedBlock, 0, s>>>(b, q, redp);
+}
+void launch_batch_stress_sum(const EnsDesc *ens, int nens, const double *redp, double *tau, hipStream_t s) {
+  k_batch_stress_sum<<<nens, 64, 0, s>>>(ens, redp, tau);
 }
 
 __global__ void k_copy(const float *__restrict__ src, float *__restrict__ dst, int64_t n) {

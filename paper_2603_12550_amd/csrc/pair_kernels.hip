@@ -43,21 +43,14 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFlush = 8;  // chunks per FP32 accumulation group
 
+// One wavefront: row blocks rb0 .. rb0 + RB - 1 against column chunks [c0, c1),
+// results into out[row][16].  No barriers: waves are independent.
 template <int KK, int RB>
-__global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB, int nrow_blocks,
-                                                   const float *__restrict__ KA, const float4 *__restrict__ VB,
-                                                   int ncol_chunks, int chunks_per_split,
-                                                   const float *__restrict__ xc, int D, int exclude_self,
-                                                   float *__restrict__ partial, int64_t part_stride_rows,
-                                                   const int *__restrict__ done) {
-  if (done != nullptr && *done) return;
+__device__ void pair_rows(const float *__restrict__ QB, int nrow_blocks, const float *__restrict__ KA,
+                          const float4 *__restrict__ VB, int c0, int c1, const float *__restrict__ xc, int D,
+                          int exclude_self, float *__restrict__ out, int rb0) {
+  if (rb0 >= nrow_blocks) return;
   const int lane = threadIdx.x & 63;
-  // wave index as a scalar so that row-block tests compile to scalar branches
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rb0 = ((int)blockIdx.x * 4 + wave) * RB;
-  if (rb0 >= nrow_blocks) return;  // no barriers below: a wave may leave alone
-  const int c0 = (int)blockIdx.y * chunks_per_split;
-  const int c1 = min(ncol_chunks, c0 + chunks_per_split);
   // position of the self pair inside a diagonal 16x16 tile, per element i
   const int diag_i = (lane & 15) - 4 * (lane >> 4);  // in 0..3 when this lane holds one
 
@@ -131,7 +124,6 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
   // the weighted kernel sum O[.][D] sits in lane (lane & 48) + D
   const int n = lane & 15;
   const int src = (lane & 48) + D;
-  float *out = partial + (int64_t)blockIdx.y * part_stride_rows * 16;
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     if (rb0 + r >= nrow_blocks) break;
@@ -144,6 +136,45 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
       else if (n == D) v = s;
       out[row * 16 + n] = (float)v;
     }
+  }
+}
+
+template <int KK, int RB>
+__global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB, int nrow_blocks,
+                                                   const float *__restrict__ KA, const float4 *__restrict__ VB,
+                                                   int ncol_chunks, int chunks_per_split,
+                                                   const float *__restrict__ xc, int D, int exclude_self,
+                                                   float *__restrict__ partial, int64_t part_stride_rows,
+                                                   const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  // wave index as a scalar so that row-block tests compile to scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rb0 = ((int)blockIdx.x * 4 + wave) * RB;
+  const int c0 = (int)blockIdx.y * chunks_per_split;
+  const int c1 = min(ncol_chunks, c0 + chunks_per_split);
+  pair_rows<KK, RB>(QB, nrow_blocks, KA, VB, c0, c1, xc, D, exclude_self,
+                    partial + (int64_t)blockIdx.y * part_stride_rows * 16, rb0);
+}
+
+// Batched ensembles: a persistent grid walks a static list of (ensemble, row
+// tile) items, sorted by decreasing cost, each over all of its ensemble's
+// columns (one split).  Operands of ensemble e start at padded particle
+// ens[e].pad_off of the concatenated arrays.
+template <int KK, int RB>
+__global__ __launch_bounds__(256) void k_batch_pair(const int2 *__restrict__ items, int nitems,
+                                                    const EnsDesc *__restrict__ ens, const float *__restrict__ QB,
+                                                    const float *__restrict__ KA, const float4 *__restrict__ VB,
+                                                    const float *__restrict__ xc, int D, float *__restrict__ partial) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 item = items[it];
+    const int64_t off = ens[item.x].pad_off;
+    const int64_t P = ens[item.x].p.P;
+    const int nrb = (int)(ens[item.x].p.Ppad / 16);
+    const int ncc = (int)((P + 15) / 16);
+    const int rb0 = (item.y * 4 + wave) * RB;
+    pair_rows<KK, RB>(QB + off * KK * 4, nrb, KA + off * KK * 4, VB + off * 4, 0, ncc, xc + off * D, D, 1,
+                      partial + off * 16, rb0);
   }
 }
 
@@ -231,6 +262,28 @@ __global__ __launch_bounds__(256) void k_pair_valu(const float *__restrict__ QB,
 #pragma unroll
     for (int n = 0; n < D; ++n) out[rows[r] * 16 + n] = (float)((double)q[r][n] * s - tot[r][n]);
     out[rows[r] * 16 + D] = (float)s;
+  }
+}
+
+template <int KK>
+static void launch_batch_kk(int rb, int grid, const int2 *items, int nitems, const EnsDesc *ens, const float *QB,
+                            const float *KA, const float *VB, const float *xc, int D, float *partial, hipStream_t s) {
+  const float4 *vb = reinterpret_cast<const float4 *>(VB);
+  switch (rb) {
+    case 1: k_batch_pair<KK, 1><<<grid, 256, 0, s>>>(items, nitems, ens, QB, KA, vb, xc, D, partial); break;
+    case 2: k_batch_pair<KK, 2><<<grid, 256, 0, s>>>(items, nitems, ens, QB, KA, vb, xc, D, partial); break;
+    default: k_batch_pair<KK, 4><<<grid, 256, 0, s>>>(items, nitems, ens, QB, KA, vb, xc, D, partial); break;
+  }
+}
+
+void launch_batch_pair(int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
+                       const float *QB, const float *KA, const float *VB, const float *xc, float *partial,
+                       hipStream_t s) {
+  switch (KK) {
+    case 2: launch_batch_kk<2>(rb, grid, items, nitems, ens, QB, KA, VB, xc, D, partial, s); break;
+    case 3: launch_batch_kk<3>(rb, grid, items, nitems, ens, QB, KA, VB, xc, D, partial, s); break;
+    case 4: launch_batch_kk<4>(rb, grid, items, nitems, ens, QB, KA, VB, xc, D, partial, s); break;
+    default: launch_batch_kk<5>(rb, grid, items, nitems, ens, QB, KA, VB, xc, D, partial, s); break;
   }
 }
 

@@ -45,6 +45,17 @@ struct EvalParams {
   float log_norm;     // (D/2) log(2 pi h^2)
 };
 
+// One ensemble of a batch: its problem parameters and where its particles sit
+// in the concatenated arrays.  Every ensemble is padded to a multiple of
+// kRowAlign particles, so each 16- or 256-particle block belongs to one ensemble.
+struct EnsDesc {
+  EvalParams p;
+  int64_t pad_off;  // first padded particle in the operand arrays
+  int64_t q_off;    // first float of the ensemble's state [nb][P][3] in the packed state
+  int blk16;        // first 16-particle block of the ensemble
+  int blk256;       // first 256-particle block of the ensemble
+};
+
 // Modes of the combine kernel.
 enum CombineMode { MODE_TERMS = 0, MODE_VELOCITY = 1, MODE_EXPLICIT = 2, MODE_PICARD = 3, MODE_OBS_ONLY = 4 };
 
@@ -57,6 +68,11 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
                       float *partial,
                       int64_t part_stride_rows, const int *done, hipStream_t s);
 bool pair_shape_ok(const vds_tuning &t, int D);
+// Batched pair pass over the (ensemble, row tile) work list `items` with a
+// persistent grid of `grid` workgroups; rb = row blocks per wavefront.
+void launch_batch_pair(int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
+                       const float *QB, const float *KA, const float *VB, const float *xc, float *partial,
+                       hipStream_t s);
 
 // ---- launchers (local_kernels.hip) ----
 void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done, hipStream_t s);
@@ -77,6 +93,26 @@ void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const 
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm,
                         float *f, hipStream_t s);
 void launch_copy(const float *src, float *dst, int64_t n, const int *done_flag_or_null, hipStream_t s);
+
+// ---- batched per-particle kernels (local_kernels.hip) ----
+// Block tables: blk16_ens[b] / blk256_ens[b] = ensemble of 16- / 256-particle block b.
+struct BatchView {
+  const EnsDesc *ens;
+  const int *blk16_ens;
+  const int *blk256_ens;
+  int nblk16, nblk256;  // total blocks over all ensembles (padded particles)
+  int D, KK;
+};
+void launch_batch_mean(const BatchView &b, const float *q, double *meanp, hipStream_t s);
+void launch_batch_prep(const BatchView &b, const float *q, const double *meanp, float *xc, float *wv, float *QB,
+                       float *KA, float *VA, hipStream_t s);
+void launch_batch_finalize_a(const BatchView &b, const float *partial, const float *xc, const float *wv, float *S,
+                             float *t1, float *VB, hipStream_t s);
+void launch_batch_explicit(const BatchView &b, const float *partial, const float *xc, const float *t1,
+                           const float *S, const float *wv, float *q, hipStream_t s);
+void launch_batch_stress(const BatchView &b, const float *q, double *redp, hipStream_t s);
+// tau[e][9] = sum of the stress block partials of ensemble e (one block per ensemble).
+void launch_batch_stress_sum(const EnsDesc *ens, int nens, const double *redp, double *tau, hipStream_t s);
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
