@@ -101,6 +101,32 @@ _sigs.update({
     "vds_batch_autotune": ([_P, _P], C.c_int),
     "vds_batch_step": ([_P, _P, C.c_int32, C.POINTER(C.c_double)], C.c_int),
 })
+class vds_mlp_rollout(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("checks", C.c_int32), ("fallbacks", C.c_int32), ("reserved", C.c_int32),
+                ("max_resid", C.c_double), ("max_energy_gap", C.c_double), ("tau", C.c_double * 9)]
+
+
+_sigs.update({
+    "vds_mlp_workspace_bytes": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_size_t),
+    "vds_mlp_create": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(_P)], C.c_int),
+    "vds_mlp_bind_workspace": ([_P, _P, C.c_size_t], C.c_int),
+    "vds_mlp_destroy": ([_P], None),
+    "vds_mlp_last_error": ([_P], C.c_char_p),
+    "vds_mlp_param_count": ([_P], C.c_int64),
+    "vds_mlp_set_params": ([_P, _P], C.c_int),
+    "vds_mlp_get_params": ([_P, _P], C.c_int),
+    "vds_mlp_get_grads": ([_P, _P], C.c_int),
+    "vds_mlp_forward": ([_P, _P, C.c_int32, _P, C.c_int32], C.c_int),
+    "vds_mlp_loss_grad": ([_P, _P, _P, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "vds_mlp_adam_step": ([_P, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+    "vds_mlp_train_epoch": ([_P, _P, _P, C.c_int32, C.c_int32, C.c_float, _P, C.POINTER(C.c_double)], C.c_int),
+    "vds_mlp_set_scaling": ([_P, _P, _P, _P, _P], C.c_int),
+    "vds_mlp_fit_scaling": ([_P, _P, _P, C.c_int32], C.c_int),
+    "vds_mlp_make_pairs": ([_P, _P, C.c_int32, C.c_float, _P, _P], C.c_int),
+    "vds_mlp_rollout_workspace_bytes": ([C.POINTER(vds_problem), C.c_int32], C.c_size_t),
+    "vds_mlp_rollout_run": ([_P, _P, _P, C.c_int32, _P, C.c_float, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                             _P, C.c_size_t, C.POINTER(vds_mlp_rollout)], C.c_int),
+})
 for _name, (_args, _ret) in _sigs.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -370,6 +396,91 @@ class Batch:
         tau = (C.c_double * (9 * self.nens))() if stress else None
         _bcheck(_lib.vds_batch_step(self.b, _ptr(q), int(nsteps), tau), self.b)
         return np.array(tau[:]).reshape(self.nens, 3, 3) if stress else None
+
+
+def _mcheck(status, m=None):
+    if status != VDS_OK:
+        msg = _lib.vds_mlp_last_error(m)
+        raise VDSError(status, msg.decode() if msg else "")
+
+
+class Mlp:
+    """Learned reduced step (include/vds_mlp.h): nin -> width -> width -> nout, SiLU."""
+
+    def __init__(self, nin, width, nout, max_batch, stream=None, device="cuda"):
+        self.nin, self.width, self.nout, self.max_batch = int(nin), int(width), int(nout), int(max_batch)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _mcheck(_lib.vds_mlp_create(self.nin, self.width, self.nout, self.max_batch,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.m = h
+        n = _lib.vds_mlp_workspace_bytes(self.nin, self.width, self.nout, self.max_batch)
+        self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _mcheck(_lib.vds_mlp_bind_workspace(self.m, _ptr(self.ws), n), self.m)
+        self.nparams = int(_lib.vds_mlp_param_count(self.m))
+
+    def __del__(self):
+        if getattr(self, "m", None):
+            _lib.vds_mlp_destroy(self.m)
+            self.m = None
+
+    def set_params(self, flat):
+        _mcheck(_lib.vds_mlp_set_params(self.m, _ptr(flat.contiguous())), self.m)
+
+    def get_params(self):
+        out = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _mcheck(_lib.vds_mlp_get_params(self.m, _ptr(out)), self.m)
+        return out
+
+    def get_grads(self):
+        out = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _mcheck(_lib.vds_mlp_get_grads(self.m, _ptr(out)), self.m)
+        return out
+
+    def forward(self, X, bf16=False):
+        Y = torch.empty((X.shape[0], self.nout), dtype=torch.float32, device=self.device)
+        _mcheck(_lib.vds_mlp_forward(self.m, _ptr(X), int(X.shape[0]), _ptr(Y), 1 if bf16 else 0), self.m)
+        return Y
+
+    def loss_grad(self, X, T):
+        loss = C.c_double()
+        _mcheck(_lib.vds_mlp_loss_grad(self.m, _ptr(X), _ptr(T), int(X.shape[0]), C.byref(loss)), self.m)
+        return loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _mcheck(_lib.vds_mlp_adam_step(self.m, float(lr), float(beta1), float(beta2), float(eps)), self.m)
+
+    def train_epoch(self, X, T, batch, lr, order=None):
+        loss = C.c_double()
+        _mcheck(_lib.vds_mlp_train_epoch(self.m, _ptr(X), _ptr(T), int(X.shape[0]), int(batch), float(lr),
+                                         _ptr(order), C.byref(loss)), self.m)
+        return loss.value
+
+    def fit_scaling(self, X, T):
+        _mcheck(_lib.vds_mlp_fit_scaling(self.m, _ptr(X), _ptr(T), int(X.shape[0])), self.m)
+
+    def make_pairs(self, traj, log_rate):
+        nt = int(traj.shape[0])
+        X = torch.empty((nt - 1, self.nin), dtype=torch.float32, device=self.device)
+        T = torch.empty((nt - 1, self.nout), dtype=torch.float32, device=self.device)
+        _mcheck(_lib.vds_mlp_make_pairs(self.m, _ptr(traj), nt, float(log_rate), _ptr(X), _ptr(T)), self.m)
+        return X, T
+
+    def set_scaling(self, x_shift, x_scale, y_shift, y_scale):
+        ts = [t.contiguous() for t in (x_shift, x_scale, y_shift, y_scale)]
+        _mcheck(_lib.vds_mlp_set_scaling(self.m, *[_ptr(t) for t in ts]), self.m)
+
+    def rollout(self, ctx, U, p, log_rate, nsteps, check_every, resid_tol, energy_tol):
+        R = int(U.shape[0])
+        n = _lib.vds_mlp_rollout_workspace_bytes(C.byref(ctx.prob), R)
+        ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        st = vds_mlp_rollout()
+        _mcheck(_lib.vds_mlp_rollout_run(self.m, ctx.ctx, _ptr(U), R, _ptr(p), float(log_rate), int(nsteps),
+                                         int(check_every), float(resid_tol), float(energy_tol), _ptr(ws), n,
+                                         C.byref(st)), self.m)
+        return dict(steps=st.steps, checks=st.checks, fallbacks=st.fallbacks, max_resid=st.max_resid,
+                    max_energy_gap=st.max_energy_gap, tau=np.array(st.tau[:]).reshape(3, 3))
 
 
 # C names, re-exported for callers who drive the ABI directly

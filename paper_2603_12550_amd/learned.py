@@ -1,0 +1,60 @@
+"""Pipeline of the learned reduced step (include/vds_mlp.h): trajectories of the
+particle scheme, a shared POD basis, training pairs, training and the checked
+rollout.  Every computation is a call into libvds; this module only orders the
+calls and moves tensors between them.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from ._vds import Context, Mlp
+
+
+def run_states(ctx: Context, q0: torch.Tensor, nsteps: int, every: int):
+    """Plain-scheme states q(0), q(every), ..., q(nsteps) (clones)."""
+    q = q0.clone()
+    out = [q.clone()]
+    for _ in range(0, nsteps, every):
+        ctx.step(q, nsteps=every)
+        out.append(q.clone())
+    return out
+
+
+def snapshot_matrix(states) -> torch.Tensor:
+    """Column-major snapshot matrix (ncols, 3P): columns (l, k) = bond k of state l."""
+    nb, P, _ = states[0].shape
+    return torch.stack(states).reshape(len(states) * nb, 3 * P).contiguous()
+
+
+def reduced_trajectory(ctx: Context, U: torch.Tensor, q0: torch.Tensor, nsteps: int) -> torch.Tensor:
+    """p(0..nsteps) = U^T q(t) of the plain scheme, rows of nb R."""
+    R = U.shape[0]
+    traj = torch.empty((nsteps + 1, ctx.nb * R), dtype=torch.float32, device=q0.device)
+    q = q0.clone()
+    traj[0] = ctx.pod_project(U, q).reshape(-1)
+    for n in range(nsteps):
+        ctx.step(q, nsteps=1)
+        traj[n + 1] = ctx.pod_project(U, q).reshape(-1)
+    return traj
+
+
+def training_set(mlp: Mlp, trajectories):
+    """[(traj, log_rate), ...] -> concatenated inputs X and increments T."""
+    Xs, Ts = [], []
+    for traj, log_rate in trajectories:
+        X, T = mlp.make_pairs(traj, log_rate)
+        Xs.append(X)
+        Ts.append(T)
+    return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
+
+
+def train(mlp: Mlp, X: torch.Tensor, T: torch.Tensor, epochs: int, batch: int, lr: float, seed: int = 0):
+    """Fits the scaling, then `epochs` passes in seeded random order; returns the losses."""
+    mlp.fit_scaling(X, T)
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    losses = []
+    for _ in range(epochs):
+        order = torch.randperm(X.shape[0], generator=gen).to(torch.int32).to(X.device)
+        losses.append(mlp.train_epoch(X, T, batch, lr, order=order))
+    return np.array(losses)

@@ -1,0 +1,170 @@
+"""GPU parity of the learned reduced step (include/vds_mlp.h): forward, loss and
+gradients against the FP64 oracle's hand-written backward pass, Adam against
+the oracle's update, BF16 inference against FP32, and the checked rollout with
+its fallback to the particle scheme.
+
+Tolerances: loss relative 1e-5; gradients relative Frobenius 1e-4 per tensor
+(FP32 MFMA products); Adam parameters after three steps relative 1e-5; BF16
+inference within 3e-2 of FP32 (8-bit mantissas); rollout stress within 1e-2 of
+the plain scheme."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2603_12550_amd as pkg
+    return pkg
+
+
+def _flat(layers):
+    return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in layers])
+
+
+def _unflat(v, sizes):
+    out, o = [], 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        W = v[o:o + a * b].reshape(b, a)
+        o += a * b
+        bb = v[o:o + b]
+        o += b
+        out.append((W, bb))
+    return out
+
+
+def _case(nin=37, w=32, nout=29, n=50, seed=3):
+    sizes = [nin, w, w, nout]
+    layers = wl.mlp_init(seed, sizes)
+    rng = np.random.default_rng(seed)
+    layers = [(W, rng.standard_normal(b.shape) * 0.1) for W, b in layers]
+    layers = [(wl.f32_as_f64(wl.to_f32(W)), wl.f32_as_f64(wl.to_f32(b))) for W, b in layers]
+    X = wl.f32_as_f64(wl.to_f32(rng.standard_normal((n, nin))))
+    T = wl.f32_as_f64(wl.to_f32(rng.standard_normal((n, nout))))
+    return sizes, layers, X, T
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(wl.to_f32(a)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_forward_loss_and_gradients_match_oracle(lib):
+    sizes, layers, X, T = _case()
+    m = lib.Mlp(sizes[0], sizes[1], sizes[3], 64)
+    m.set_params(_dev(_flat(layers)))
+    Y = m.forward(_dev(X)).cpu().numpy()
+    Y_o, _ = omlp.forward(layers, X)
+    assert _rel(Y, Y_o) < 1e-5
+    loss = m.loss_grad(_dev(X), _dev(T))
+    loss_o, grads_o = omlp.backward(layers, X, T)
+    assert loss == pytest.approx(loss_o, rel=1e-5)
+    g = _unflat(m.get_grads().cpu().numpy().astype(np.float64), sizes)
+    for (gW, gb), (oW, ob) in zip(g, grads_o):
+        assert _rel(gW, oW) < 1e-4
+        assert _rel(gb, ob) < 1e-4
+
+
+def test_bf16_inference_tracks_fp32(lib):
+    sizes, layers, X, _ = _case(nin=541, w=128, nout=540, n=16, seed=4)
+    m = lib.Mlp(541, 128, 540, 16)
+    m.set_params(_dev(_flat(layers)))
+    y32 = m.forward(_dev(X)).cpu().numpy()
+    y16 = m.forward(_dev(X), bf16=True).cpu().numpy()
+    assert _rel(y16, y32) < 3e-2
+    y1 = m.forward(_dev(X[:1]), bf16=True).cpu().numpy()   # batch of one, as in the rollout
+    assert _rel(y1, y16[:1]) < 1e-6
+
+
+def test_adam_steps_match_oracle(lib):
+    sizes, layers, X, T = _case(seed=5)
+    m = lib.Mlp(sizes[0], sizes[1], sizes[3], 64)
+    m.set_params(_dev(_flat(layers)))
+    mo, vo = omlp.adam_init(layers)
+    lo = layers
+    for t in range(1, 4):
+        m.loss_grad(_dev(X), _dev(T))
+        m.adam_step(1e-2)
+        _, g = omlp.backward(lo, X, T)
+        lo, mo, vo = omlp.adam_step(lo, g, mo, vo, t, lr=1e-2)
+    got = m.get_params().cpu().numpy().astype(np.float64)
+    assert _rel(got, _flat(lo)) < 1e-5
+
+
+def test_training_epochs_reduce_loss(lib):
+    import torch
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((512, 9))
+    T = np.tanh(X @ rng.standard_normal((9, 8)))
+    m = lib.Mlp(9, 32, 8, 64)
+    m.set_params(_dev(_flat(wl.mlp_init(7, [9, 32, 32, 8]))))
+    from paper_2603_12550_amd import learned
+    losses = learned.train(m, _dev(X), _dev(T), epochs=60, batch=64, lr=3e-3, seed=1)
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def _pipeline(lib, P=400, R=20, rates=(0.5, 1.0, 2.0), nsteps=300, width=64, epochs=150):
+    import torch
+    from paper_2603_12550_amd import learned
+    cfgs = []
+    states = []
+    for i, r in enumerate(rates):
+        ctx = lib.Context(3, P, 0.4, G=wl.shear_gradient(r), dt=1e-3, scheme="explicit")
+        q0 = torch.from_numpy(wl.to_f32(wl.gaussian_bonds(60, 3, P, 1 / 3))).cuda()
+        cfgs.append((ctx, q0, r))
+        states += learned.run_states(ctx, q0, nsteps, 10)
+    U, eig = cfgs[0][0].pod_basis(learned.snapshot_matrix(states), R)
+    trajs = [(learned.reduced_trajectory(ctx, U, q0, nsteps), math.log(r)) for ctx, q0, r in cfgs]
+    m = lib.Mlp(3 * R + 1, width, 3 * R, 256)
+    m.set_params(_dev(_flat(wl.mlp_init(8, [3 * R + 1, width, width, 3 * R]))))
+    X, T = learned.training_set(m, trajs)
+    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=2)
+    return cfgs, U, m, trajs, losses
+
+
+def test_learned_rollout_tracks_plain_scheme_and_falls_back(lib):
+    import torch
+    _say("learned-step pipeline P=400 R=20")
+    cfgs, U, m, trajs, losses = _pipeline(lib)
+    assert losses[-1] < 0.1 * losses[0]
+    ctx, q0, r = cfgs[1]
+    # plain scheme reference at t_end
+    q = q0.clone()
+    ctx.step(q, nsteps=300)
+    tau_ref = ctx.stress(q)
+    p = ctx.pod_project(U, q0)
+    st = m.rollout(ctx, U, p, math.log(r), nsteps=300, check_every=50, resid_tol=0.5, energy_tol=0.5)
+    _say("rollout", st)
+    assert st["checks"] == 6
+    assert np.linalg.norm(st["tau"] - tau_ref) / np.linalg.norm(tau_ref) < 1e-2
+    # a tolerance of zero rejects every window: the rollout is the plain scheme, re-projected
+    p = ctx.pod_project(U, q0)
+    st0 = m.rollout(ctx, U, p, math.log(r), nsteps=300, check_every=50, resid_tol=0.0, energy_tol=0.5)
+    assert st0["fallbacks"] == st0["checks"] == 6
+    assert np.linalg.norm(st0["tau"] - tau_ref) / np.linalg.norm(tau_ref) < 1e-2
+    # a broken network (scaling replaced, increments ten times larger) fails the residual check
+    R = U.shape[0]
+    xs = torch.zeros(3 * R + 1, device="cuda")
+    m.set_scaling(xs, torch.ones_like(xs), torch.zeros(3 * R, device="cuda"),
+                  10.0 * torch.ones(3 * R, device="cuda"))
+    p = ctx.pod_project(U, q0)
+    st10 = m.rollout(ctx, U, p, math.log(r), nsteps=100, check_every=50, resid_tol=0.5, energy_tol=0.5)
+    assert st10["fallbacks"] == st10["checks"] == 2
