@@ -86,6 +86,211 @@ def copy_calibration(nbytes: int = 1 << 29, reps: int = 5):
     print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def _timer_rate(ctx, which):
+    from paper_2603_12550_amd import _vds
+    t = ctx.timing_read(which)
+    return t["ms"], t["launches"], t["work"]
+
+
+def measure_pod_rom(pkg, wl, torch, P):
+    """POD-reduced chain: reference run of 2000 implicit steps collecting 300
+    snapshots over steps 0..1000, rank-180 basis, 2000 reduced explicit steps
+    with freezes every 300; errors of the reduced state and stress at t_end."""
+    from paper_2603_12550_amd import _vds
+    cfg = wl.pod_chain4(P=P)
+    ctx = pkg.Context(3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
+    snaps = [int(v) for v in wl.snapshot_steps(cfg["snapshots"], cfg["snap_until"])]
+    X = torch.empty((len(snaps) * 3, 3 * P), dtype=torch.float32, device="cuda")
+    q = q0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for li, s in enumerate(snaps):
+        if s > done:
+            ctx.step(q, nsteps=s - done)
+            done = s
+        X[3 * li:3 * li + 3].copy_(q.reshape(3, 3 * P))
+    ctx.step(q, nsteps=cfg["steps"] - done)
+    torch.cuda.synchronize()
+    T_ref = time.perf_counter() - t0
+    tau_ref = ctx.stress(q)
+    ctx.timing_enable(True)
+    t1 = time.perf_counter()
+    U, eig = ctx.pod_basis(X, cfg["R"])
+    torch.cuda.synchronize()
+    T_pod = time.perf_counter() - t1
+    gemm = _timer_rate(ctx, _vds.VDS_TIMER_GEMM)
+    ctx.timing_enable(False)
+    rom = pkg.Rom(ctx, U)
+    p = ctx.pod_project(U, q0)
+    rom.run(p.clone(), 300, 300)          # warm-up
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tau_rom = rom.run(p, cfg["rom_steps"], cfg["freeze_every"])
+    torch.cuda.synchronize()
+    T_rom = time.perf_counter() - t2
+    kg = _timer_rate(ctx, _vds.VDS_TIMER_KGEMM)
+    ctx.timing_enable(False)
+    q_rom = ctx.pod_reconstruct(U, p)
+    err_mor = float((q_rom - q).norm() / q.norm())
+    lam = np.asarray(eig)
+    return {
+        "workload": f"POD-reduced 4-bead chain, P={P}: reference 2000 implicit steps, 300 snapshots over "
+                    f"steps 0-1000 (900 columns), R=180, 2000 reduced explicit steps, freeze every 300",
+        "T_ref_s": T_ref, "T_rom_s": T_rom, "T_rom_over_T_ref": T_rom / T_ref, "T_pod_offline_s": T_pod,
+        "err_mor_t_end": err_mor,
+        "stress_rel_err_vs_plain": float(np.linalg.norm(tau_rom - tau_ref) / np.linalg.norm(tau_ref)),
+        "tau_ref": tau_ref.tolist(), "tau_rom": tau_rom.tolist(),
+        "eig_head": lam[:8].tolist(),
+        # tail eigenvalues of the FP32 Gram matrix below its rounding level come out
+        # of either sign: the remaining energy counts the positive ones, and the
+        # largest negative one gives the level below which it cannot be resolved
+        "remaining_energy_at_R": float(np.clip(lam[cfg["R"]:], 0, None).sum() / np.clip(lam, 0, None).sum()),
+        "gram_rounding_level": float(max(0.0, -lam.min()) / np.clip(lam, 0, None).sum()),
+        "gemm_ms": gemm[0], "gemm_tflops": gemm[2] / (gemm[0] * 1e-3) / 1e12 if gemm[0] else None,
+        "kernel_gemm_ms_per_freeze": kg[0] / max(1, kg[1]),
+        "kernel_gemm_tflops": kg[2] / (kg[0] * 1e-3) / 1e12 if kg[0] else None,
+    }
+
+
+def measure_batched(pkg, wl, torch, steps):
+    """512 ensembles, explicit Euler, one graph-captured step replayed."""
+    ens = wl.ensembles()
+    G = np.stack([wl.shear_gradient(r) for r in ens["rate"]])
+    b = pkg.Batch(ens["P"], ens["h"], G)
+    states = [torch.from_numpy(wl.to_f32(wl.ensemble_state(ens, e))).cuda() for e in range(ens["n_ens"])]
+    q0 = b.pack(states)
+    tune = b.autotune(q0)
+    q = q0.clone()
+    b.step(q, nsteps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tau = b.step(q, nsteps=steps, stress=True)
+    torch.cuda.synchronize()
+    T_b = time.perf_counter() - t0
+    pairs = 2.0 * float((ens["P"].astype(np.float64) ** 2).sum()) * steps
+    # plain single-ensemble contexts on a sample, same steps from the same start
+    rng = np.random.default_rng(11)
+    sample = rng.choice(ens["n_ens"], 12, replace=False)
+    qs = q0.clone()
+    tau_s = b.step(qs, nsteps=20, stress=True)
+    t_plain, pairs_plain, errs = 0.0, 0.0, []
+    for e in sample:
+        e = int(e)
+        ctx = pkg.Context(3, int(ens["P"][e]), ens["h"][e], G=G[e], dt=ens["dt"], scheme="explicit")
+        qe = states[e].clone()
+        ctx.step(qe, nsteps=1)
+        qe = states[e].clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.step(qe, nsteps=20)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t1
+        pairs_plain += 2.0 * float(ens["P"][e]) ** 2 * 20
+        tp = ctx.stress(qe)
+        errs.append(float(np.linalg.norm(tau_s[e] - tp) / np.linalg.norm(tp)))
+    rate_b, rate_p = pairs / T_b, pairs_plain / t_plain
+    return {
+        "workload": f"{ens['n_ens']} independent 4-bead ensembles, P_b in [2000, 16000] (sum {int(ens['P'].sum())}), "
+                    f"shear rate log-uniform [0.1, 10], h_b = 0.4 (P_b/20000)^(-1/13), explicit dt=1e-3, {steps} steps",
+        "tuning": tune, "seconds": T_b, "pair_evals_per_s": rate_b,
+        "plain_single_ensemble_pair_evals_per_s": rate_p, "speedup_vs_plain_single": rate_b / rate_p,
+        "plain_sample": [int(v) for v in sample],
+        "max_stress_rel_err_vs_plain_after_20_steps": max(errs),
+        "tau_mean_trace": float(np.mean([np.trace(t) for t in tau])),
+    }
+
+
+def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps):
+    """Learned reduced step on the 4-bead chain (R = 180, input 541, width 128):
+    training pairs from projected explicit runs at log-uniform shear rates, then
+    a checked rollout at a held-out rate against the plain scheme and against the
+    POD-Galerkin reduced model (the method without the network)."""
+    import math
+    from paper_2603_12550_amd import learned
+    R, h = 180, 0.4
+    rates = wl.mlp_shear_rates(n_runs)
+    q0 = torch.from_numpy(wl.to_f32(wl.gaussian_bonds(2, 3, P, 1 / 3))).cuda()
+    ctxs = [pkg.Context(3, P, h, G=wl.shear_gradient(r), dt=1e-3, scheme="explicit") for r in rates]
+    t0 = time.perf_counter()
+    states = []
+    for ctx in ctxs:
+        states += learned.run_states(ctx, q0, run_steps, 10)
+    U, eig = ctxs[0].pod_basis(learned.snapshot_matrix(states), R)
+    trajs = [(learned.reduced_trajectory(ctx, U, q0, run_steps), math.log(r)) for ctx, r in zip(ctxs, rates)]
+    m = pkg.Mlp(3 * R + 1, 128, 3 * R, 256)
+    init = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in wl.mlp_init(9, [3 * R + 1, 128, 128, 3 * R])])
+    m.set_params(torch.from_numpy(wl.to_f32(init)).cuda())
+    X, T = learned.training_set(m, trajs)
+    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=3)
+    torch.cuda.synchronize()
+    T_offline = time.perf_counter() - t0
+    rate = 1.0
+    ctx = pkg.Context(3, P, h, G=wl.shear_gradient(rate), dt=1e-3, scheme="explicit")
+    q = q0.clone()
+    ctx.step(q.clone(), nsteps=2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.step(q, nsteps=rollout_steps)
+    torch.cuda.synchronize()
+    T_plain = time.perf_counter() - t1
+    tau_ref = ctx.stress(q)
+    p = ctx.pod_project(U, q0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = m.rollout(ctx, U, p, math.log(rate), nsteps=rollout_steps, check_every=50, resid_tol=0.5, energy_tol=0.5)
+    torch.cuda.synchronize()
+    T_roll = time.perf_counter() - t2
+    rom = pkg.Rom(ctx, U)
+    pg = ctx.pod_project(U, q0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    tau_gal = rom.run(pg, rollout_steps, 50)
+    torch.cuda.synchronize()
+    T_gal = time.perf_counter() - t3
+    err = lambda t: float(np.linalg.norm(t - tau_ref) / np.linalg.norm(tau_ref))
+    return {
+        "workload": f"learned reduced step, 4-bead chain P={P}, R={R} (input {3 * R + 1}, width 128, SiLU), "
+                    f"{n_runs} training runs x {run_steps} explicit steps at shear rates log-uniform [0.1, 10] "
+                    f"({int(X.shape[0])} pairs), {epochs} epochs of batch 64 at lr 2e-3; rollout {rollout_steps} steps at the held-out rate 1.0, "
+                    f"checked every 50 steps",
+        "offline_s": T_offline, "final_loss": float(losses[-1]), "first_loss": float(losses[0]),
+        "T_plain_s": T_plain, "T_rollout_s": T_roll, "speedup_vs_plain": T_plain / T_roll,
+        "stress_rel_err_vs_plain": err(st["tau"]), "checks": st["checks"], "fallbacks": st["fallbacks"],
+        "max_resid": st["max_resid"], "max_energy_gap": st["max_energy_gap"],
+        "without_network_pod_galerkin": {"T_s": T_gal, "stress_rel_err_vs_plain": err(tau_gal),
+                                         "speedup_vs_plain": T_plain / T_gal},
+    }
+
+
+def measure_fene(pkg, wl, torch, steps):
+    """6-bead FENE chain (D = 15), P = 50000, explicit steps of the plain scheme."""
+    from paper_2603_12550_amd import _vds
+    cfg = wl.fene_chain6()
+    P = cfg["P"]
+    ctx = pkg.Context(5, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme="explicit", potential="fene",
+                      b_max=cfg["b_max"])
+    q = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
+    tune = ctx.autotune(q)
+    ctx.step(q, nsteps=2)
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(q, nsteps=steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    ms, n, work = _timer_rate(ctx, _vds.VDS_TIMER_PAIR)
+    ctx.timing_enable(False)
+    avg = ms / max(1, n)
+    return {"workload": f"6-bead FENE chain, D=15, P={P}, b_max=50, explicit dt=1e-3, {steps} steps",
+            "tuning": tune, "pair_evals_per_s": 2.0 * P * P * steps / T,
+            "pair_kernel_avg_ms": avg,
+            "pair_kernel_tflops": P * P * flops_per_pair(15) / (avg * 1e-3) / 1e12,
+            "tau": ctx.stress(q).tolist()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +302,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy of known size")
     ap.add_argument("--sweep", action="store_true", help="only time every pair-kernel tuning and print a table")
     ap.add_argument("--t-end", action="store_true", help="also time the full 500-step run to t_end")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the POD-reduced, batched, learned and FENE measurements")
+    ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--learned-runs", type=int, default=8)
+    ap.add_argument("--learned-run-steps", type=int, default=300)
+    ap.add_argument("--learned-epochs", type=int, default=600)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -200,6 +411,18 @@ def main():
         torch.cuda.synchronize()
         out["t_end"] = {"steps": cfg["steps"], "seconds": time.perf_counter() - t1, "iterations": d["iters"],
                         "tau": d["tau"].tolist()}
+
+    if not args.no_extras:
+        extras = {}
+        for name, fn in (("pod_reduced", lambda: measure_pod_rom(pkg, wl, torch, P)),
+                         ("batched", lambda: measure_batched(pkg, wl, torch, args.batched_steps)),
+                         ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
+                                                            args.learned_run_steps, args.learned_epochs, 300)),
+                         ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20))):
+            t0 = time.perf_counter()
+            extras[name] = fn()
+            print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        out["extras"] = extras
 
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
