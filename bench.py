@@ -332,7 +332,7 @@ def main():
                       picard_rtol=1e-6, picard_max=50, picard_batch=3)
     q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
     if args.sweep:
-        for impl, rbs in ((0, (1, 2, 4)), (1, (1,))):
+        for impl, rbs in ((0, (1, 2, 4)), (2, (1, 2, 4)), (3, (1, 2, 4)), (1, (1,))):
             for rb in rbs:
                 for sp in (1, 2, 4, 8, 16, 32):
                     ctx.set_tuning(impl, rb, sp)

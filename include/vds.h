@@ -46,7 +46,18 @@ typedef enum vds_status {
 
 enum { VDS_HOOKEAN = 0, VDS_FENE = 1 };
 enum { VDS_EXPLICIT = 0, VDS_IMPLICIT = 1 };
-enum { VDS_PAIR_MFMA = 0, VDS_PAIR_VALU = 1 };
+/* Pair-kernel implementations (all compute the same sums):
+ *   VDS_PAIR_MFMA       FP32 matrix cores for both products (distances, kernel-weighted sums);
+ *   VDS_PAIR_VALU       FP32 vector FMAs;
+ *   VDS_PAIR_MFMA_F16X2 FP32 matrix cores for the distances, the kernel-weighted sums on FP16
+ *                       matrix cores with both factors split into high and low halves (about
+ *                       22 significant bits, against 24 for FP32; sums beyond 128 columns
+ *                       in FP64 as for the others);
+ *   VDS_PAIR_MFMA_F16X2_ALL  both products on FP16 matrix cores with split factors; the
+ *                       squared norms enter in FP32.  FP16 range: valid while every centred
+ *                       particle lies within about 5e4 h of the weighted mean (the FP32 forms
+ *                       lose all accuracy well before that). */
+enum { VDS_PAIR_MFMA = 0, VDS_PAIR_VALU = 1, VDS_PAIR_MFMA_F16X2 = 2, VDS_PAIR_MFMA_F16X2_ALL = 3 };
 
 /* Problem description (Sections 2.1, 2.2, 3.1; Appendix A).
  * Drift of bond k of particle I (eq. model_DymRepPar, convection dropped):
@@ -88,8 +99,8 @@ typedef struct vds_diag {
 
 /* Pair-kernel launch shape (chosen by vds_autotune or set by hand). */
 typedef struct vds_tuning {
-  int32_t impl;          /* VDS_PAIR_MFMA or VDS_PAIR_VALU */
-  int32_t rows_per_wave; /* MFMA: 16-row blocks per wavefront (1, 2 or 4) */
+  int32_t impl;          /* one of the VDS_PAIR_* implementations */
+  int32_t rows_per_wave; /* MFMA forms: 16-row blocks per wavefront (1, 2 or 4) */
   int32_t col_splits;    /* column ranges summed separately, then reduced (>= 1) */
   int32_t reserved;
 } vds_tuning;

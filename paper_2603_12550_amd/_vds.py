@@ -24,7 +24,7 @@ _lib = C.CDLL(LIB_PATH)
 VDS_OK, VDS_ERR_ARG, VDS_ERR_HIP, VDS_ERR_NOMEM, VDS_ERR_NOT_CONVERGED, VDS_ERR_STATE = range(6)
 VDS_HOOKEAN, VDS_FENE = 0, 1
 VDS_EXPLICIT, VDS_IMPLICIT = 0, 1
-VDS_PAIR_MFMA, VDS_PAIR_VALU = 0, 1
+VDS_PAIR_MFMA, VDS_PAIR_VALU, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL = 0, 1, 2, 3
 VDS_TIMER_PAIR, VDS_TIMER_GEMM, VDS_TIMER_KGEMM, VDS_TIMER_PROJ = range(4)
 STATUS_NAMES = {0: "VDS_OK", 1: "VDS_ERR_ARG", 2: "VDS_ERR_HIP", 3: "VDS_ERR_NOMEM",
                 4: "VDS_ERR_NOT_CONVERGED", 5: "VDS_ERR_STATE"}

@@ -39,6 +39,47 @@ __device__ inline int64_t qk_index(int64_t I, int k, int KK) {
 __device__ inline int64_t v_index(int64_t J, int n) {
   return ((J >> 4) * 64 + ((J & 15) >> 2) * 16 + n) * 4 + (J & 3);
 }
+//   V as FP16 halves (VDS_PAIR_MFMA_F16X2): the high half of element n of V_J
+//          at [((J / 32) * 64 + n + 16 ((J % 16) / 4)) * 8 + 4 ((J / 16) % 2) + J % 4]
+//          and the low half Ppad * 16 halves further on.
+__device__ inline int64_t vh_index(int64_t J, int n) {
+  return ((J >> 5) * 64 + n + 16 * ((J & 15) >> 2)) * 8 + 4 * ((J >> 4) & 1) + (J & 3);
+}
+//   QH/KH: FP16 distance slot s (0 <= s < 32 KQ) of particle I at
+//          [(((I / 16) * KQ + s / 32) * 64 + I % 16 + 16 ((s % 32) / 8)) * 8 + s % 8]
+__device__ inline int64_t dh_index(int64_t I, int s, int KQ) {
+  return ((((I >> 4) * KQ + (s >> 5)) * 64 + (I & 15) + 16 * ((s & 31) >> 3)) << 3) + (s & 7);
+}
+// Row-side and column-side values of FP16 distance slot s, given the component
+// y_k = cs x_k for k = s / 3 and the norm term -kappa |x|^2 (see pair_kernels.hip).
+__device__ inline void dh_slot(const EvalParams &p, int s, float yk, float nterm, _Float16 &qv, _Float16 &kv) {
+  const _Float16 z = (_Float16)0.f;
+  qv = z;
+  kv = z;
+  if (s < 3 * p.D) {
+    const int ty = s % 3;
+    const _Float16 hi = (_Float16)yk;
+    const _Float16 lo = (_Float16)(yk - (float)hi);
+    qv = ty == 2 ? lo : hi;
+    kv = ty == 1 ? lo : hi;
+  } else if (s < 3 * p.D + 2) {
+    const float v = nterm * 0.0625f;
+    const _Float16 hi = (_Float16)v;
+    qv = (_Float16)16.f;
+    kv = s == 3 * p.D ? hi : (_Float16)(v - (float)hi);
+  }
+}
+__device__ inline void store_v(const EvalParams &p, float *V, int64_t J, int n, float v) {
+  if (p.vhalf) {
+    _Float16 *h = reinterpret_cast<_Float16 *>(V);
+    const _Float16 hi = (_Float16)v;
+    const int64_t i = vh_index(J, n);
+    h[i] = hi;
+    h[i + p.Ppad * 16] = (_Float16)(v - (float)hi);
+  } else {
+    V[v_index(J, n)] = v;
+  }
+}
 
 // Partial sums of w_I x_I (FP64) per block, for the weighted centring.
 // Bodies take the block index `lb` within the problem (one ensemble) so that
@@ -56,6 +97,16 @@ __device__ void mean_partials_body(const EvalParams &p, int64_t lb, const float 
   }
   block_sum<kMaxD>(v, sm);
   if (threadIdx.x < kMaxD) meanp[lb * 16 + threadIdx.x] = v[threadIdx.x];
+  // slot 15: the block's largest weight
+  __shared__ float wm[kRedBlock / 64];
+  float m = I < p.P ? load_weight(w, I, p.uniform_w) : 0.f;
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kRedBlock / 64; ++i) m = fmaxf(m, wm[i]);
+    meanp[lb * 16 + 15] = (double)m;
+  }
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const float *__restrict__ q,
@@ -65,12 +116,17 @@ __global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const
   mean_partials_body(p, blockIdx.x, q, w, meanp);
 }
 
-// Sum of the centring partials, computed identically by every block.
+// Sum of the centring partials (mean_sh[0..D)) and the largest weight
+// (mean_sh[15]), computed identically by every block.
 __device__ void load_mean(const EvalParams &p, const double *meanp, int nmeanp, float *mean_sh) {
   if (threadIdx.x < p.D) {
     double s = 0.0;
     for (int b = 0; b < nmeanp; ++b) s += meanp[(int64_t)b * 16 + threadIdx.x];
     mean_sh[threadIdx.x] = (float)s;
+  } else if (threadIdx.x == 15) {
+    double m = 0.0;
+    for (int b = 0; b < nmeanp; ++b) m = fmax(m, meanp[(int64_t)b * 16 + 15]);
+    mean_sh[15] = (float)m;
   }
   __syncthreads();
 }
@@ -90,13 +146,15 @@ __device__ inline float gsum(float v) {
   return v;
 }
 
-// Centre, pack Q/K operands and the pass-A V operand (weights w).
+// Centre, pack Q/K operands and the pass-A V operand (weights w; over their
+// maximum, which goes to *wscale, when V is written in FP16 halves).
 __device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
                           const double *__restrict__ meanp, int nmeanp, float *__restrict__ xc,
                           float *__restrict__ wv, float *__restrict__ QB, float *__restrict__ KA,
-                          float *__restrict__ VA) {
-  __shared__ float mean_sh[kMaxD];
+                          float *__restrict__ VA, float *__restrict__ wscale, F16Operands f16) {
+  __shared__ float mean_sh[16];
   load_mean(p, meanp, nmeanp, mean_sh);
+  if (p.vhalf && wscale != nullptr && lb == 0 && threadIdx.x == 0) *wscale = mean_sh[15];
   const int64_t I = group_particle(lb);
   const int n = group_lane();
   if (I >= p.Ppad) return;
@@ -123,19 +181,35 @@ __device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restri
     QB[qk_index(I, k, p.KK)] = qa;
     KA[qk_index(I, k, p.KK)] = ka;
   }
+  if (p.qhalf) {
+    _Float16 *qh = reinterpret_cast<_Float16 *>(f16.QH);
+    _Float16 *kh = reinterpret_cast<_Float16 *>(f16.KH);
+    const float y = p.cs * x;
+    for (int sl = n; sl < 32 * p.KQ; sl += 16) {  // the same trip count on every lane
+      const int k = sl / 3;
+      const float yk = gshfl(y, k < 16 ? k : 0);
+      _Float16 qv, kv;
+      dh_slot(p, sl, yk, real ? -p.kappa * nrm : 0.f, qv, kv);
+      qh[dh_index(I, sl, p.KQ)] = qv;
+      kh[dh_index(I, sl, p.KQ)] = kv;
+    }
+    if (n == 0) f16.RN[I] = real ? -p.kappa * nrm : 0.f;
+  }
+  const float wn = p.vhalf ? (real ? wi / mean_sh[15] : 0.f) : wi;
   float v = 0.f;
-  if (n < p.D) v = wi * x;
-  else if (n == p.D) v = wi;
-  VA[v_index(I, n)] = v;
+  if (n < p.D) v = wn * x;
+  else if (n == p.D) v = wn;
+  store_v(p, VA, I, n, v);
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *__restrict__ q,
                                                     const float *__restrict__ w, const double *__restrict__ meanp,
                                                     int nmeanp, float *__restrict__ xc, float *__restrict__ wv,
                                                     float *__restrict__ QB, float *__restrict__ KA,
-                                                    float *__restrict__ VA, const int *__restrict__ done) {
+                                                    float *__restrict__ VA, float *__restrict__ wscale,
+                                                    F16Operands f16, const int *__restrict__ done) {
   if (done != nullptr && *done) return;
-  prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA);
+  prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16);
 }
 
 // Component n of row I summed over the column splits, in FP64.
@@ -156,7 +230,7 @@ __device__ void finalize_a_body(const EvalParams &p, int64_t lb, const float *__
   const int n = group_lane();
   if (I >= p.Ppad) return;
   if (I >= p.P) {  // padding columns carry zero weight in pass B too
-    VB[v_index(I, n)] = 0.f;
+    store_v(p, VB, I, n, 0.f);
     return;
   }
   const double o = n <= p.D ? sum_splits(p, partial, splits, I, n) : 0.0;
@@ -171,7 +245,7 @@ __device__ void finalize_a_body(const EvalParams &p, int64_t lb, const float *__
     S[I] = (float)Si;
     v = wb;
   }
-  VB[v_index(I, n)] = v;
+  store_v(p, VB, I, n, v);  // wb <= 1, so the FP16 form needs no normalisation
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, int splits,
@@ -392,8 +466,9 @@ __global__ __launch_bounds__(kRedBlock) void k_stress(EvalParams p, const float 
 // Foreign rows y[ny][D] (particle-major) as Q operands, centred like the particles.
 __global__ __launch_bounds__(kRedBlock) void k_density_rows(EvalParams p, const float *__restrict__ y, int64_t ny,
                                                             const double *__restrict__ meanp, int nmeanp,
-                                                            float *__restrict__ QB, int64_t nrows_pad) {
-  __shared__ float mean_sh[kMaxD];
+                                                            float *__restrict__ QB, F16Operands f16,
+                                                            int64_t nrows_pad) {
+  __shared__ float mean_sh[16];
   load_mean(p, meanp, nmeanp, mean_sh);
   const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
   if (I >= nrows_pad) return;
@@ -411,6 +486,16 @@ __global__ __launch_bounds__(kRedBlock) void k_density_rows(EvalParams p, const 
       else if (k == p.D + 1) qa = 1.f;
     }
     QB[qk_index(I, k, p.KK)] = qa;
+  }
+  if (p.qhalf) {
+    _Float16 *qh = reinterpret_cast<_Float16 *>(f16.QH);
+    for (int sl = 0; sl < 32 * p.KQ; ++sl) {
+      const int k = sl / 3;
+      _Float16 qv, kv;
+      dh_slot(p, sl, I < ny && k < p.D ? p.cs * x[k] : 0.f, 0.f, qv, kv);
+      qh[dh_index(I, sl, p.KQ)] = qv;
+    }
+    f16.RN[I] = I < ny ? -p.kappa * nrm : 0.f;
   }
 }
 
@@ -439,7 +524,8 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_prep(BatchView b, const flo
   const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
   const int64_t o = d.pad_off;
   prep_body(d.p, blockIdx.x - d.blk16, q + d.q_off, nullptr, meanp + (int64_t)d.blk256 * 16,
-            (int)(d.p.Ppad / kRedBlock), xc + o * b.D, wv + o, QB + o * b.KK * 4, KA + o * b.KK * 4, VA + o * 16);
+            (int)(d.p.Ppad / kRedBlock), xc + o * b.D, wv + o, QB + o * b.KK * 4, KA + o * b.KK * 4, VA + o * 16,
+            nullptr, F16Operands{nullptr, nullptr, nullptr});
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_batch_finalize_a(BatchView b, const float *__restrict__ partial,
@@ -489,8 +575,10 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
   k_mean_partials<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, meanp, done);
 }
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
-                 float *wv, float *QB, float *KA, float *VA, const int *done, hipStream_t s) {
-  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, done);
+                 float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16, const int *done,
+                 hipStream_t s) {
+  const F16Operands ops = f16 != nullptr ? *f16 : F16Operands{nullptr, nullptr, nullptr};
+  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, done);
 }
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {
@@ -516,10 +604,11 @@ void launch_stress(const EvalParams &p, const float *q, const float *w, double *
   k_stress<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, redp);
 }
 void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,
-                         float *QB, hipStream_t s) {
+                         float *QB, const F16Operands *f16, hipStream_t s) {
+  const F16Operands ops = f16 != nullptr ? *f16 : F16Operands{nullptr, nullptr, nullptr};
   // rows are padded to a multiple of 256 within the Ppad-row operand buffer
   const int64_t nrows_pad = round_up(ny, kRowAlign);
-  k_density_rows<<<nblocks(nrows_pad), kRedBlock, 0, s>>>(p, y, ny, meanp, nmeanp, QB, nrows_pad);
+  k_density_rows<<<nblocks(nrows_pad), kRedBlock, 0, s>>>(p, y, ny, meanp, nmeanp, QB, ops, nrows_pad);
 }
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm, float *f,
                         hipStream_t s) {

@@ -20,6 +20,21 @@
 //    consecutive dwords.
 //  * VALU: one thread per row pair, column tiles of 256 staged in LDS, FP32
 //    FMAs, v_exp_f32.
+//  * MFMA, FP16-split product: t as above on FP32 MFMA, then the e V product
+//    on v_mfma_f32_16x16x32_f16 with both factors split into two halves,
+//    e = e_hi + e_lo and V = V_hi + V_lo, and e V taken as
+//    e_hi V_hi + e_hi V_lo + e_lo V_hi (the dropped e_lo V_lo is 2^-22 of it).
+//    Half products are exact in the FP32 accumulator, so the product keeps
+//    about 22 bits against 24 for FP32, at three MFMAs per 32 columns instead
+//    of eight.  FP16 has a narrow exponent range, so e is computed as
+//    2^(t + 15) (the shift enters through the accumulator of the t product)
+//    and the column weights in V are divided by their maximum; with e spanning
+//    2^15 down to the FP16 subnormals, pairs as weak as 1e-12 of the strongest
+//    still count.  The shift and the weight maximum are taken out in FP64 at
+//    the end.
+//  * MFMA, FP16-split products throughout: as the previous one, and t too on
+//    v_mfma_f32_16x16x32_f16 from split halves of sqrt(2 kappa) x, with the
+//    squared norms kept in FP32 (layout at pair_rows_f16).
 // Column ranges are split over blockIdx.y; every split writes its own partial
 // sums, reduced later in a fixed order (deterministic, no float atomics).
 //
@@ -156,6 +171,205 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
                     partial + (int64_t)blockIdx.y * part_stride_rows * 16, rb0);
 }
 
+// ---- FP16-split variant ----------------------------------------------------
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+constexpr float kF16Shift = 15.f;  // e = 2^(t + 15) <= 2^15 < FP16 max
+constexpr int kFlushPairs = 4;     // chunk pairs (32 columns each) per FP32 group
+
+// (a, b) -> hi = (a, b) rounded toward zero to FP16, lo = the remainders
+// a - hi, b - hi (exact in FP32) rounded to nearest FP16.  `one` is 1.0 passed
+// in at run time, so that the compiler keeps fma(-hi, one, a) and selects the
+// mixed-precision FMA that reads the packed FP16 halves directly.
+__device__ inline void split_pair(float a, float b, float one, half2v &hi, half2v &lo) {
+  hi = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(a, b));
+  const float ra = __builtin_fmaf(-(float)hi.x, one, a);
+  const float rb = __builtin_fmaf(-(float)hi.y, one, b);
+  lo = half2v{(_Float16)ra, (_Float16)rb};
+}
+
+__device__ inline half8 as_half8(uint4 u) {
+  half8 h;
+  __builtin_memcpy(&h, &u, sizeof(h));
+  return h;
+}
+
+// One wavefront: row blocks rb0 .. rb0 + RB - 1 against column chunk pairs
+// [p0, p1).  VH[cp * 64 + lane] holds, for lane = n + 16 g, the FP16 highs of
+// V_J[n] for the eight columns J = 32 cp + 16 s + 4 g + i (slot 4 s + i) and
+// VH[lo_off + cp * 64 + lane] the lows.  out_scale multiplies every sum.
+//
+// t comes from FP32 MFMAs over the QB/KA operands (KQ = 0, KK slices), or
+// (KQ > 0) from KQ FP16 MFMAs of 32 products each over the QH/KH operands:
+// with c = sqrt(2 kappa) and y = c x split into FP16 halves, slot 3k + (0, 1, 2)
+// holds (y_I,hi y_J,hi, y_I,hi y_J,lo, y_I,lo y_J,hi) for component k, and
+// slots 3D, 3D + 1 hold 16 times the two halves of -kappa |x_J|^2 / 16.  The
+// row norm -kappa |x_I|^2 (RN) enters exactly, in FP32, through the
+// accumulator's initial value.
+template <int KK, int KQ, int RB>
+__device__ void pair_rows_f16(const float *__restrict__ QB, const uint4 *__restrict__ QH,
+                              const float *__restrict__ RN, int nrow_blocks, const float *__restrict__ KA,
+                              const uint4 *__restrict__ KH, const uint4 *__restrict__ VH, int64_t lo_off, int p0,
+                              int p1, const float *__restrict__ xc, int D, int exclude_self, double out_scale,
+                              float one, float *__restrict__ out, int rb0) {
+  constexpr bool kQ16 = KQ > 0;
+  constexpr int NK = kQ16 ? 1 : KK;  // FP32 operand slices (unused with FP16 distances)
+  constexpr int NQ = kQ16 ? KQ : 1;  // FP16 operand slices (unused with FP32 distances)
+  if (rb0 >= nrow_blocks) return;
+  const int lane = threadIdx.x & 63;
+  const int diag_i = (lane & 15) - 4 * (lane >> 4);
+
+  float qv[RB][NK];
+  half8 qh[RB][NQ];
+  float rinit[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const bool ok = rb0 + r < nrow_blocks;
+    if constexpr (kQ16) {
+#pragma unroll
+      for (int m = 0; m < KQ; ++m)
+        qh[r][m] = as_half8(ok ? QH[((int64_t)(rb0 + r) * KQ + m) * 64 + lane] : uint4{0, 0, 0, 0});
+      rinit[r] = (ok ? RN[(int64_t)(rb0 + r) * 16 + (lane & 15)] : 0.f) + kF16Shift;
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk) qv[r][kk] = ok ? QB[((int64_t)(rb0 + r) * KK + kk) * 64 + lane] : 0.f;
+      rinit[r] = kF16Shift;
+    }
+  }
+
+  double tot[RB][4];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[r][i] = 0.0;
+
+  float ka[2][NK];
+  uint4 kh[2][NQ];
+  uint4 vh, vl;
+  auto load_cols = [&](int cp, float (&fa)[2][NK], uint4 (&ha)[2][NQ], uint4 &h, uint4 &l) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if constexpr (kQ16) {
+#pragma unroll
+        for (int m = 0; m < KQ; ++m) ha[s][m] = KH[((int64_t)(2 * cp + s) * KQ + m) * 64 + lane];
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) fa[s][kk] = KA[((int64_t)(2 * cp + s) * KK + kk) * 64 + lane];
+      }
+    }
+    h = VH[(int64_t)cp * 64 + lane];
+    l = VH[lo_off + (int64_t)cp * 64 + lane];
+  };
+  if (p0 < p1) load_cols(p0, ka, kh, vh, vl);
+  for (int cp = p0; cp < p1;) {
+    const int g_end = min(p1, cp + kFlushPairs);
+    floatx4 acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; cp < g_end; ++cp) {
+      // prefetch the next chunk pair's operands while this one computes
+      float kan[2][NK];
+      uint4 khn[2][NQ];
+      uint4 vhn, vln;
+      load_cols((cp + 1 < p1) ? cp + 1 : cp, kan, khn, vhn, vln);
+      const half8 h8 = as_half8(vh), l8 = as_half8(vl);
+
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        float e[8];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          floatx4 t = {rinit[r], rinit[r], rinit[r], rinit[r]};
+          if constexpr (kQ16) {
+#pragma unroll
+            for (int m = 0; m < KQ; ++m)
+              t = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(kh[s][m]), qh[r][m], t, 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ka[s][kk], qv[r][kk], t, 0, 0, 0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) e[4 * s + i] = fminf(__builtin_amdgcn_exp2f(t[i]), 32768.f);
+        }
+        if (exclude_self && (2 * cp == rb0 + r || 2 * cp + 1 == rb0 + r)) {  // scalar branch: diagonal tile
+          const int sd = 2 * cp == rb0 + r ? 0 : 4;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) e[sd + i] = diag_i == i ? 0.f : e[sd + i];
+        }
+        half8 eh, el;
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          half2v h, l;
+          split_pair(e[j], e[j + 1], one, h, l);
+          eh[j] = h.x;
+          eh[j + 1] = h.y;
+          el[j] = l.x;
+          el[j + 1] = l.y;
+        }
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, h8, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, l8, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(el, h8, acc[r], 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) ka[s][kk] = kan[s][kk];
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) kh[s][m] = khn[s][m];
+      }
+      vh = vhn;
+      vl = vln;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tot[r][i] += (double)acc[r][i];
+  }
+
+  const int n = lane & 15;
+  const int src = (lane & 48) + D;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (rb0 + r >= nrow_blocks) break;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double s = __shfl(tot[r][i], src);
+      const int64_t row = (int64_t)(rb0 + r) * 16 + 4 * (lane >> 4) + i;
+      double v = 0.0;
+      if (n < D) v = ((double)xc[row * D + n] * s - tot[r][i]) * out_scale;
+      else if (n == D) v = s * out_scale;
+      out[row * 16 + n] = (float)v;
+    }
+  }
+}
+
+// Operands of the FP16-split pair pass.
+struct PairF16Ops {
+  const float *QB, *KA;   // FP32 distance operands (FP32 distances)
+  const uint4 *QH, *KH;   // FP16 distance operands (FP16 distances)
+  const float *RN;        // row norms -kappa |x_I|^2 (FP16 distances)
+  const uint4 *VH;        // V highs, then lows at lo_off
+  int64_t lo_off;
+};
+
+template <int KK, int KQ, int RB>
+__global__ __launch_bounds__(256) void k_pair_mfma16(PairF16Ops ops, int nrow_blocks, int ncol_pairs,
+                                                     int pairs_per_split, const float *__restrict__ xc, int D,
+                                                     int exclude_self, const float *__restrict__ wscale, float one,
+                                                     float *__restrict__ partial, int64_t part_stride_rows,
+                                                     const int *__restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rb0 = ((int)blockIdx.x * 4 + wave) * RB;
+  const int p0 = (int)blockIdx.y * pairs_per_split;
+  const int p1 = min(ncol_pairs, p0 + pairs_per_split);
+  const double scale = (wscale != nullptr ? (double)*wscale : 1.0) * 0x1p-15;
+  pair_rows_f16<KK, KQ, RB>(ops.QB, ops.QH, ops.RN, nrow_blocks, ops.KA, ops.KH, ops.VH, ops.lo_off, p0, p1, xc, D,
+                            exclude_self, scale, one, partial + (int64_t)blockIdx.y * part_stride_rows * 16, rb0);
+}
+
 // Batched ensembles: a persistent grid walks a static list of (ensemble, row
 // tile) items, sorted by decreasing cost, each over all of its ensemble's
 // columns (one split).  Operands of ensemble e start at padded particle
@@ -290,7 +504,8 @@ void launch_batch_pair(int rb, int grid, int KK, int D, const int2 *items, int n
 bool pair_shape_ok(const vds_tuning &t, int D) {
   if (D < 3 || D > kMaxD || D % 3 != 0) return false;
   if (t.col_splits < 1 || t.col_splits > kMaxSplits) return false;
-  if (t.impl == VDS_PAIR_MFMA) return t.rows_per_wave == 1 || t.rows_per_wave == 2 || t.rows_per_wave == 4;
+  if (t.impl == VDS_PAIR_MFMA || t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL)
+    return t.rows_per_wave == 1 || t.rows_per_wave == 2 || t.rows_per_wave == 4;
   return t.impl == VDS_PAIR_VALU;
 }
 
@@ -306,13 +521,48 @@ static void launch_mfma_kk(int rb, dim3 grid, const float *QB, int nrb, const fl
   }
 }
 
+template <int KK, int KQ>
+static void launch_mfma16_k(int rb, dim3 grid, const PairF16Ops &ops, int nrb, int ncp, int pps, const float *xc,
+                            int D, int ex, const float *wscale, float *partial, int64_t stride, const int *done,
+                            hipStream_t s) {
+  switch (rb) {
+    case 1: k_pair_mfma16<KK, KQ, 1><<<grid, 256, 0, s>>>(ops, nrb, ncp, pps, xc, D, ex, wscale, 1.f, partial, stride, done); break;
+    case 2: k_pair_mfma16<KK, KQ, 2><<<grid, 256, 0, s>>>(ops, nrb, ncp, pps, xc, D, ex, wscale, 1.f, partial, stride, done); break;
+    default: k_pair_mfma16<KK, KQ, 4><<<grid, 256, 0, s>>>(ops, nrb, ncp, pps, xc, D, ex, wscale, 1.f, partial, stride, done); break;
+  }
+}
+
 void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64_t nrow_blocks, const float *KA,
-                      const float *VB, int64_t ncol_chunks, const float *xc, bool exclude_self, float *partial,
-                      int64_t part_stride_rows, const int *done, hipStream_t s) {
+                      const float *VB, int64_t ncol_chunks, int64_t ncol_pad, const float *xc, bool exclude_self,
+                      const float *wscale, const F16Operands &f16, float *partial, int64_t part_stride_rows,
+                      const int *done, hipStream_t s) {
   const int ex = exclude_self ? 1 : 0;
   const int splits = t.col_splits;
   const int64_t cps = (ncol_chunks + splits - 1) / splits;
-  if (t.impl == VDS_PAIR_MFMA) {
+  if (t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL) {
+    // chunk pairs; the second chunk of the last pair lies inside the padding
+    // (ncol_pad is a multiple of 32 columns), whose V is zero
+    const int64_t ncp = (ncol_chunks + 1) / 2;
+    const int64_t pps = (ncp + splits - 1) / splits;
+    PairF16Ops ops{QB, KA, reinterpret_cast<const uint4 *>(f16.QH), reinterpret_cast<const uint4 *>(f16.KH), f16.RN,
+                   reinterpret_cast<const uint4 *>(VB), ncol_pad / 32 * 64};  // lows follow the highs
+    const int rb = t.rows_per_wave;
+    dim3 grid((unsigned)((nrow_blocks + 4 * rb - 1) / (4 * rb)), (unsigned)splits);
+    const int nrb = (int)nrow_blocks, np = (int)ncp, pp = (int)pps;
+    if (t.impl == VDS_PAIR_MFMA_F16X2_ALL) {
+      if (f16_slices(D) == 1)
+        launch_mfma16_k<0, 1>(rb, grid, ops, nrb, np, pp, xc, D, ex, wscale, partial, part_stride_rows, done, s);
+      else
+        launch_mfma16_k<0, 2>(rb, grid, ops, nrb, np, pp, xc, D, ex, wscale, partial, part_stride_rows, done, s);
+    } else {
+      switch (KK) {
+        case 2: launch_mfma16_k<2, 0>(rb, grid, ops, nrb, np, pp, xc, D, ex, wscale, partial, part_stride_rows, done, s); break;
+        case 3: launch_mfma16_k<3, 0>(rb, grid, ops, nrb, np, pp, xc, D, ex, wscale, partial, part_stride_rows, done, s); break;
+        case 4: launch_mfma16_k<4, 0>(rb, grid, ops, nrb, np, pp, xc, D, ex, wscale, partial, part_stride_rows, done, s); break;
+        default: launch_mfma16_k<5, 0>(rb, grid, ops, nrb, np, pp, xc, D, ex, wscale, partial, part_stride_rows, done, s); break;
+      }
+    }
+  } else if (t.impl == VDS_PAIR_MFMA) {
     const int rb = t.rows_per_wave;
     dim3 grid((unsigned)((nrow_blocks + 4 * rb - 1) / (4 * rb)), (unsigned)splits);
     switch (KK) {

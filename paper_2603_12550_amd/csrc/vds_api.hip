@@ -46,24 +46,34 @@ hipEvent_t get_event(vds_ctx c) {
 int64_t ncol_chunks(const vds_ctx c) { return (c->prob.P + 15) / 16; }
 
 // One pair pass over all particle rows with the V operand `V`.
-void pair_pass(vds_ctx c, const float *V, const int *done) {
+// `wscale` is the weight maximum the FP16-split V operand was divided by
+// (pass A), or NULL (pass B: its weights w_J / S_J are at most one already).
+void pair_pass(vds_ctx c, const float *V, const float *wscale, const int *done) {
   const int64_t nrb = c->ep.Ppad / 16;
   const double pairs = (double)c->prob.P * (double)c->prob.P;
   timed(c, VDS_TIMER_PAIR, pairs, [&] {
-    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->QB, nrb, c->KA, V, ncol_chunks(c), c->xc, true, c->part, c->ep.Ppad,
-                     done, c->stream);
+    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->QB, nrb, c->KA, V, ncol_chunks(c), c->ep.Ppad, c->xc, true,
+                     wscale, c->f16, c->part, c->ep.Ppad, done, c->stream);
   });
+}
+
+// Keeps the operand format the prep and finalisation kernels write in step
+// with the pair implementation.
+void apply_tuning(vds_ctx c, const vds_tuning &t) {
+  c->tune = t;
+  c->ep.vhalf = (t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
+  c->ep.qhalf = t.impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
 }
 
 void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done) {
   const EvalParams &e = c->ep;
   launch_mean_partials(e, q, w, c->meanp, done, c->stream);
-  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, done, c->stream);
-  pair_pass(c, c->VA, done);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done, c->stream);
+  pair_pass(c, c->VA, c->wscale, done);
   launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
 }
 
-void eval_pass_b(vds_ctx c, const int *done) { pair_pass(c, c->VB, done); }
+void eval_pass_b(vds_ctx c, const int *done) { pair_pass(c, c->VB, nullptr, done); }
 
 }  // namespace vds
 
@@ -123,6 +133,10 @@ Layout make_layout(const vds_problem &p) {
   L.redout = take(sizeof(double) * 16);
   L.ctrl = take(sizeof(Ctrl));
   L.blockmax = take(sizeof(float) * 2 * nblk);
+  L.wscale = take(sizeof(float) * 4);
+  L.QH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
+  L.KH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
+  L.RN = take(sizeof(float) * Ppad);
   L.qstar = take(sizeof(float) * p.P * D);
   L.xb0 = take(sizeof(float) * p.P * D);
   L.xb1 = take(sizeof(float) * p.P * D);
@@ -150,6 +164,8 @@ void fill_params(vds_ctx c) {
   e.potential = p.potential;
   e.uniform_w = (float)(1.0 / (double)p.P);
   e.log_norm = (float)(0.5 * e.D * std::log(2.0 * M_PI * p.h * p.h));
+  e.KQ = f16_slices(e.D);
+  e.cs = (float)std::sqrt(2.0 * 1.4426950408889634 / (2.0 * p.h * p.h));
   c->nblk = (int)((p.P + kRedBlock - 1) / kRedBlock);
   c->nblk_comb = (int)((p.P * 16 + kRedBlock - 1) / kRedBlock);
 }
@@ -288,6 +304,8 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->redout = reinterpret_cast<double *>(c->ws + L.redout);
   c->ctrl = reinterpret_cast<Ctrl *>(c->ws + L.ctrl);
   c->blockmax = reinterpret_cast<float *>(c->ws + L.blockmax);
+  c->wscale = reinterpret_cast<float *>(c->ws + L.wscale);
+  c->f16 = F16Operands{c->ws + L.QH, c->ws + L.KH, reinterpret_cast<float *>(c->ws + L.RN)};
   c->qstar = reinterpret_cast<float *>(c->ws + L.qstar);
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
   c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);
@@ -297,7 +315,7 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
 vds_status vds_set_tuning(vds_ctx c, const vds_tuning *t) {
   if (c == nullptr || t == nullptr) return VDS_ERR_ARG;
   if (!pair_shape_ok(*t, c->ep.D)) return set_err(c, VDS_ERR_ARG, "invalid tuning");
-  c->tune = *t;
+  apply_tuning(c, *t);
   return VDS_OK;
 }
 
@@ -422,16 +440,16 @@ vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float
   if (ny == 0) return VDS_OK;
   const EvalParams &e = c->ep;
   launch_mean_partials(e, q, w, c->meanp, nullptr, c->stream);
-  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, nullptr, c->stream);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr, c->stream);
   const float norm = (float)std::pow(2.0 * M_PI * c->prob.h * c->prob.h, -0.5 * e.D);
   // foreign rows go through the Q-operand buffer in blocks of Ppad rows
   for (int64_t r0 = 0; r0 < ny; r0 += e.Ppad) {
     const int64_t nr = std::min<int64_t>(e.Ppad, ny - r0);
-    launch_density_rows(e, y + r0 * e.D, nr, c->meanp, c->nblk, c->QB, c->stream);
+    launch_density_rows(e, y + r0 * e.D, nr, c->meanp, c->nblk, c->QB, &c->f16, c->stream);
     const int64_t nrb = round_up(nr, kRowAlign) / 16;
     timed(c, VDS_TIMER_PAIR, (double)nr * (double)c->prob.P, [&] {
-      launch_pair_pass(c->tune, e.KK, e.D, c->QB, nrb, c->KA, c->VA, ncol_chunks(c), c->xc, false, c->part, e.Ppad,
-                       nullptr, c->stream);
+      launch_pair_pass(c->tune, e.KK, e.D, c->QB, nrb, c->KA, c->VA, ncol_chunks(c), e.Ppad, c->xc, false,
+                       c->wscale, c->f16, c->part, e.Ppad, nullptr, c->stream);
     });
     launch_density_out(e, c->part, c->tune.col_splits, nr, norm, f + r0, c->stream);
   }
@@ -463,27 +481,32 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
   vds_status st = ready(c);
   if (st != VDS_OK) return st;
   if (!q) return set_err(c, VDS_ERR_ARG, "null state");
-  const EvalParams &e = c->ep;
-  launch_mean_partials(e, q, w, c->meanp, nullptr, c->stream);
-  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, nullptr, c->stream);
   hipEvent_t a = get_event(c), b = get_event(c);
   vds_tuning best = c->tune;
   float best_ms = 1e30f;
   const int splits_list[] = {1, 2, 4, 8, 16, 32};
   const int rb_list[] = {1, 2, 4};
   std::vector<vds_tuning> cands;
-  for (int rb : rb_list)
-    for (int sp : splits_list) cands.push_back(vds_tuning{VDS_PAIR_MFMA, rb, sp, 0});
+  for (int impl : {VDS_PAIR_MFMA, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL})
+    for (int rb : rb_list)
+      for (int sp : splits_list) cands.push_back(vds_tuning{impl, rb, sp, 0});
   for (int sp : splits_list) cands.push_back(vds_tuning{VDS_PAIR_VALU, 1, sp, 0});
   const bool was_timing = c->timing;
   c->timing = false;
+  int prepared = -1;
   for (const vds_tuning &t : cands) {
-    if (!pair_shape_ok(t, e.D)) continue;
-    c->tune = t;
-    pair_pass(c, c->VA, nullptr);  // warm-up
+    if (!pair_shape_ok(t, c->ep.D)) continue;
+    apply_tuning(c, t);
+    if (c->ep.vhalf + 2 * c->ep.qhalf != prepared) {  // operand formats follow the implementation
+      launch_mean_partials(c->ep, q, w, c->meanp, nullptr, c->stream);
+      launch_prep(c->ep, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr,
+                  c->stream);
+      prepared = c->ep.vhalf + 2 * c->ep.qhalf;
+    }
+    pair_pass(c, c->VA, c->wscale, nullptr);  // warm-up
     (void)hipEventRecord(a, c->stream);
     const int reps = 3;
-    for (int r = 0; r < reps; ++r) pair_pass(c, c->VA, nullptr);
+    for (int r = 0; r < reps; ++r) pair_pass(c, c->VA, c->wscale, nullptr);
     (void)hipEventRecord(b, c->stream);
     st = hip_check(c, hipEventSynchronize(b), "autotune");
     if (st != VDS_OK) break;
@@ -497,7 +520,7 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
   c->timing = was_timing;
   c->event_pool.push_back(a);
   c->event_pool.push_back(b);
-  c->tune = best;
+  apply_tuning(c, best);
   return st;
 }
 

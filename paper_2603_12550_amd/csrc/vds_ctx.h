@@ -9,7 +9,7 @@
 namespace vds {
 
 struct Layout {
-  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, qstar, xb0, xb1, total;
+  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, qstar, xb0, xb1, total;
 };
 
 struct TimerAcc {
@@ -37,7 +37,8 @@ struct vds_ctx_s {
   std::vector<hipEvent_t> event_pool;
 
   // workspace views
-  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *qstar, *xb[2], *blockmax;
+  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *qstar, *xb[2], *blockmax, *wscale;
+  vds::F16Operands f16{};
   double *meanp, *redp, *redout;
   vds::Ctrl *ctrl;
   int nblk;       // blocks of the one-thread-per-particle kernels

@@ -43,6 +43,21 @@ struct EvalParams {
   int potential;
   float uniform_w;    // 1 / P
   float log_norm;     // (D/2) log(2 pi h^2)
+  int vhalf;          // V operands as FP16 high/low halves (FP16-split products), weights over their maximum
+  int qhalf;          // FP16 distance operands QH/KH and row norms RN written too (VDS_PAIR_MFMA_F16X2_ALL)
+  int KQ;             // FP16 distance slices of 32 products: f16_slices(D)
+  float cs;           // sqrt(2 kappa): the distance operands are cs x
+};
+
+// FP16 MFMA slices (32 products each) of the split distance product: three
+// per configuration component and two for the column norm.
+__host__ __device__ constexpr int f16_slices(int D) { return (3 * D + 2 + 31) / 32; }
+
+// Workspace of the FP16 distance operands (see pair_kernels.hip).
+struct F16Operands {
+  void *QH;   // [Ppad / 16][KQ][64 lanes][8] halves, row side
+  void *KH;   // same layout, column side
+  float *RN;  // [Ppad] -kappa |x_I|^2
 };
 
 // One ensemble of a batch: its problem parameters and where its particles sit
@@ -62,10 +77,13 @@ enum CombineMode { MODE_TERMS = 0, MODE_VELOCITY = 1, MODE_EXPLICIT = 2, MODE_PI
 // ---- launchers (pair_kernels.hip) ----
 // Writes partial[split][row][0..D) = sum_J e wh (x_row - x_J) and [D] = sum_J e wh,
 // J = row left out when exclude_self (rows are the particles themselves).
-// `xc` holds the centred row coordinates the difference sums use.
+// `xc` holds the centred row coordinates the difference sums use; ncol_pad is
+// the padded column count the V operand was written for.  With the FP16-split
+// implementation the V weights were divided by *wscale (NULL: by one), which
+// the pass multiplies back.
 void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64_t nrow_blocks,
-                      const float *KA, const float *VB, int64_t ncol_chunks, const float *xc, bool exclude_self,
-                      float *partial,
+                      const float *KA, const float *VB, int64_t ncol_chunks, int64_t ncol_pad, const float *xc,
+                      bool exclude_self, const float *wscale, const F16Operands &f16, float *partial,
                       int64_t part_stride_rows, const int *done, hipStream_t s);
 bool pair_shape_ok(const vds_tuning &t, int D);
 // Batched pair pass over the (ensemble, row tile) work list `items` with a
@@ -76,8 +94,12 @@ void launch_batch_pair(int rb, int grid, int KK, int D, const int2 *items, int n
 
 // ---- launchers (local_kernels.hip) ----
 void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done, hipStream_t s);
+// With p.vhalf, VA is written as FP16 halves (see pair_kernels.hip) with the
+// weights divided by their maximum, which goes to *wscale; with p.qhalf the
+// FP16 distance operands and row norms too (f16 may be null otherwise).
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp,
-                 float *xc, float *wv, float *QB, float *KA, float *VA, const int *done, hipStream_t s);
+                 float *xc, float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16,
+                 const int *done, hipStream_t s);
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
@@ -89,7 +111,7 @@ void launch_picard_check(Ctrl *ctrl, const float *blockmax, int nblk, float rtol
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s);
 void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,
-                         float *QB, hipStream_t s);
+                         float *QB, const F16Operands *f16, hipStream_t s);
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm,
                         float *f, hipStream_t s);
 void launch_copy(const float *src, float *dst, int64_t n, const int *done_flag_or_null, hipStream_t s);

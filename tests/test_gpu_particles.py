@@ -7,6 +7,8 @@ Tolerances (float32 GPU vs float64 oracle on the same float32 inputs):
     (for v the denominator is max(||v||, ||(1/zeta)(A (x) I) grad Psi||), since
     the total velocity can nearly vanish at steady state)
   stress: relative Frobenius 1e-4; energy terms: 1e-5 of their magnitude
+The same bounds hold for every pair implementation, the FP16-split ones
+included (their products keep about 22 significant bits).
 """
 import math
 import sys
@@ -46,7 +48,10 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
-TUNINGS = [(0, 1, 1), (0, 2, 8), (0, 4, 3), (1, 1, 1), (1, 1, 5)]
+TUNINGS = [(0, 1, 1), (0, 2, 8), (0, 4, 3), (1, 1, 1), (1, 1, 5), (2, 1, 1), (2, 2, 8), (2, 4, 3),
+           (3, 1, 1), (3, 2, 8), (3, 4, 3)]
+# the default FP32 MFMA shape and the two FP16-split forms at a benchmark shape
+IMPLS = [None, (2, 4, 16), (3, 2, 16)]
 
 
 @pytest.mark.parametrize("P", [1, 2, 3, 17, 63, 64, 300])
@@ -115,27 +120,30 @@ def _velocity_check(lib, cfg, rows=None, tuning=None, threads=8):
     return err, diag, ctx
 
 
-def test_velocity_dumbbell_full_size(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_velocity_dumbbell_full_size(lib, tuning):
     cfg = wl.dumbbell_shear()  # P = 2000, D = 3, h = 0.3
-    _say("velocity dumbbell P=2000")
-    err, diag, _ = _velocity_check(lib, cfg)
+    _say(f"velocity dumbbell P=2000 tuning {tuning}")
+    err, diag, _ = _velocity_check(lib, cfg, tuning=tuning)
     assert err < 1e-5, err
 
 
-def test_velocity_chain4_full_size_sampled_rows(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_velocity_chain4_full_size_sampled_rows(lib, tuning):
     cfg = wl.chain4_shear()  # P = 20000, D = 9, h = 0.4
     rows = np.random.default_rng(0).choice(cfg["P"], 256, replace=False)
     rows = np.concatenate([rows, [0, cfg["P"] - 1]])
-    _say("velocity chain4 P=20000 sampled rows")
-    err, _, _ = _velocity_check(lib, cfg, rows=rows)
+    _say(f"velocity chain4 P=20000 sampled rows tuning {tuning}")
+    err, _, _ = _velocity_check(lib, cfg, rows=rows, tuning=tuning)
     assert err < 1e-5, err
 
 
-def test_velocity_fene_chain6_sampled_rows(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_velocity_fene_chain6_sampled_rows(lib, tuning):
     cfg = wl.fene_chain6(P=6000)
     rows = np.random.default_rng(1).choice(cfg["P"], 200, replace=False)
-    _say("velocity FENE chain6 P=6000")
-    err, _, _ = _velocity_check(lib, cfg, rows=rows)
+    _say(f"velocity FENE chain6 P=6000 tuning {tuning}")
+    err, _, _ = _velocity_check(lib, cfg, rows=rows, tuning=tuning)
     assert err < 1e-5, err
 
 
@@ -165,7 +173,8 @@ def test_energy_dissipation_work_match_oracle(lib):
     assert abs(W - W_o) / (abs(W_o) + 1e-3 * D_o) < 1e-4
 
 
-def test_implicit_steps_match_oracle_trajectory(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_implicit_steps_match_oracle_trajectory(lib, tuning):
     cfg = wl.chain4_shear(P=3000, seed=12)
     prob = ovds.problem_from(cfg)
     P = cfg["P"]
@@ -174,8 +183,10 @@ def test_implicit_steps_match_oracle_trajectory(lib):
     qo = wl.f32_as_f64(q32)
     qg = _dev(q32)
     ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
     for s in range(5):
-        _say(f"implicit step {s} chain4 P=3000")
+        _say(f"implicit step {s} chain4 P=3000 tuning {tuning}")
         d = ctx.step(qg)
         qo, m = ovds.step_implicit(qo, w, prob, threads=8)
         assert 1 <= d["last_iters"] <= 10
@@ -184,7 +195,8 @@ def test_implicit_steps_match_oracle_trajectory(lib):
         assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
-def test_implicit_dumbbell_trajectory_and_stress(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_implicit_dumbbell_trajectory_and_stress(lib, tuning):
     cfg = wl.dumbbell_shear()
     prob = ovds.problem_from(cfg)
     P = cfg["P"]
@@ -193,8 +205,10 @@ def test_implicit_dumbbell_trajectory_and_stress(lib):
     qo = wl.f32_as_f64(q32)
     qg = _dev(q32)
     ctx = _ctx(lib, 1, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
     for s in range(6):
-        _say(f"implicit step {s} dumbbell P=2000")
+        _say(f"implicit step {s} dumbbell P=2000 tuning {tuning}")
         d = ctx.step(qg)
         qo, _ = ovds.step_implicit(qo, w, prob, threads=8)
         assert _rel(qg.cpu().numpy(), qo) < 1e-5
@@ -202,7 +216,8 @@ def test_implicit_dumbbell_trajectory_and_stress(lib):
         assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
-def test_explicit_steps_match_oracle_fene(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_explicit_steps_match_oracle_fene(lib, tuning):
     cfg = wl.fene_chain6(P=700)
     prob = ovds.problem_from(cfg)
     P = cfg["P"]
@@ -212,13 +227,17 @@ def test_explicit_steps_match_oracle_fene(lib):
     qg = _dev(q32)
     ctx = _ctx(lib, 5, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme="explicit", potential="fene",
                b_max=cfg["b_max"])
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    _say(f"explicit steps FENE chain6 P=700 tuning {tuning}")
     ctx.step(qg, nsteps=4)
     for _ in range(4):
         qo = ovds.step_explicit(qo, w, prob)
     assert _rel(qg.cpu().numpy(), qo) < 1e-5
 
 
-def test_implicit_step_full_size_solves_the_implicit_equation(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_implicit_step_full_size_solves_the_implicit_equation(lib, tuning):
     # chain4 at P = 20000: one implicit step on the GPU; on sampled rows the
     # oracle checks (q+ - q*)/dt = u(q+) with q* = q + dt G q (Appendix A)
     cfg = wl.chain4_shear()
@@ -229,7 +248,9 @@ def test_implicit_step_full_size_solves_the_implicit_equation(lib):
     q0 = wl.f32_as_f64(q32)
     qg = _dev(q32)
     ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
-    _say("implicit step chain4 P=20000")
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    _say(f"implicit step chain4 P=20000 tuning {tuning}")
     d = ctx.step(qg)
     assert 2 <= d["last_iters"] <= 8
     qp = qg.cpu().numpy().astype(np.float64)
@@ -246,7 +267,8 @@ def test_implicit_step_full_size_solves_the_implicit_equation(lib):
     assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
-def test_density_at_grid_points(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_density_at_grid_points(lib, tuning):
     # Appendix A density on the {-2, 0, 2}^D grid (D = 6 here: 729 points)
     nb, P, h = 2, 900, 0.5
     q32 = wl.to_f32(wl.gaussian_bonds(17, nb, P, 1.0))
@@ -254,14 +276,20 @@ def test_density_at_grid_points(lib):
     grid = np.array(np.meshgrid(*[[-2.0, 0.0, 2.0]] * (3 * nb), indexing="ij")).reshape(3 * nb, -1).T
     f_o = ovds.density_at(grid, q, ovds.uniform_weights(P), h)
     ctx = _ctx(lib, nb, P, h)
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    _say(f"density at grid points tuning {tuning}")
     f = ctx.density_at(_dev(q32), _dev(grid)).cpu().numpy()
     assert np.linalg.norm(f - f_o) / np.linalg.norm(f_o) < 1e-5
 
 
-def test_runs_are_bitwise_deterministic(lib):
+@pytest.mark.parametrize("tuning", IMPLS)
+def test_runs_are_bitwise_deterministic(lib, tuning):
     cfg = wl.chain4_shear(P=4000, seed=4)
     q32 = wl.to_f32(cfg["q0"])
     ctx = _ctx(lib, 3, cfg["P"], cfg["h"], H=cfg["H"], G=cfg["G"])
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
     a = ctx.velocity(_dev(q32)).cpu().numpy()
     b = ctx.velocity(_dev(q32)).cpu().numpy()
     assert np.array_equal(a, b)
@@ -272,7 +300,7 @@ def test_autotune_picks_a_valid_shape(lib):
     q32 = wl.to_f32(cfg["q0"])
     ctx = _ctx(lib, 3, cfg["P"], cfg["h"], H=cfg["H"], G=cfg["G"])
     t = ctx.autotune(_dev(q32))
-    assert t["impl"] in (0, 1) and 1 <= t["col_splits"] <= 32
+    assert t["impl"] in (0, 1, 2, 3) and 1 <= t["col_splits"] <= 32
     err, _, _ = _velocity_check(lib, cfg, tuning=(t["impl"], t["rows_per_wave"], t["col_splits"]))
     assert err < 1e-5
 
