@@ -62,6 +62,28 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
+PAIR_KERNEL = {0: "k_pair_mfma", 1: "k_pair_valu", 2: "k_pair_mfma16", 3: "k_pair_mfma16"}
+# v_exp_f32 issues at a quarter of the FP32 lane rate: 8 lanes per cycle per SIMD
+EXP_PER_S = 256 * 4 * 8 * 2.4e9
+PEAK_FP16_TFLOPS = 2500.0
+
+
+def secondary_ceilings(impl: int, D: int, pairs_per_s: float):
+    """Ceilings besides the FP32 rate: one exp per pair-eval on the
+    transcendental unit, and for the FP16-split kernels the FP16 matrix-core
+    rate over the FP16 MFMA work each pair-eval costs there."""
+    out = {"exp_unit": {"pair_evals_per_s": EXP_PER_S, "frac": pairs_per_s / EXP_PER_S}}
+    if impl in (2, 3):
+        slices = (3 * D + 2 + 31) // 32 if impl == 3 else 0
+        # per 16x16 tile: the weighted sums take 1.5 FP16 MFMAs (3 per 32 columns);
+        # distances take `slices` FP16 MFMAs (impl 3) or FP32 MFMAs (impl 2, not counted here)
+        fp16_flop_per_pair = (1.5 + slices) * 16 * 16 * 32 * 2 / 256
+        cap = PEAK_FP16_TFLOPS * 1e12 / fp16_flop_per_pair
+        out["fp16_mfma"] = {"fp16_flop_per_pair": fp16_flop_per_pair, "pair_evals_per_s": cap,
+                            "frac": pairs_per_s / cap}
+    return out
+
+
 def measured_traffic(kernel: str, tuning: dict, P: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
     if it was taken on the current kernel source and the same launch shape."""
@@ -181,6 +203,7 @@ def measure_batched(pkg, wl, torch, steps):
         e = int(e)
         ctx = pkg.Context(3, int(ens["P"][e]), ens["h"][e], G=G[e], dt=ens["dt"], scheme="explicit")
         qe = states[e].clone()
+        ctx.autotune(qe)
         ctx.step(qe, nsteps=1)
         qe = states[e].clone()
         torch.cuda.synchronize()
@@ -397,10 +420,11 @@ def main():
         "roofline": {"bound": "mfma" if tune["impl"] == 0 else "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic("k_pair_mfma" if tune["impl"] == 0 else "k_pair_valu", tune, P),
-                     "kernel": "k_pair_mfma" if tune["impl"] == 0 else "k_pair_valu",
+                     "traffic": measured_traffic(PAIR_KERNEL[tune["impl"]], tune, P),
+                     "kernel": PAIR_KERNEL[tune["impl"]],
                      "avg_launch_ms": avg_ms, "launches": tim["launches"],
-                     "flop_per_launch": flop_launch, "flop_per_pair": flops_per_pair(D)},
+                     "flop_per_launch": flop_launch, "flop_per_pair": flops_per_pair(D),
+                     "secondary_ceilings": secondary_ceilings(tune["impl"], D, P * P / (avg_ms * 1e-3))},
     }
 
     if args.t_end:

@@ -96,8 +96,9 @@ _sigs.update({
     "vds_batch_destroy": ([_P], None),
     "vds_batch_last_error": ([_P], C.c_char_p),
     "vds_batch_state_offset": ([_P, C.c_int32], C.c_int64),
-    "vds_batch_set_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
-    "vds_batch_get_tuning": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "vds_batch_set_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "vds_batch_get_tuning": ([_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32)], C.c_int),
     "vds_batch_autotune": ([_P, _P], C.c_int),
     "vds_batch_step": ([_P, _P, C.c_int32, C.POINTER(C.c_double)], C.c_int),
 })
@@ -380,13 +381,17 @@ class Batch:
     def unpack(self, q):
         return [q[self.offsets[e]:self.offsets[e + 1]].reshape(self.nb, int(self.P[e]), 3) for e in range(self.nens)]
 
-    def set_tuning(self, rows_per_wave=2, grid=1024, use_graph=True):
-        _bcheck(_lib.vds_batch_set_tuning(self.b, int(rows_per_wave), int(grid), 1 if use_graph else 0), self.b)
+    def set_tuning(self, rows_per_wave=2, grid=1024, use_graph=True, impl=None):
+        """impl None keeps the current pair implementation."""
+        if impl is None:
+            impl = self.get_tuning()["impl"]
+        _bcheck(_lib.vds_batch_set_tuning(self.b, int(impl), int(rows_per_wave), int(grid), 1 if use_graph else 0),
+                self.b)
 
     def get_tuning(self):
-        rb, g, u = C.c_int32(), C.c_int32(), C.c_int32()
-        _bcheck(_lib.vds_batch_get_tuning(self.b, C.byref(rb), C.byref(g), C.byref(u)), self.b)
-        return dict(rows_per_wave=rb.value, grid=g.value, use_graph=u.value)
+        im, rb, g, u = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _bcheck(_lib.vds_batch_get_tuning(self.b, C.byref(im), C.byref(rb), C.byref(g), C.byref(u)), self.b)
+        return dict(impl=im.value, rows_per_wave=rb.value, grid=g.value, use_graph=u.value)
 
     def autotune(self, q):
         _bcheck(_lib.vds_batch_autotune(self.b, _ptr(q)), self.b)

@@ -20,7 +20,7 @@ namespace {
 thread_local std::string g_batch_create_error;
 
 struct BatchLayout {
-  size_t ens, blk16, blk256, items, QB, KA, VA, VB, xc, t1, S, wv, part, meanp, redp, tau, total;
+  size_t ens, blk16, blk256, items, QB, KA, VA, VB, QH, KH, RN, xc, t1, S, wv, part, meanp, redp, tau, total;
 };
 
 }  // namespace
@@ -35,18 +35,19 @@ struct vds_batch_s {
   char *ws = nullptr;
   hipStream_t user = nullptr, priv = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  int rb = 2, grid = 1024, use_graph = 1;
+  int impl = VDS_PAIR_MFMA_F16X2_ALL, rb = 2, grid = 1024, use_graph = 1;
   int nitems = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const float *graph_q = nullptr;  // state pointer the graph was captured for
-  int graph_rb = 0, graph_grid = 0;
+  int graph_impl = -1, graph_rb = 0, graph_grid = 0;
   std::string err;
 
   EnsDesc *d_ens;
   int *d_blk16, *d_blk256;
   int2 *d_items;
   float *QB, *KA, *VA, *VB, *xc, *t1, *S, *wv, *part;
+  F16Operands f16{};
   double *meanp, *redp, *tau;
 };
 
@@ -87,6 +88,9 @@ BatchLayout batch_layout(int nens, const int64_t *P, int nb) {
   L.KA = take(sizeof(float) * Ptot * KK * 4);
   L.VA = take(sizeof(float) * Ptot * 16);
   L.VB = take(sizeof(float) * Ptot * 16);
+  L.QH = take(sizeof(uint16_t) * Ptot * 32 * f16_slices(D));
+  L.KH = take(sizeof(uint16_t) * Ptot * 32 * f16_slices(D));
+  L.RN = take(sizeof(float) * Ptot);
   L.xc = take(sizeof(float) * Ptot * D);
   L.t1 = take(sizeof(float) * Ptot * D);
   L.S = take(sizeof(float) * Ptot);
@@ -130,11 +134,29 @@ BatchView view(vds_batch b) {
   v.nblk256 = (int)(b->Ptot_pad / 256);
   v.D = b->D;
   v.KK = b->KK;
+  v.f16 = b->f16;
   return v;
 }
 
-void pair_pass(vds_batch b, const float *V, hipStream_t s) {
-  launch_batch_pair(b->rb, b->grid, b->KK, b->D, b->d_items, b->nitems, b->d_ens, b->QB, b->KA, V, b->xc, b->part, s);
+// Operand formats of the ensembles follow the pair implementation.
+void set_formats(vds_batch b) {
+  for (EnsDesc &d : b->ens) {
+    d.p.vhalf = (b->impl == VDS_PAIR_MFMA_F16X2 || b->impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
+    d.p.qhalf = b->impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
+  }
+}
+
+vds_status upload_ens(vds_batch b) {
+  set_formats(b);
+  vds_status st = bhip(b, hipMemcpyAsync(b->d_ens, b->ens.data(), sizeof(EnsDesc) * b->nens, hipMemcpyHostToDevice,
+                                         b->priv), "upload ensembles");
+  if (st == VDS_OK) st = bhip(b, hipStreamSynchronize(b->priv), "synchronise");
+  return st;
+}
+
+void pair_pass(vds_batch b, const float *V, bool pass_a, hipStream_t s) {
+  launch_batch_pair(b->impl, b->rb, b->grid, b->KK, b->D, b->d_items, b->nitems, b->d_ens, b->QB, b->KA, V, b->f16,
+                    pass_a, b->xc, b->part, s);
 }
 
 // Centring, packing and pass A (through its finalisation) of every ensemble.
@@ -142,13 +164,13 @@ void pass_a(vds_batch b, const float *q, hipStream_t s) {
   const BatchView v = view(b);
   launch_batch_mean(v, q, b->meanp, s);
   launch_batch_prep(v, q, b->meanp, b->xc, b->wv, b->QB, b->KA, b->VA, s);
-  pair_pass(b, b->VA, s);
+  pair_pass(b, b->VA, true, s);
   launch_batch_finalize_a(v, b->part, b->xc, b->wv, b->S, b->t1, b->VB, s);
 }
 
 void one_step(vds_batch b, float *q, hipStream_t s) {
   pass_a(b, q, s);
-  pair_pass(b, b->VB, s);
+  pair_pass(b, b->VB, false, s);
   launch_batch_explicit(view(b), b->part, b->xc, b->t1, b->S, b->wv, q, s);
 }
 
@@ -170,6 +192,7 @@ vds_status capture(vds_batch b, float *q) {
   st = bhip(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "instantiate graph");
   if (st != VDS_OK) return st;
   b->graph_q = q;
+  b->graph_impl = b->impl;
   b->graph_rb = b->rb;
   b->graph_grid = b->grid;
   return VDS_OK;
@@ -240,6 +263,8 @@ vds_status vds_batch_create(int32_t nens, const int64_t *P, const double *h, con
     p.potential = c.potential;
     p.uniform_w = (float)(1.0 / (double)P[e]);
     p.log_norm = (float)(0.5 * b->D * std::log(2.0 * M_PI * h[e] * h[e]));
+    p.KQ = f16_slices(b->D);
+    p.cs = (float)std::sqrt(2.0 * 1.4426950408889634 / (2.0 * h[e] * h[e]));
     d.pad_off = pad_off;
     d.q_off = q_off;
     d.blk16 = (int)(pad_off / 16);
@@ -278,6 +303,7 @@ vds_status vds_batch_bind_workspace(vds_batch b, void *ws, size_t bytes) {
   b->S = f(L.S);
   b->wv = f(L.wv);
   b->part = f(L.part);
+  b->f16 = F16Operands{b->ws + L.QH, b->ws + L.KH, f(L.RN)};
   b->meanp = reinterpret_cast<double *>(b->ws + L.meanp);
   b->redp = reinterpret_cast<double *>(b->ws + L.redp);
   b->tau = reinterpret_cast<double *>(b->ws + L.tau);
@@ -289,6 +315,7 @@ vds_status vds_batch_bind_workspace(vds_batch b, void *ws, size_t bytes) {
     if (st != VDS_OK) return st;
   }
   drop_graph(b);
+  set_formats(b);
   st = bhip(b, hipMemcpyAsync(b->d_ens, b->ens.data(), sizeof(EnsDesc) * b->nens, hipMemcpyHostToDevice, b->priv),
             "upload ensembles");
   if (st == VDS_OK)
@@ -317,20 +344,27 @@ int64_t vds_batch_state_offset(vds_batch b, int32_t e) {
   return e == b->nens ? b->qlen : b->ens[e].q_off;
 }
 
-vds_status vds_batch_set_tuning(vds_batch b, int32_t rb, int32_t grid, int32_t use_graph) {
+vds_status vds_batch_set_tuning(vds_batch b, int32_t impl, int32_t rb, int32_t grid, int32_t use_graph) {
   if (b == nullptr) return VDS_ERR_ARG;
+  if (impl != VDS_PAIR_MFMA && impl != VDS_PAIR_MFMA_F16X2 && impl != VDS_PAIR_MFMA_F16X2_ALL)
+    return berr(b, VDS_ERR_ARG, "impl must be VDS_PAIR_MFMA or one of the FP16-split forms");
   if (!(rb == 1 || rb == 2 || rb == 4) || grid < 1 || grid > (1 << 20))
     return berr(b, VDS_ERR_ARG, "rows_per_wave must be 1, 2 or 4 and grid >= 1");
   const bool items_change = rb != b->rb;
+  const bool impl_change = impl != b->impl;
+  b->impl = impl;
   b->rb = rb;
   b->grid = grid;
   b->use_graph = use_graph ? 1 : 0;
-  if (items_change && b->ws) return upload_items(b);
-  return VDS_OK;
+  vds_status st = VDS_OK;
+  if (impl_change && b->ws) st = upload_ens(b);
+  if (st == VDS_OK && items_change && b->ws) st = upload_items(b);
+  return st;
 }
 
-vds_status vds_batch_get_tuning(vds_batch b, int32_t *rb, int32_t *grid, int32_t *use_graph) {
+vds_status vds_batch_get_tuning(vds_batch b, int32_t *impl, int32_t *rb, int32_t *grid, int32_t *use_graph) {
   if (b == nullptr) return VDS_ERR_ARG;
+  if (impl) *impl = b->impl;
   if (rb) *rb = b->rb;
   if (grid) *grid = b->grid;
   if (use_graph) *use_graph = b->use_graph;
@@ -344,36 +378,42 @@ vds_status vds_batch_autotune(vds_batch b, const float *q) {
   vds_status st = bhip(b, hipEventRecord(b->ev_in, b->user), "event");
   if (st == VDS_OK) st = bhip(b, hipStreamWaitEvent(b->priv, b->ev_in, 0), "wait");
   if (st != VDS_OK) return st;
-  pass_a(b, q, b->priv);
   hipEvent_t t0, t1;
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
   float best = 1e30f;
-  int best_rb = b->rb, best_grid = b->grid;
-  for (int rb : {1, 2, 4}) {
-    for (int per_cu : {2, 4, 8}) {
-      st = vds_batch_set_tuning(b, rb, 256 * per_cu, b->use_graph);
-      if (st != VDS_OK) break;
-      pair_pass(b, b->VB, b->priv);  // warm-up
-      (void)hipEventRecord(t0, b->priv);
-      pair_pass(b, b->VB, b->priv);
-      (void)hipEventRecord(t1, b->priv);
-      st = bhip(b, hipEventSynchronize(t1), "autotune");
-      if (st != VDS_OK) break;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      if (ms < best) {
-        best = ms;
-        best_rb = rb;
-        best_grid = 256 * per_cu;
+  int best_impl = b->impl, best_rb = b->rb, best_grid = b->grid;
+  for (int impl : {VDS_PAIR_MFMA, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL}) {
+    st = vds_batch_set_tuning(b, impl, b->rb, b->grid, b->use_graph);
+    if (st != VDS_OK) break;
+    pass_a(b, q, b->priv);  // operands in this implementation's format
+    for (int rb : {1, 2, 4}) {
+      for (int per_cu : {2, 4, 8}) {
+        st = vds_batch_set_tuning(b, impl, rb, 256 * per_cu, b->use_graph);
+        if (st != VDS_OK) break;
+        pair_pass(b, b->VB, false, b->priv);  // warm-up
+        (void)hipEventRecord(t0, b->priv);
+        pair_pass(b, b->VB, false, b->priv);
+        (void)hipEventRecord(t1, b->priv);
+        st = bhip(b, hipEventSynchronize(t1), "autotune");
+        if (st != VDS_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        if (ms < best) {
+          best = ms;
+          best_impl = impl;
+          best_rb = rb;
+          best_grid = 256 * per_cu;
+        }
       }
+      if (st != VDS_OK) break;
     }
     if (st != VDS_OK) break;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (st != VDS_OK) return st;
-  return vds_batch_set_tuning(b, best_rb, best_grid, b->use_graph);
+  return vds_batch_set_tuning(b, best_impl, best_rb, best_grid, b->use_graph);
 }
 
 vds_status vds_batch_step(vds_batch b, float *q, int32_t nsteps, double *tau_host) {
@@ -384,7 +424,8 @@ vds_status vds_batch_step(vds_batch b, float *q, int32_t nsteps, double *tau_hos
   if (st == VDS_OK) st = bhip(b, hipStreamWaitEvent(b->priv, b->ev_in, 0), "wait");
   if (st != VDS_OK) return st;
   if (b->use_graph && nsteps > 0) {
-    if (b->exec == nullptr || b->graph_q != q || b->graph_rb != b->rb || b->graph_grid != b->grid) {
+    if (b->exec == nullptr || b->graph_q != q || b->graph_impl != b->impl || b->graph_rb != b->rb ||
+        b->graph_grid != b->grid) {
       st = capture(b, q);
       if (st != VDS_OK) return st;
     }

@@ -517,6 +517,14 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_mean(BatchView b, const flo
   mean_partials_body(d.p, blockIdx.x - d.blk256, q + d.q_off, nullptr, meanp + (int64_t)d.blk256 * 16);
 }
 
+// Ensemble d's slice of the concatenated FP16 distance operands.
+__device__ inline F16Operands batch_f16(const BatchView &b, const EnsDesc &d) {
+  if (!d.p.qhalf) return F16Operands{nullptr, nullptr, nullptr};
+  const int64_t halves = d.pad_off * 32 * d.p.KQ;
+  return F16Operands{reinterpret_cast<_Float16 *>(b.f16.QH) + halves, reinterpret_cast<_Float16 *>(b.f16.KH) + halves,
+                     b.f16.RN + d.pad_off};
+}
+
 __global__ __launch_bounds__(kRedBlock) void k_batch_prep(BatchView b, const float *__restrict__ q,
                                                           const double *__restrict__ meanp, float *__restrict__ xc,
                                                           float *__restrict__ wv, float *__restrict__ QB,
@@ -525,7 +533,7 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_prep(BatchView b, const flo
   const int64_t o = d.pad_off;
   prep_body(d.p, blockIdx.x - d.blk16, q + d.q_off, nullptr, meanp + (int64_t)d.blk256 * 16,
             (int)(d.p.Ppad / kRedBlock), xc + o * b.D, wv + o, QB + o * b.KK * 4, KA + o * b.KK * 4, VA + o * 16,
-            nullptr, F16Operands{nullptr, nullptr, nullptr});
+            nullptr, batch_f16(b, d));
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_batch_finalize_a(BatchView b, const float *__restrict__ partial,

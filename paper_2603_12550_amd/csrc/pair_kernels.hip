@@ -479,6 +479,40 @@ __global__ __launch_bounds__(256) void k_pair_valu(const float *__restrict__ QB,
   }
 }
 
+// Batched FP16-split variant over the same work list.  Pass A's V holds the
+// weights 1/P_e over their maximum 1/P_e, so its sums are scaled by 1/P_e.
+template <int KK, int KQ, int RB>
+__global__ __launch_bounds__(256) void k_batch_pair16(const int2 *__restrict__ items, int nitems,
+                                                      const EnsDesc *__restrict__ ens, PairF16Ops ops, int pass_a,
+                                                      const float *__restrict__ xc, int D, float one,
+                                                      float *__restrict__ partial) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 item = items[it];
+    const EnsDesc &d = ens[item.x];
+    const int64_t off = d.pad_off;
+    const int nrb = (int)(d.p.Ppad / 16);
+    const int ncp = (int)((d.p.P + 31) / 32);
+    const int rb0 = (item.y * 4 + wave) * RB;
+    const double scale = (pass_a ? (double)d.p.uniform_w : 1.0) * 0x1p-15;
+    const int64_t qoff = (off / 16) * KQ * 64;  // uint4 units of the distance operands
+    pair_rows_f16<KK, KQ, RB>(ops.QB + off * KK * 4, ops.QH + qoff, ops.RN + off, nrb, ops.KA + off * KK * 4,
+                              ops.KH + qoff, ops.VH + off * 4, d.p.Ppad * 2, 0, ncp, xc + off * D, D, 1, scale,
+                              one, partial + off * 16, rb0);
+  }
+}
+
+template <int KK, int KQ>
+static void launch_batch16_k(int rb, int grid, const int2 *items, int nitems, const EnsDesc *ens,
+                             const PairF16Ops &ops, int pass_a, const float *xc, int D, float *partial,
+                             hipStream_t s) {
+  switch (rb) {
+    case 1: k_batch_pair16<KK, KQ, 1><<<grid, 256, 0, s>>>(items, nitems, ens, ops, pass_a, xc, D, 1.f, partial); break;
+    case 2: k_batch_pair16<KK, KQ, 2><<<grid, 256, 0, s>>>(items, nitems, ens, ops, pass_a, xc, D, 1.f, partial); break;
+    default: k_batch_pair16<KK, KQ, 4><<<grid, 256, 0, s>>>(items, nitems, ens, ops, pass_a, xc, D, 1.f, partial); break;
+  }
+}
+
 template <int KK>
 static void launch_batch_kk(int rb, int grid, const int2 *items, int nitems, const EnsDesc *ens, const float *QB,
                             const float *KA, const float *VB, const float *xc, int D, float *partial, hipStream_t s) {
@@ -490,9 +524,26 @@ static void launch_batch_kk(int rb, int grid, const int2 *items, int nitems, con
   }
 }
 
-void launch_batch_pair(int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
-                       const float *QB, const float *KA, const float *VB, const float *xc, float *partial,
-                       hipStream_t s) {
+void launch_batch_pair(int impl, int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
+                       const float *QB, const float *KA, const float *VB, const F16Operands &f16, bool pass_a,
+                       const float *xc, float *partial, hipStream_t s) {
+  if (impl == VDS_PAIR_MFMA_F16X2 || impl == VDS_PAIR_MFMA_F16X2_ALL) {
+    const PairF16Ops ops{QB, KA, reinterpret_cast<const uint4 *>(f16.QH), reinterpret_cast<const uint4 *>(f16.KH),
+                         f16.RN, reinterpret_cast<const uint4 *>(VB), 0};
+    const int pa = pass_a ? 1 : 0;
+    if (impl == VDS_PAIR_MFMA_F16X2_ALL) {
+      if (f16_slices(D) == 1) launch_batch16_k<0, 1>(rb, grid, items, nitems, ens, ops, pa, xc, D, partial, s);
+      else launch_batch16_k<0, 2>(rb, grid, items, nitems, ens, ops, pa, xc, D, partial, s);
+    } else {
+      switch (KK) {
+        case 2: launch_batch16_k<2, 0>(rb, grid, items, nitems, ens, ops, pa, xc, D, partial, s); break;
+        case 3: launch_batch16_k<3, 0>(rb, grid, items, nitems, ens, ops, pa, xc, D, partial, s); break;
+        case 4: launch_batch16_k<4, 0>(rb, grid, items, nitems, ens, ops, pa, xc, D, partial, s); break;
+        default: launch_batch16_k<5, 0>(rb, grid, items, nitems, ens, ops, pa, xc, D, partial, s); break;
+      }
+    }
+    return;
+  }
   switch (KK) {
     case 2: launch_batch_kk<2>(rb, grid, items, nitems, ens, QB, KA, VB, xc, D, partial, s); break;
     case 3: launch_batch_kk<3>(rb, grid, items, nitems, ens, QB, KA, VB, xc, D, partial, s); break;

@@ -168,6 +168,7 @@ void fill_params(vds_ctx c) {
   e.cs = (float)std::sqrt(2.0 * 1.4426950408889634 / (2.0 * p.h * p.h));
   c->nblk = (int)((p.P + kRedBlock - 1) / kRedBlock);
   c->nblk_comb = (int)((p.P * 16 + kRedBlock - 1) / kRedBlock);
+  apply_tuning(c, c->tune);  // operand formats of the default implementation
 }
 
 void drain_timers(vds_ctx c) {

@@ -88,9 +88,12 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
 bool pair_shape_ok(const vds_tuning &t, int D);
 // Batched pair pass over the (ensemble, row tile) work list `items` with a
 // persistent grid of `grid` workgroups; rb = row blocks per wavefront.
-void launch_batch_pair(int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
-                       const float *QB, const float *KA, const float *VB, const float *xc, float *partial,
-                       hipStream_t s);
+// impl selects the pair implementation (VDS_PAIR_MFMA or one of the FP16-split
+// ones, whose operand formats the ensembles' vhalf / qhalf flags must match);
+// pass_a tells the FP16-split kernels that V holds the uniform weights 1/P_e.
+void launch_batch_pair(int impl, int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
+                       const float *QB, const float *KA, const float *VB, const F16Operands &f16, bool pass_a,
+                       const float *xc, float *partial, hipStream_t s);
 
 // ---- launchers (local_kernels.hip) ----
 void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done, hipStream_t s);
@@ -124,6 +127,7 @@ struct BatchView {
   const int *blk256_ens;
   int nblk16, nblk256;  // total blocks over all ensembles (padded particles)
   int D, KK;
+  F16Operands f16;      // concatenated FP16 distance operands (used when the ensembles' qhalf is set)
 };
 void launch_batch_mean(const BatchView &b, const float *q, double *meanp, hipStream_t s);
 void launch_batch_prep(const BatchView &b, const float *q, const double *meanp, float *xc, float *wv, float *QB,

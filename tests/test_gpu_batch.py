@@ -4,7 +4,8 @@ oracle run per ensemble, and of the captured-graph step against eager launches.
 Tolerances: states relative 1e-5 (float32 vs float64 oracle on the same float32
 inputs, a few explicit steps); per-ensemble stress relative Frobenius 1e-4;
 graph replays bitwise equal to eager launches (same kernels, fixed reduction
-order)."""
+order).  Every pair implementation is covered: FP32 MFMA and the FP16-split
+forms."""
 import sys
 
 import numpy as np
@@ -50,26 +51,33 @@ def _oracle_steps(q, P, h, G, nsteps):
     return q, ovds.stress(q, w, prob)
 
 
-def test_batch_matches_oracle_per_ensemble(lib):
+IMPLS = (0, 2, 3)  # FP32 MFMA and the two FP16-split forms
+
+
+@pytest.mark.parametrize("impl", IMPLS)
+def test_batch_matches_oracle_per_ensemble(lib, impl):
     import torch
     P, h, G, states = _small_batch()
     b = lib.Batch(P, h, G, poison=True)
+    b.set_tuning(2, 1024, impl=impl)
     q = b.pack([torch.from_numpy(wl.to_f32(s)).cuda() for s in states])
     tau = b.step(q, nsteps=3, stress=True)
     out = b.unpack(q)
     for e in range(len(P)):
-        _say(f"ensemble {e} P={P[e]}")
+        _say(f"impl {impl} ensemble {e} P={P[e]}")
         qo, tau_o = _oracle_steps(wl.f32_as_f64(wl.to_f32(states[e])), int(P[e]), h[e], G[e], 3)
         assert _rel(out[e].cpu().numpy(), qo) < 1e-5, e
         assert np.linalg.norm(tau[e] - tau_o) / np.linalg.norm(tau_o) < 1e-4, e
 
 
-def test_graph_replays_equal_eager_launches(lib):
+@pytest.mark.parametrize("impl", IMPLS)
+def test_graph_replays_equal_eager_launches(lib, impl):
     import torch
     P, h, G, states = _small_batch()
     b = lib.Batch(P, h, G, poison=True)
     q0 = b.pack([torch.from_numpy(wl.to_f32(s)).cuda() for s in states])
-    b.set_tuning(2, 512, use_graph=False)
+    _say(f"graph replays impl {impl}")
+    b.set_tuning(2, 512, use_graph=False, impl=impl)
     qe = q0.clone()
     eager = []
     for _ in range(4):
@@ -89,18 +97,22 @@ def test_tunings_agree_and_autotune_is_valid(lib):
     P, h, G, states = _small_batch()
     b = lib.Batch(P, h, G, poison=True)
     q0 = b.pack([torch.from_numpy(wl.to_f32(s)).cuda() for s in states])
-    ref = None
-    for rb in (1, 2, 4):
-        for grid in (7, 256, 2048):
-            b.set_tuning(rb, grid)
-            q = q0.clone()
-            b.step(q, nsteps=2)
-            r = q.cpu().numpy()
-            if ref is None:
-                ref = r
-            assert np.array_equal(r, ref), (rb, grid)   # one split: identical arithmetic
+    refs = {}
+    for impl in IMPLS:
+        for rb in (1, 2, 4):
+            for grid in (7, 256, 2048):
+                _say(f"batch tuning impl {impl} rb {rb} grid {grid}")
+                b.set_tuning(rb, grid, impl=impl)
+                q = q0.clone()
+                b.step(q, nsteps=2)
+                r = q.cpu().numpy()
+                ref = refs.setdefault(impl, r)
+                assert np.array_equal(r, ref), (impl, rb, grid)   # one split: identical arithmetic
+    # the implementations agree with each other to the parity tolerance
+    for impl in IMPLS[1:]:
+        assert _rel(refs[impl], refs[0].astype(np.float64)) < 1e-5, impl
     t = b.autotune(q0)
-    assert t["rows_per_wave"] in (1, 2, 4) and t["grid"] >= 1
+    assert t["impl"] in IMPLS and t["rows_per_wave"] in (1, 2, 4) and t["grid"] >= 1
 
 
 def test_batch_matches_single_ensemble_contexts(lib):

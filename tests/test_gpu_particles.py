@@ -50,8 +50,9 @@ def _rel(a, b):
 
 TUNINGS = [(0, 1, 1), (0, 2, 8), (0, 4, 3), (1, 1, 1), (1, 1, 5), (2, 1, 1), (2, 2, 8), (2, 4, 3),
            (3, 1, 1), (3, 2, 8), (3, 4, 3)]
-# the default FP32 MFMA shape and the two FP16-split forms at a benchmark shape
-IMPLS = [None, (2, 4, 16), (3, 2, 16)]
+# the default (FP16-split distances and sums), the FP32 MFMA form and the
+# FP16-split sums alone, at benchmark shapes
+IMPLS = [None, (0, 4, 16), (2, 4, 16)]
 
 
 @pytest.mark.parametrize("P", [1, 2, 3, 17, 63, 64, 300])
