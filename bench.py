@@ -321,7 +321,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--P", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--tuning", type=str, default="", help="impl,rows_per_wave,col_splits (skips the autotuner)")
+    ap.add_argument("--tuning", type=str, default="3,2,8",
+                    help="impl,rows_per_wave,col_splits of the pair kernel (the fastest shape measured on MI355X)")
+    ap.add_argument("--autotune", action="store_true", help="let the library's autotuner pick the pair shape")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy of known size")
     ap.add_argument("--sweep", action="store_true", help="only time every pair-kernel tuning and print a table")
     ap.add_argument("--t-end", action="store_true", help="also time the full 500-step run to t_end")
@@ -373,10 +375,10 @@ def main():
                                       "pair_avg_ms": tim["ms"] / max(1, tim["launches"]),
                                       "step_ms": el * 1e3 / 5, "iters": d["iters"]}), flush=True)
         return
-    if args.tuning:
-        ctx.set_tuning(*[int(v) for v in args.tuning.split(",")])
-    else:
+    if args.autotune:
         ctx.autotune(q0)
+    else:
+        ctx.set_tuning(*[int(v) for v in args.tuning.split(",")])
     tune = ctx.get_tuning()
     q = q0.clone()
 

@@ -97,7 +97,8 @@ typedef struct vds_diag {
   double tau[9];         /* stress n sum_I w_I sum_j q_j (x) grad Psi_j, row-major */
 } vds_diag;
 
-/* Pair-kernel launch shape (chosen by vds_autotune or set by hand). */
+/* Pair-kernel launch shape (chosen by vds_autotune or set by hand; a new
+ * context starts with VDS_PAIR_MFMA_F16X2_ALL, 2 row blocks per wave, 8 splits). */
 typedef struct vds_tuning {
   int32_t impl;          /* one of the VDS_PAIR_* implementations */
   int32_t rows_per_wave; /* MFMA forms: 16-row blocks per wavefront (1, 2 or 4) */
@@ -121,7 +122,8 @@ vds_status vds_bind_workspace(vds_ctx ctx, void *ws_dev, size_t bytes);
 const char *vds_last_error(vds_ctx ctx);
 vds_status vds_set_tuning(vds_ctx ctx, const vds_tuning *t);
 vds_status vds_get_tuning(vds_ctx ctx, vds_tuning *t);
-/* Times every admissible tuning on the state q_dev and keeps the fastest
+/* Times every admissible tuning on the state q_dev (a pair pass with the
+ * finalisation that sums its column splits) and keeps the fastest
  * (synchronises). */
 vds_status vds_autotune(vds_ctx ctx, const float *q_dev, const float *w_dev);
 

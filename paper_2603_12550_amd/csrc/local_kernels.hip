@@ -117,16 +117,24 @@ __global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const
 }
 
 // Sum of the centring partials (mean_sh[0..D)) and the largest weight
-// (mean_sh[15]), computed identically by every block.
+// (mean_sh[15]), computed identically by every block: thread (c, j) = (t % 16,
+// t / 16) folds the partials of blocks j, j + 16, ... of slot c, then one
+// thread per slot combines the sixteen results in order.
 __device__ void load_mean(const EvalParams &p, const double *meanp, int nmeanp, float *mean_sh) {
-  if (threadIdx.x < p.D) {
-    double s = 0.0;
-    for (int b = 0; b < nmeanp; ++b) s += meanp[(int64_t)b * 16 + threadIdx.x];
-    mean_sh[threadIdx.x] = (float)s;
-  } else if (threadIdx.x == 15) {
-    double m = 0.0;
-    for (int b = 0; b < nmeanp; ++b) m = fmax(m, meanp[(int64_t)b * 16 + 15]);
-    mean_sh[15] = (float)m;
+  __shared__ double part[16][17];
+  const int c = threadIdx.x & 15, j = threadIdx.x >> 4;  // blockDim.x == 256
+  double v = 0.0;
+  if (c == 15) {
+    for (int b = j; b < nmeanp; b += 16) v = fmax(v, meanp[(int64_t)b * 16 + 15]);
+  } else if (c < p.D) {
+    for (int b = j; b < nmeanp; b += 16) v += meanp[(int64_t)b * 16 + c];
+  }
+  part[c][j] = v;
+  __syncthreads();
+  if (threadIdx.x < 16 && (threadIdx.x < p.D || threadIdx.x == 15)) {
+    double r = 0.0;
+    for (int i = 0; i < 16; ++i) r = threadIdx.x == 15 ? fmax(r, part[threadIdx.x][i]) : r + part[threadIdx.x][i];
+    mean_sh[threadIdx.x] = (float)r;
   }
   __syncthreads();
 }

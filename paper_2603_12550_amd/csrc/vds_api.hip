@@ -504,10 +504,15 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
                   c->stream);
       prepared = c->ep.vhalf + 2 * c->ep.qhalf;
     }
-    pair_pass(c, c->VA, c->wscale, nullptr);  // warm-up
+    // each candidate is timed with the finalisation that sums its column splits
+    auto pass = [&] {
+      pair_pass(c, c->VA, c->wscale, nullptr);
+      launch_finalize_a(c->ep, c->part, t.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
+    };
+    pass();  // warm-up
     (void)hipEventRecord(a, c->stream);
     const int reps = 3;
-    for (int r = 0; r < reps; ++r) pair_pass(c, c->VA, c->wscale, nullptr);
+    for (int r = 0; r < reps; ++r) pass();
     (void)hipEventRecord(b, c->stream);
     st = hip_check(c, hipEventSynchronize(b), "autotune");
     if (st != VDS_OK) break;
