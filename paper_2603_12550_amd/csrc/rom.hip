@@ -205,6 +205,137 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
   }
 }
 
+// ---- FP16-split kernel-GEMM (used with the FP16-split pair kernels) ---------
+//
+// The same product with Z and B split into FP16 halves and taken on
+// v_mfma_f32_16x16x32_f16 as Z_hi B_hi + Z_hi B_lo + Z_lo B_hi (about 22
+// significant bits).  Z enters as 2^15 Z and B as 2^8 B' with B' = U_a for the
+// w-weighted columns (uniform weights over their maximum) and (w/S) U_a for the
+// others; the epilogue multiplies column col by scale0 (col < 3R) or scale1.
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+constexpr float kKgShift = 15.f;
+constexpr float kKgBScale = 256.f;
+constexpr int kKgFlushPairs = 4;
+
+// BH[((cp NB16 + nbk) 64 + n + 16 g) 8 + 4 s + i] = high half of B[32 cp + 16 s + 4 g + i][16 nbk + n];
+// the low halves follow after Ppad ldy halves.
+__global__ void k_rom_bsw16(const float *__restrict__ Ude, const float *__restrict__ wv,
+                            const float *__restrict__ invS, float wmax, int64_t P, int64_t Ppad, int R, int NB16,
+                            _Float16 *__restrict__ BH) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t ldy = (int64_t)NB16 * 16;
+  if (t >= Ppad * ldy) return;
+  const int64_t J = t / ldy;
+  const int col = (int)(t % ldy);
+  const int dR = 3 * R;
+  float v = 0.f;
+  if (J < P && col < 2 * dR) {
+    const int h = col / dR, rem = col % dR, a = rem / R, tt = rem % R;
+    const float wgt = h == 0 ? wv[J] / wmax : wv[J] * invS[J];
+    v = kKgBScale * wgt * Ude[((int64_t)a * R + tt) * P + J];
+  }
+  const int jl = (int)(J & 15);
+  const int64_t idx = (((J >> 5) * NB16 + (col >> 4)) * 64 + (col & 15) + 16 * (jl >> 2)) * 8 + 4 * ((J >> 4) & 1) +
+                      (jl & 3);
+  const _Float16 hi = (_Float16)v;
+  BH[idx] = hi;
+  BH[idx + Ppad * ldy] = (_Float16)(v - (float)hi);
+}
+
+__device__ inline half8 as_half8(uint4 u) {
+  half8 h;
+  __builtin_memcpy(&h, &u, sizeof(h));
+  return h;
+}
+
+template <int KK>
+__global__ __launch_bounds__(256) void k_kernel_gemm16(const float *__restrict__ QB, const float *__restrict__ KA,
+                                                       int nrow_blocks, int ncol_chunks,
+                                                       const uint4 *__restrict__ BH, int64_t lo_off, int NB16,
+                                                       int dR, double scale0, double scale1, float one,
+                                                       float *__restrict__ Y, int64_t ldy) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rb = (int)blockIdx.x * 4 + wave;
+  if (rb >= nrow_blocks) return;
+  const int nb0 = (int)blockIdx.y * kNBG;
+  const int nbn = min(kNBG, NB16 - nb0);
+  const int diag_i = (lane & 15) - 4 * (lane >> 4);
+  const int ncp = (ncol_chunks + 1) / 2;  // the last pair's second chunk lies in the zero padding
+  float qv[KK];
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) qv[kk] = QB[((int64_t)rb * KK + kk) * 64 + lane];
+  double tot[kNBG][4];
+#pragma unroll
+  for (int g = 0; g < kNBG; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[g][i] = 0.0;
+  const floatx4 shift = {kKgShift, kKgShift, kKgShift, kKgShift};
+
+  for (int cp = 0; cp < ncp;) {
+    const int g_end = min(ncp, cp + kKgFlushPairs);
+    floatx4 acc[kNBG];
+#pragma unroll
+    for (int g = 0; g < kNBG; ++g) acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; cp < g_end; ++cp) {
+      float e[8];
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) {
+        const int c = 2 * cp + sc;
+        floatx4 t = shift;
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+          t = __builtin_amdgcn_mfma_f32_16x16x4f32(KA[((int64_t)c * KK + kk) * 64 + lane], qv[kk], t, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[4 * sc + i] = fminf(__builtin_amdgcn_exp2f(t[i]), 32768.f);
+        if (c == rb) {  // the self pair has Z_II = K_h(0) = 1 exactly
+#pragma unroll
+          for (int i = 0; i < 4; ++i) e[4 * sc + i] = diag_i == i ? 32768.f : e[4 * sc + i];
+        }
+      }
+      half8 eh, el;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const half2v h = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(e[j], e[j + 1]));
+        const float ra = __builtin_fmaf(-(float)h.x, one, e[j]);
+        const float rb2 = __builtin_fmaf(-(float)h.y, one, e[j + 1]);
+        eh[j] = h.x;
+        eh[j + 1] = h.y;
+        el[j] = (_Float16)ra;
+        el[j + 1] = (_Float16)rb2;
+      }
+      const uint4 *bp = BH + ((int64_t)cp * NB16 + nb0) * 64 + lane;
+#pragma unroll
+      for (int g = 0; g < kNBG; ++g) {
+        if (g < nbn) {
+          const half8 bh = as_half8(bp[(int64_t)g * 64]);
+          const half8 bl = as_half8(bp[lo_off + (int64_t)g * 64]);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, bh, acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, bl, acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(el, bh, acc[g], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kNBG; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tot[g][i] += (double)acc[g][i];
+  }
+#pragma unroll
+  for (int g = 0; g < kNBG; ++g) {
+    if (g >= nbn) break;
+    const int col = (nb0 + g) * 16 + (lane & 15);
+    const double sc = col < dR ? scale0 : scale1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = (int64_t)rb * 16 + 4 * (lane >> 4) + i;
+      Y[row * ldy + col] = (float)(tot[g][i] * sc);
+    }
+  }
+}
+
 __global__ void k_fill_scaled(const float *__restrict__ src, float a, int64_t n, float *__restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t < n) dst[t] = a * src[t];
@@ -274,6 +405,90 @@ __global__ __launch_bounds__(1024) void k_rom_steps(const float *__restrict__ XH
     __syncthreads();
   }
   for (int t = tid; t < nb * R; t += blockDim.x) p[t] = ps[t / R][t % R];
+}
+
+// The same steps with both operators held in registers for the whole window:
+// thread t works on matrix row t / 2 (the rows of X^H, then those of X^B) over
+// half t % 2 of its columns, so a step reads only the state, from LDS, and
+// combines the two halves with one shuffle.  768 threads (three waves per
+// SIMD leave room for the matrix slice); R <= 2 kHalf <= 384.
+constexpr int kRegThreads = 768;
+template <int kHalf>
+__global__ __launch_bounds__(kRegThreads) void k_rom_steps_reg(const float *__restrict__ XH,
+                                                               const float *__restrict__ XB, float *__restrict__ p,
+                                                               int nb, int R, int nsteps, EvalParams ep) {
+  constexpr int W = 2 * kHalf;
+  constexpr int kPer = (kMaxNb * W + kRegThreads - 1) / kRegThreads;  // state entries per thread
+  __shared__ float ps[kMaxNb][W];
+  __shared__ float y[kMaxNb][W];
+  __shared__ float z[kMaxNb][W];
+  const int tid = threadIdx.x;
+  const int row = tid >> 1, half = tid & 1;
+  const int hl = (R + 1) / 2;
+  const int u0 = half * hl;
+  const int len = min(hl, R - u0);
+  const bool active = row < 2 * R;
+  const float *M = row < R ? XH + (int64_t)row * R : XB + (int64_t)(row - R) * R;
+  float m[kHalf];
+#pragma unroll
+  for (int j = 0; j < kHalf; ++j) m[j] = (active && j < len) ? M[u0 + j] : 0.f;
+  for (int t = tid; t < kMaxNb * W; t += kRegThreads) {  // zero padding: the unused m[j] meet zeros
+    const int k = t / W, s = t % W;
+    ps[k][s] = (k < nb && s < R) ? p[k * R + s] : 0.f;
+  }
+  __syncthreads();
+  const float ktz = ep.kT * ep.inv_zeta;
+  for (int step = 0; step < nsteps; ++step) {
+    float acc[kMaxNb];
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
+    const float *pr = &ps[0][u0];  // u0 + j < W since u0 = half ceil(R / 2) <= kHalf
+#pragma unroll
+    for (int j = 0; j < kHalf; ++j) {
+#pragma unroll
+      for (int k = 0; k < kMaxNb; ++k)
+        if (k < nb) acc[k] = fmaf(m[j], pr[k * W + j], acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k) acc[k] += __shfl_xor(acc[k], 1);
+    if (active && half == 0) {
+#pragma unroll
+      for (int k = 0; k < kMaxNb; ++k) {
+        if (k < nb) {
+          if (row < R) y[k][row] = acc[k];
+          else z[k][row - R] = acc[k];
+        }
+      }
+    }
+    __syncthreads();
+    float pn[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int t = tid + i * kRegThreads;
+      pn[i] = 0.f;
+      if (t < nb * R) {
+        const int k = t / R, s = t % R;
+        float az = 2.f * z[k][s], ah = 2.f * ep.H[k] * ps[k][s];
+        if (k > 0) {
+          az -= z[k - 1][s];
+          ah -= ep.H[k - 1] * ps[k - 1][s];
+        }
+        if (k + 1 < nb) {
+          az -= z[k + 1][s];
+          ah -= ep.H[k + 1] * ps[k + 1][s];
+        }
+        pn[i] = ps[k][s] + ep.dt * (y[k][s] - ktz * az - ep.inv_zeta * ah);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int t = tid + i * kRegThreads;
+      if (t < nb * R) ps[t / R][t % R] = pn[i];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < nb * R; t += kRegThreads) p[t] = ps[t / R][t % R];
 }
 
 // tau_ab = (n / P) sum_k H_k p_k^T M_ab p_k (uniform weights), FP64 sums.
@@ -347,9 +562,28 @@ vds_status freeze(vds_rom r, const float *p) {
   eval_pass_b(c, nullptr);
   k_rom_scalars<<<nblk256(Ppad), 256, 0, s>>>(c->part, c->tune.col_splits, Ppad, P, c->ep.D, c->S, c->wv, r->T,
                                               r->invS);
-  k_rom_bsw<<<nblk256(Ppad * L.ldy), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, L.NB16, r->Bsw);
-  // Y = Z B
-  {
+  // Y = Z B, in the FP16-split form when the context's pair kernels use it
+  if (c->ep.vhalf) {
+    const float wmax = c->ep.uniform_w;  // the reduced model runs with uniform weights
+    k_rom_bsw16<<<nblk256(Ppad * L.ldy), 256, 0, s>>>(r->Ude, c->wv, r->invS, wmax, P, Ppad, R, L.NB16,
+                                                      reinterpret_cast<_Float16 *>(r->Bsw));
+    const int nrb = (int)(Ppad / 16), ncc = (int)((P + 15) / 16);
+    dim3 grid((unsigned)((nrb + 3) / 4), (unsigned)((L.NB16 + kNBG - 1) / kNBG));
+    const uint4 *bh = reinterpret_cast<const uint4 *>(r->Bsw);
+    const int64_t lo_off = Ppad * L.ldy / 8;  // uint4 units
+    const double unscale = 1.0 / ((double)kKgBScale * 32768.0);
+    const double s0 = (double)wmax * unscale, s1 = unscale;
+    const double flops = 2.0 * (double)P * P * 2 * 3 * R;
+    timed(c, VDS_TIMER_KGEMM, flops, [&] {
+      switch (c->ep.KK) {
+        case 2: k_kernel_gemm16<2><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;
+        case 3: k_kernel_gemm16<3><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;
+        case 4: k_kernel_gemm16<4><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;
+        default: k_kernel_gemm16<5><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;
+      }
+    });
+  } else {
+    k_rom_bsw<<<nblk256(Ppad * L.ldy), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, L.NB16, r->Bsw);
     const int nrb = (int)(Ppad / 16), ncc = (int)((P + 15) / 16);
     dim3 grid((unsigned)((nrb + 3) / 4), (unsigned)((L.NB16 + kNBG - 1) / kNBG));
     const float4 *b4 = reinterpret_cast<const float4 *>(r->Bsw);
@@ -518,7 +752,13 @@ vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every
     vds_status st = freeze(r, p);
     if (st != VDS_OK) return st;
     const int n = std::min(freeze_every, nsteps - s0);
-    k_rom_steps<<<1, 1024, 0, c->stream>>>(r->XH, r->XB, p, c->prob.nb, r->R, n, c->ep);
+    const int nb = c->prob.nb, R = r->R;
+    if (R <= 128)
+      k_rom_steps_reg<64><<<1, kRegThreads, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
+    else if (R <= 192)
+      k_rom_steps_reg<96><<<1, kRegThreads, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
+    else
+      k_rom_steps<<<1, 1024, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
   }
   vds_status st = hip_check(c, hipGetLastError(), "reduced steps");
   if (st != VDS_OK) return st;

@@ -138,10 +138,22 @@ def _small_rom_case(P=300, R=12, seed=5):
     return U32, Uf, p32, prob
 
 
-def test_rom_operators_small_vs_oracle(lib):
+# default: FP16-split pair kernels and kernel-GEMM; (0, 4, 16): the FP32 MFMA forms
+TUNINGS = [None, (0, 4, 16)]
+
+
+def _tuned(ctx, tuning):
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    return ctx
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_rom_operators_small_vs_oracle(lib, tuning):
     P, R = 300, 12
     U32, Uf, p32, prob = _small_rom_case(P, R)
-    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    ctx = _tuned(lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True), tuning)
+    _say(f"reduced operators P=300 R=12 tuning {tuning}")
     rom = lib.Rom(ctx, _dev(U32))
     XH, XB1, XB2 = (_np(t) for t in rom.operators(_dev(p32)))
     qt = opod.reconstruct(Uf, p32.astype(np.float64), P)
@@ -152,10 +164,15 @@ def test_rom_operators_small_vs_oracle(lib):
     assert _rel(XB2, XB2_o) < 1e-4
 
 
-def test_rom_run_small_vs_oracle(lib):
-    P, R = 300, 12
+@pytest.mark.parametrize("tuning", TUNINGS)
+@pytest.mark.parametrize("R", [12, 140, 250])
+def test_rom_run_small_vs_oracle(lib, tuning, R):
+    # R = 140 and 250 take the register-resident stepper (R <= 192) and the
+    # plain one; P = 300 gives P d = 900 >= R
+    P = 300
     U32, Uf, p32, prob = _small_rom_case(P, R, seed=6)
-    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    ctx = _tuned(lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True), tuning)
+    _say(f"reduced run P=300 R={R} tuning {tuning}")
     rom = lib.Rom(ctx, _dev(U32))
     p = _dev(p32)
     tau = rom.run(p, nsteps=30, freeze_every=10)
@@ -167,7 +184,8 @@ def test_rom_run_small_vs_oracle(lib):
     assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
-def test_full_rank_rom_equals_full_explicit_scheme(lib):
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_full_rank_rom_equals_full_explicit_scheme(lib, tuning):
     # R = P d with an orthogonal U and a freeze every step: the reduced model is the
     # full explicit scheme in another basis (Section 2.4 approximations are exact)
     P = 40
@@ -177,7 +195,8 @@ def test_full_rank_rom_equals_full_explicit_scheme(lib):
     Uf = U32.astype(np.float64).T
     cfg = wl.dumbbell_shear(P=P, seed=9)
     q32 = wl.to_f32(cfg["q0"])
-    ctx = lib.Context(1, P, 0.5, G=cfg["G"], dt=1e-3, scheme="explicit", poison=True)
+    ctx = _tuned(lib.Context(1, P, 0.5, G=cfg["G"], dt=1e-3, scheme="explicit", poison=True), tuning)
+    _say(f"full-rank reduced model P=40 tuning {tuning}")
     rom = lib.Rom(ctx, _dev(U32))
     p = ctx.pod_project(_dev(U32), _dev(q32))
     rom.run(p, nsteps=5, freeze_every=1)
