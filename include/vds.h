@@ -167,6 +167,15 @@ vds_status vds_density_at(vds_ctx ctx, const float *q_dev, const float *w_dev,
 
 /* ---- per-kernel timing (HIP events on the context's stream) ------------- */
 
+/* Median-heuristic bandwidth (eq. model_bandwidth): med = the median of
+ * |q_J - q_K| (configuration-space distance) over all P^2 ordered pairs, J = K
+ * included (for an even count, the mean of the two middle values), and
+ * h = med / sqrt(2 log P).  Unweighted.  Exact selection over the FP32 squared
+ * distances of the state q_dev ([nb][P][3]); med_host, h_host (either may be
+ * NULL) receive the FP64 results.  Needs 2 <= P <= 2^24.  Synchronises (three passes over
+ * the pairs).  The context's h is not changed: create a context with the result. */
+vds_status vds_median_bandwidth(vds_ctx ctx, const float *q_dev, double *med_host, double *h_host);
+
 enum { VDS_TIMER_PAIR = 0, VDS_TIMER_GEMM = 1, VDS_TIMER_KGEMM = 2, VDS_TIMER_PROJ = 3, VDS_TIMER_COUNT = 4 };
 /* enable != 0 starts recording an event pair around every launch of the timed
  * kernels and clears the totals; 0 stops. */

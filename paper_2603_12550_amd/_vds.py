@@ -71,6 +71,7 @@ _sigs = {
     "vds_stress": ([_P, _P, _P, C.POINTER(C.c_double)], C.c_int),
     "vds_energy": ([_P, _P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "vds_density_at": ([_P, _P, _P, _P, C.c_int64, _P], C.c_int),
+    "vds_median_bandwidth": ([_P, _P, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "vds_timing_enable": ([_P, C.c_int32], C.c_int),
     "vds_timing_read": ([_P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)], C.c_int),
 }
@@ -293,6 +294,12 @@ class Context:
         ws = self._map_ws(R)
         _check(_lib.vds_pod_reconstruct(self.ctx, _ptr(U), R, _ptr(p), _ptr(q), _ptr(ws), ws.numel()), self.ctx)
         return q
+
+    def median_bandwidth(self, q):
+        """(med, h) of the median rule (eq. model_bandwidth) for the state q."""
+        med, h = C.c_double(), C.c_double()
+        _check(_lib.vds_median_bandwidth(self.ctx, _ptr(q), C.byref(med), C.byref(h)), self.ctx)
+        return med.value, h.value
 
     def density_at(self, q, y, w=None):
         y = y.contiguous()

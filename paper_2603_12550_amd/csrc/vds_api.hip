@@ -137,6 +137,7 @@ Layout make_layout(const vds_problem &p) {
   L.QH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
   L.KH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
   L.RN = take(sizeof(float) * Ppad);
+  L.hist = take(sizeof(unsigned long long) * 2 * kHistBins);
   L.qstar = take(sizeof(float) * p.P * D);
   L.xb0 = take(sizeof(float) * p.P * D);
   L.xb1 = take(sizeof(float) * p.P * D);
@@ -307,6 +308,7 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->blockmax = reinterpret_cast<float *>(c->ws + L.blockmax);
   c->wscale = reinterpret_cast<float *>(c->ws + L.wscale);
   c->f16 = F16Operands{c->ws + L.QH, c->ws + L.KH, reinterpret_cast<float *>(c->ws + L.RN)};
+  c->hist = reinterpret_cast<unsigned long long *>(c->ws + L.hist);
   c->qstar = reinterpret_cast<float *>(c->ws + L.qstar);
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
   c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);

@@ -9,7 +9,7 @@
 namespace vds {
 
 struct Layout {
-  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, qstar, xb0, xb1, total;
+  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, hist, qstar, xb0, xb1, total;
 };
 
 struct TimerAcc {
@@ -39,6 +39,7 @@ struct vds_ctx_s {
   // workspace views
   float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *qstar, *xb[2], *blockmax, *wscale;
   vds::F16Operands f16{};
+  unsigned long long *hist;  // median-bandwidth histograms [2][kHistBins]
   double *meanp, *redp, *redout;
   vds::Ctrl *ctrl;
   int nblk;       // blocks of the one-thread-per-particle kernels

@@ -15,6 +15,7 @@ constexpr int kMaxNb = 5;          // D = 3 nb <= 15 keeps D + 1 within one 16-w
 constexpr int kMaxD = 3 * kMaxNb;
 constexpr int kMaxSplits = 32;     // column splits the partial-sum buffer is sized for
 constexpr int kRowAlign = 256;     // particle padding: rows and columns come in multiples of this
+constexpr int kHistBins = 4096;   // bins per target of the median-bandwidth selection
 constexpr int kRedBlock = 256;     // threads per block of the O(P) kernels
 constexpr int kNumRed = 16;        // FP64 reduction slots: F, diss, work, tau[9], spare
 

@@ -313,3 +313,26 @@ def test_not_converged_status(lib):
     with pytest.raises(lib.VDSError) as ei:
         ctx.step(_dev(cfg["q0"]))
     assert ei.value.status == lib._vds.VDS_ERR_NOT_CONVERGED
+
+
+@pytest.mark.parametrize("P", [2, 3, 17, 300, 1001, 2000])
+@pytest.mark.parametrize("nb", [1, 3, 5])
+def test_median_bandwidth_matches_oracle(lib, P, nb):
+    # eq. model_bandwidth: exact selection over the P^2 ordered pair distances
+    # (J = K included); FP32 squared distances against the FP64 oracle
+    q32 = wl.to_f32(wl.gaussian_bonds(200 + P, nb, P, 1.0))
+    q = wl.f32_as_f64(q32)
+    ctx = _ctx(lib, nb, P, 0.4)
+    _say(f"median bandwidth P={P} nb={nb}")
+    med, h = ctx.median_bandwidth(_dev(q32))
+    h_o = ovds.median_bandwidth(q)
+    med_o = h_o * math.sqrt(2.0 * math.log(P))
+    assert med == pytest.approx(med_o, rel=1e-6, abs=1e-12)
+    assert h == pytest.approx(h_o, rel=1e-6, abs=1e-12)
+
+
+def test_median_bandwidth_rejects_one_particle(lib):
+    ctx = _ctx(lib, 1, 1, 0.4)
+    with pytest.raises(lib.VDSError) as ei:
+        ctx.median_bandwidth(_dev(np.zeros((1, 1, 3))))
+    assert ei.value.status == lib._vds.VDS_ERR_ARG
