@@ -288,6 +288,24 @@ def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps)
     }
 
 
+def measure_appendix_a(pkg, wl, torch):
+    """Accuracy study of the reference dynamics (Appendix A) at the paper's
+    settings: 4-bead chain, P = 1000, t = 6, dt in {1e-2 .. 5e-4} for both
+    schemes, and P in {100 .. 5000} at dt = 1e-3; median-rule bandwidths."""
+    from paper_2603_12550_amd import accuracy
+    grid = torch.from_numpy(wl.to_f32(wl.density_grid(9))).cuda()
+    t0 = time.perf_counter()
+    res = accuracy.time_step_study(wl.appendix_a_chain4(P=1000), grid)
+    res["particles"] = accuracy.particle_study(lambda P: wl.appendix_a_chain4(P=P, seed=30 + P), grid)
+    res["seconds"] = time.perf_counter() - t0
+    res["paper"] = {"dt_1e-3_error": "about 1e-4",
+                    "explicit_vs_implicit_dt_5e-4": {"position_l2": 9.51e-5, "position_linf": 1.01e-4,
+                                                     "density_l2": 1.17e-4, "density_linf": 1.80e-4,
+                                                     "stress_fro": 9.56e-5},
+                    "P_1000_vs_5000": "about 5-10 %"}
+    return res
+
+
 def measure_fene(pkg, wl, torch, steps):
     """6-bead FENE chain (D = 15), P = 50000, explicit steps of the plain scheme."""
     from paper_2603_12550_amd import _vds
@@ -444,7 +462,8 @@ def main():
                          ("batched", lambda: measure_batched(pkg, wl, torch, args.batched_steps)),
                          ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
                                                             args.learned_run_steps, args.learned_epochs, 300)),
-                         ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20))):
+                         ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20)),
+                         ("appendix_a", lambda: measure_appendix_a(pkg, wl, torch))):
             t0 = time.perf_counter()
             extras[name] = fn()
             print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

@@ -200,7 +200,7 @@ class Context:
             self.ctx = None
 
     # -- tuning / timing --
-    def set_tuning(self, impl=VDS_PAIR_MFMA, rows_per_wave=2, col_splits=8):
+    def set_tuning(self, impl=VDS_PAIR_MFMA_F16X2_ALL, rows_per_wave=2, col_splits=8):
         t = vds_tuning(impl, rows_per_wave, col_splits, 0)
         _check(_lib.vds_set_tuning(self.ctx, C.byref(t)), self.ctx)
 

@@ -130,6 +130,22 @@ def fene_chain6(P: int = 50000, seed: int = 5, b_max: float = 50.0):
                 q0=truncated_gaussian_bonds(seed, 5, P, 1.0, 0.9 * b_max))
 
 
+def appendix_a_chain4(P: int = 1000, seed: int = 21, rate: float = 1.0):
+    """Accuracy study of the reference dynamics (Appendix A): 4-bead Hookean
+    chain in simple shear, thermal-equilibrium start N(0, kT/H) = N(0, I) per
+    bond, zeta = 4, up to t = 6; the bandwidth follows the median rule of the
+    initial state (computed by the caller)."""
+    return dict(name=f"appendix_a_chain4_P{P}", nb=3, P=P, kT=1.0, zeta=4.0, n=1.0, dt=1e-3,
+                G=shear_gradient(rate), H=np.ones(3), potential="hookean", b_max=0.0, t_end=6.0,
+                q0=gaussian_bonds(seed, 3, P, 1.0))
+
+
+def density_grid(D: int, values=(-2.0, 0.0, 2.0)) -> np.ndarray:
+    """All points of values^D (Appendix A evaluates the density on {-2, 0, 2}^D)."""
+    axes = np.meshgrid(*[np.asarray(values, dtype=np.float64)] * D, indexing="ij")
+    return np.stack([a.reshape(-1) for a in axes], axis=1)
+
+
 def mlp_shear_rates(n_runs: int, seed: int = 5) -> np.ndarray:
     """Shear rates of the learned-model training runs, log-uniform in [0.1, 10]."""
     rng = np.random.default_rng(seed)
