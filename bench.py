@@ -306,6 +306,18 @@ def measure_appendix_a(pkg, wl, torch):
     return res
 
 
+def measure_paper_tables(pkg, wl, torch):
+    """Tables 1-6 (Sections 3.2, 3.3) at the paper's sizes: reference run,
+    POD basis, and the POD-Galerkin run for every reduced rank, with
+    T_mor / T_ref and err_MOR(t = 6) next to the paper's CPU values."""
+    from paper_2603_12550_amd import tables
+    out = {}
+    for name in wl.PAPER_TABLES:
+        case = wl.paper_table_case(name)
+        out[name] = tables.run_table(case, wl.snapshot_steps(case["snapshots"], case["snap_until"]))
+    return out
+
+
 def measure_fene(pkg, wl, torch, steps):
     """6-bead FENE chain (D = 15), P = 50000, explicit steps of the plain scheme."""
     from paper_2603_12550_amd import _vds
@@ -463,7 +475,8 @@ def main():
                          ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
                                                             args.learned_run_steps, args.learned_epochs, 300)),
                          ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20)),
-                         ("appendix_a", lambda: measure_appendix_a(pkg, wl, torch))):
+                         ("appendix_a", lambda: measure_appendix_a(pkg, wl, torch)),
+                         ("paper_tables", lambda: measure_paper_tables(pkg, wl, torch))):
             t0 = time.perf_counter()
             extras[name] = fn()
             print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

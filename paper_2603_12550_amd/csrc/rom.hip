@@ -409,22 +409,27 @@ __global__ __launch_bounds__(1024) void k_rom_steps(const float *__restrict__ XH
 
 // The same steps with both operators held in registers for the whole window:
 // thread t works on matrix row t / 2 (the rows of X^H, then those of X^B) over
-// half t % 2 of its columns, so a step reads only the state, from LDS, and
-// combines the two halves with one shuffle.  768 threads (three waves per
-// SIMD leave room for the matrix slice); R <= 2 kHalf <= 384.
+// half t % 2 of its columns (halves aligned to four columns), so a step reads
+// only the state, as float4 broadcasts from LDS, and combines the two halves
+// with one shuffle.  The state is double-buffered: two barriers per step.
+// 768 threads (three waves per SIMD leave room for the matrix slice);
+// R <= 2 kHalf, NB = nb bonds known at compile time (no per-bond branches
+// between the loads and their uses).
 constexpr int kRegThreads = 768;
-template <int kHalf>
+template <int kHalf, int NB>
 __global__ __launch_bounds__(kRegThreads) void k_rom_steps_reg(const float *__restrict__ XH,
                                                                const float *__restrict__ XB, float *__restrict__ p,
-                                                               int nb, int R, int nsteps, EvalParams ep) {
+                                                               int R, int nsteps, EvalParams ep) {
+  static_assert(kHalf % 4 == 0, "halves are read as float4");
   constexpr int W = 2 * kHalf;
-  constexpr int kPer = (kMaxNb * W + kRegThreads - 1) / kRegThreads;  // state entries per thread
-  __shared__ float ps[kMaxNb][W];
-  __shared__ float y[kMaxNb][W];
-  __shared__ float z[kMaxNb][W];
+  constexpr int kPer = (NB * W + kRegThreads - 1) / kRegThreads;  // state entries per thread
+  __shared__ float4 ps4[2][NB][W / 4];
+  __shared__ float y[NB][W];
+  __shared__ float z[NB][W];
+  float *ps0 = reinterpret_cast<float *>(&ps4[0][0][0]);
   const int tid = threadIdx.x;
   const int row = tid >> 1, half = tid & 1;
-  const int hl = (R + 1) / 2;
+  const int hl = (((R + 1) / 2) + 3) & ~3;  // <= kHalf
   const int u0 = half * hl;
   const int len = min(hl, R - u0);
   const bool active = row < 2 * R;
@@ -432,63 +437,74 @@ __global__ __launch_bounds__(kRegThreads) void k_rom_steps_reg(const float *__re
   float m[kHalf];
 #pragma unroll
   for (int j = 0; j < kHalf; ++j) m[j] = (active && j < len) ? M[u0 + j] : 0.f;
-  for (int t = tid; t < kMaxNb * W; t += kRegThreads) {  // zero padding: the unused m[j] meet zeros
-    const int k = t / W, s = t % W;
-    ps[k][s] = (k < nb && s < R) ? p[k * R + s] : 0.f;
+  for (int t = tid; t < 2 * NB * W; t += kRegThreads) {  // zero padding: the unused m[j] meet zeros
+    const int b = t / (NB * W), k = (t / W) % NB, s = t % W;
+    ps0[t] = (b == 0 && s < R) ? p[k * R + s] : 0.f;
   }
   __syncthreads();
   const float ktz = ep.kT * ep.inv_zeta;
+  int cur = 0;
   for (int step = 0; step < nsteps; ++step) {
-    float acc[kMaxNb];
+    float acc[NB];
 #pragma unroll
-    for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
-    const float *pr = &ps[0][u0];  // u0 + j < W since u0 = half ceil(R / 2) <= kHalf
+    for (int k = 0; k < NB; ++k) acc[k] = 0.f;
 #pragma unroll
-    for (int j = 0; j < kHalf; ++j) {
+    for (int j4 = 0; j4 < kHalf / 4; ++j4) {
 #pragma unroll
-      for (int k = 0; k < kMaxNb; ++k)
-        if (k < nb) acc[k] = fmaf(m[j], pr[k * W + j], acc[k]);
+      for (int k = 0; k < NB; ++k) {
+        const float4 v = ps4[cur][k][(u0 >> 2) + j4];
+        acc[k] = fmaf(m[4 * j4], v.x, acc[k]);
+        acc[k] = fmaf(m[4 * j4 + 1], v.y, acc[k]);
+        acc[k] = fmaf(m[4 * j4 + 2], v.z, acc[k]);
+        acc[k] = fmaf(m[4 * j4 + 3], v.w, acc[k]);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxNb; ++k) acc[k] += __shfl_xor(acc[k], 1);
+    for (int k = 0; k < NB; ++k) acc[k] += __shfl_xor(acc[k], 1);
     if (active && half == 0) {
 #pragma unroll
-      for (int k = 0; k < kMaxNb; ++k) {
-        if (k < nb) {
-          if (row < R) y[k][row] = acc[k];
-          else z[k][row - R] = acc[k];
-        }
+      for (int k = 0; k < NB; ++k) {
+        if (row < R) y[k][row] = acc[k];
+        else z[k][row - R] = acc[k];
       }
     }
     __syncthreads();
-    float pn[kPer];
+    const float *pc = reinterpret_cast<const float *>(&ps4[cur][0][0]);
+    float *pn = reinterpret_cast<float *>(&ps4[cur ^ 1][0][0]);
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int t = tid + i * kRegThreads;
-      pn[i] = 0.f;
-      if (t < nb * R) {
+      if (t < NB * R) {
         const int k = t / R, s = t % R;
-        float az = 2.f * z[k][s], ah = 2.f * ep.H[k] * ps[k][s];
+        float az = 2.f * z[k][s], ah = 2.f * ep.H[k] * pc[k * W + s];
         if (k > 0) {
           az -= z[k - 1][s];
-          ah -= ep.H[k - 1] * ps[k - 1][s];
+          ah -= ep.H[k - 1] * pc[(k - 1) * W + s];
         }
-        if (k + 1 < nb) {
+        if (k + 1 < NB) {
           az -= z[k + 1][s];
-          ah -= ep.H[k + 1] * ps[k + 1][s];
+          ah -= ep.H[k + 1] * pc[(k + 1) * W + s];
         }
-        pn[i] = ps[k][s] + ep.dt * (y[k][s] - ktz * az - ep.inv_zeta * ah);
+        pn[k * W + s] = pc[k * W + s] + ep.dt * (y[k][s] - ktz * az - ep.inv_zeta * ah);
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int t = tid + i * kRegThreads;
-      if (t < nb * R) ps[t / R][t % R] = pn[i];
-    }
-    __syncthreads();
+    cur ^= 1;
   }
-  for (int t = tid; t < nb * R; t += kRegThreads) p[t] = ps[t / R][t % R];
+  const float *pf = reinterpret_cast<const float *>(&ps4[cur][0][0]);
+  for (int t = tid; t < NB * R; t += kRegThreads) p[t] = pf[(t / R) * W + t % R];
+}
+
+template <int kHalf>
+void launch_steps_reg(int nb, const float *XH, const float *XB, float *p, int R, int n, const EvalParams &ep,
+                      hipStream_t s) {
+  switch (nb) {
+    case 1: k_rom_steps_reg<kHalf, 1><<<1, kRegThreads, 0, s>>>(XH, XB, p, R, n, ep); break;
+    case 2: k_rom_steps_reg<kHalf, 2><<<1, kRegThreads, 0, s>>>(XH, XB, p, R, n, ep); break;
+    case 3: k_rom_steps_reg<kHalf, 3><<<1, kRegThreads, 0, s>>>(XH, XB, p, R, n, ep); break;
+    case 4: k_rom_steps_reg<kHalf, 4><<<1, kRegThreads, 0, s>>>(XH, XB, p, R, n, ep); break;
+    default: k_rom_steps_reg<kHalf, 5><<<1, kRegThreads, 0, s>>>(XH, XB, p, R, n, ep); break;
+  }
 }
 
 // tau_ab = (n / P) sum_k H_k p_k^T M_ab p_k (uniform weights), FP64 sums.
@@ -753,10 +769,14 @@ vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every
     if (st != VDS_OK) return st;
     const int n = std::min(freeze_every, nsteps - s0);
     const int nb = c->prob.nb, R = r->R;
-    if (R <= 128)
-      k_rom_steps_reg<64><<<1, kRegThreads, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
+    if (R <= 32)
+      launch_steps_reg<16>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
+    else if (R <= 64)
+      launch_steps_reg<32>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
+    else if (R <= 128)
+      launch_steps_reg<64>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
     else if (R <= 192)
-      k_rom_steps_reg<96><<<1, kRegThreads, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
+      launch_steps_reg<96>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
     else
       k_rom_steps<<<1, 1024, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
   }

@@ -140,6 +140,44 @@ def appendix_a_chain4(P: int = 1000, seed: int = 21, rate: float = 1.0):
                 q0=gaussian_bonds(seed, 3, P, 1.0))
 
 
+# Tables 1-6 (Sections 3.2, 3.3): beads, P, flow, inhomogeneous springs, reduced ranks, and
+# the paper's own T_mor / T_ref and err_MOR(t = 6) (in percent) on its CPU.
+PAPER_TABLES = {
+    "table1_noflow_2bead": dict(beads=2, P=1000, rate=0.0, H_k=False, R=(1, 2, 3, 4, 5, 10, 20, 40),
+                                T_ref_s=394, time_pct=(0.360, 0.605, 0.819, 1.08, 1.43, 3.66, 11.8, 43.3),
+                                err_pct=(4.76, 2.34, 1.04, 0.635, 0.595, 0.816, 0.843, 0.865)),
+    "table2_noflow_3bead": dict(beads=3, P=1000, rate=0.0, H_k=False, R=(1, 2, 3, 4, 5, 10, 20, 40),
+                                T_ref_s=533, time_pct=(0.441, 0.612, 0.758, 0.955, 1.23, 2.82, 8.90, 32.1),
+                                err_pct=(70.8, 12.8, 7.50, 4.47, 2.72, 1.82, 1.98, 1.98)),
+    "table3_shear_2bead": dict(beads=2, P=1000, rate=1.0, H_k=False, R=(10, 15, 20, 25, 30, 40),
+                               T_ref_s=385, time_pct=(3.77, 7.31, 12.2, 18.4, 26.0, 44.9),
+                               err_pct=(10.5, 9.47, 8.76, 8.41, 8.23, 8.08)),
+    "table4_shear_4bead_P1000": dict(beads=4, P=1000, rate=1.0, H_k=False, R=(10, 15, 20, 25, 30, 40),
+                                     T_ref_s=704, time_pct=(2.30, 4.24, 6.89, 10.3, 14.4, 24.8),
+                                     err_pct=(12.5, 6.67, 5.67, 5.00, 4.42, 3.72)),
+    "table5_shear_4bead_P10000": dict(beads=4, P=10000, rate=1.0, H_k=False, R=(10, 15, 20, 25, 30, 40),
+                                      T_ref_s=70104, time_pct=(2.31, 4.30, 6.90, 10.5, 14.8, 25.4),
+                                      err_pct=(13.2, 6.60, 5.99, 5.59, 5.41, 5.18)),
+    "table6_shear_4bead_Hk": dict(beads=4, P=1000, rate=1.0, H_k=True, R=(10, 15, 20, 25, 30, 40),
+                                  T_ref_s=673, time_pct=(2.39, 4.43, 7.20, 10.8, 15.1, 25.8),
+                                  err_pct=(18.3, 11.1, 9.55, 8.36, 7.93, 7.02)),
+}
+
+
+def paper_table_case(name: str, seed: int = 40):
+    """Setting of one of the paper's tables (Section 3.1): thermal-equilibrium
+    start N(0, kT/H_k), zeta = 4, explicit dt = 1e-3 to t = 6, snapshots at
+    L + 1 uniform times in [0, 3] with L = P d / (N - 1) capped at the 3000 steps
+    available, freezes every 300 steps."""
+    t = PAPER_TABLES[name]
+    nb, P = t["beads"] - 1, t["P"]
+    H = np.arange(1, nb + 1, dtype=np.float64) if t["H_k"] else np.ones(nb)
+    L = min(P * D_SPACE // nb, 3000)
+    return dict(name=name, nb=nb, P=P, kT=1.0, zeta=4.0, n=1.0, dt=1e-3, G=shear_gradient(t["rate"]), H=H,
+                steps=6000, snap_until=3000, snapshots=L + 1, freeze_every=300, R=t["R"],
+                q0=gaussian_bonds(seed, nb, P, 1.0 / H), paper=t)
+
+
 def density_grid(D: int, values=(-2.0, 0.0, 2.0)) -> np.ndarray:
     """All points of values^D (Appendix A evaluates the density on {-2, 0, 2}^D)."""
     axes = np.meshgrid(*[np.asarray(values, dtype=np.float64)] * D, indexing="ij")
