@@ -54,9 +54,10 @@ enum { VDS_EXPLICIT = 0, VDS_IMPLICIT = 1 };
  *                       22 significant bits, against 24 for FP32; sums beyond 128 columns
  *                       in FP64 as for the others);
  *   VDS_PAIR_MFMA_F16X2_ALL  both products on FP16 matrix cores with split factors; the
- *                       squared norms enter in FP32.  FP16 range: valid while every centred
- *                       particle lies within about 5e4 h of the weighted mean (the FP32 forms
- *                       lose all accuracy well before that). */
+ *                       squared norms enter in FP32.
+ * The FP16-split forms are valid while every centred particle lies within about 1e3 h of
+ * the weighted mean; further out the rounding of the expanded squared distance can exceed
+ * the FP16 range (the FP32 forms have lost all accuracy there too). */
 enum { VDS_PAIR_MFMA = 0, VDS_PAIR_VALU = 1, VDS_PAIR_MFMA_F16X2 = 2, VDS_PAIR_MFMA_F16X2_ALL = 3 };
 
 /* Problem description (Sections 2.1, 2.2, 3.1; Appendix A).
