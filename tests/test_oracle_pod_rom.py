@@ -98,6 +98,42 @@ def test_rom_exact_without_noise_or_flow_in_invariant_subspace():
     assert np.allclose(p, expect, rtol=1e-12, atol=1e-13)
 
 
+def test_exact_windows_match_the_closed_form_without_noise_or_flow():
+    # kT = 0, G = 0: dp/dt = -(1/zeta) A diag(H) p across bonds, so
+    # p(t) = V exp(t Lambda) V^-1 p(0) with the eigenpairs of -(1/zeta) A diag(H),
+    # whatever the window lengths
+    P = 15
+    rng = np.random.default_rng(19)
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, 5)))
+    p0 = rng.standard_normal((3, 5))
+    q0 = pod.reconstruct(U, p0, P)
+    prob = vds.Problem(nb=3, h=0.5, dt=1e-2, kT=0.0, H=np.array([1.0, 2.0, 3.0]))
+    lam, V = np.linalg.eig(-vds.rouse_matrix(3) @ np.diag(prob.H) / prob.zeta)
+    t = 0.9
+    expect = np.real(V @ np.diag(np.exp(t * lam)) @ np.linalg.inv(V)) @ p0
+    for windows in ([0.9], [0.3, 0.3, 0.3], [0.1, 0.5, 0.25, 0.05]):
+        p = rom.rom_run_windows(U, q0, vds.uniform_weights(P), prob, windows)
+        assert np.allclose(p, expect, rtol=1e-12, atol=1e-13), windows
+
+
+def test_exact_windows_and_euler_agree_to_first_order():
+    # the same freeze schedule: explicit Euler inside the windows differs from the
+    # exact solution by O(dt), so halving dt halves the difference
+    q, prob = _small_case(P=14)
+    P = q.shape[1]
+    U, _ = np.linalg.qr(np.random.default_rng(20).standard_normal((3 * P, 8)))
+    w = vds.uniform_weights(P)
+    exact = rom.rom_run_windows(U, q, w, prob, [0.02, 0.02, 0.02])
+    diffs = []
+    for dt in (2e-3, 1e-3):
+        pr = vds.Problem(nb=prob.nb, h=prob.h, dt=dt, G=prob.G, kT=prob.kT, H=prob.H)
+        n = int(round(0.02 / dt))
+        p = rom.rom_run(U, q, w, pr, 3 * n, freeze_every=n)
+        diffs.append(np.linalg.norm(p - exact) / np.linalg.norm(exact))
+    assert 0.4 < diffs[1] / diffs[0] < 0.6, diffs
+    assert diffs[0] < 0.05
+
+
 def test_weighted_brownian_operator_reduces_to_uniform():
     q, prob = _small_case(P=14)
     P = q.shape[1]
