@@ -157,6 +157,21 @@ def measure_pod_rom(pkg, wl, torch, P):
     ctx.timing_enable(False)
     q_rom = ctx.pod_reconstruct(U, p)
     err_mor = float((q_rom - q).norm() / q.norm())
+    # the same windows integrated exactly, then with windows chosen by the energy law
+    exact = {}
+    for label, adaptive in (("exact_windows", False), ("adaptive_windows", True)):
+        pe = ctx.pod_project(U, q0)
+        rom.run_exact(pe.clone(), 300, 300, adaptive=adaptive, energy_tol=0.1)  # warm-up
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        tau_e, windows, wstats = rom.run_exact(pe, cfg["rom_steps"], cfg["freeze_every"], adaptive=adaptive,
+                                               energy_tol=0.1)
+        torch.cuda.synchronize()
+        T_e = time.perf_counter() - t3
+        exact[label] = {"T_s": T_e, "T_over_T_ref": T_e / T_ref,
+                        "err_mor_t_end": float((ctx.pod_reconstruct(U, pe) - q).norm() / q.norm()),
+                        "stress_rel_err_vs_plain": float(np.linalg.norm(tau_e - tau_ref) / np.linalg.norm(tau_ref)),
+                        **wstats, "window_lengths": [round(w_, 6) for w_ in windows]}
     lam = np.asarray(eig)
     return {
         "workload": f"POD-reduced 4-bead chain, P={P}: reference 2000 implicit steps, 300 snapshots over "
@@ -173,6 +188,7 @@ def measure_pod_rom(pkg, wl, torch, P):
         "gram_rounding_level": float(max(0.0, -lam.min()) / np.clip(lam, 0, None).sum()),
         "gemm_ms": gemm[0], "gemm_tflops": gemm[2] / (gemm[0] * 1e-3) / 1e12 if gemm[0] else None,
         "kernel_gemm_ms_per_freeze": kg[0] / max(1, kg[1]),
+        **exact,
         "kernel_gemm_tflops": kg[2] / (kg[0] * 1e-3) / 1e12 if kg[0] else None,
     }
 
@@ -359,6 +375,7 @@ def main():
     ap.add_argument("--t-end", action="store_true", help="also time the full 500-step run to t_end")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the POD-reduced, batched, learned and FENE measurements")
+    ap.add_argument("--extras", type=str, default="", help="comma-separated subset of the extra measurements")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--learned-runs", type=int, default=24)
     ap.add_argument("--learned-run-steps", type=int, default=300)
@@ -477,6 +494,8 @@ def main():
                          ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20)),
                          ("appendix_a", lambda: measure_appendix_a(pkg, wl, torch)),
                          ("paper_tables", lambda: measure_paper_tables(pkg, wl, torch))):
+            if args.extras and name not in args.extras.split(","):
+                continue
             t0 = time.perf_counter()
             extras[name] = fn()
             print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

@@ -83,6 +83,43 @@ vds_status vds_rom_run(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze
 /* Stress of q~ = U p from p_dev and the M_ab: tau_ab = (n/P) sum_j H_j p_j^T M_ab p_j. */
 vds_status vds_rom_stress(vds_rom rom, const float *p_dev, double *tau_host);
 
+/* ---- exact integration of the frozen windows (beyond the paper) ----------- */
+
+/* Between freezes eq. model_DymReduced is linear with constant coefficients,
+ * so a window of length t_w advances vec(p) (index k R + s) exactly by
+ * exp(t_w L), L the (nb R) x (nb R) generator of the reduced equation with X^B
+ * frozen at the window start (FP64: scaling so that |t_w L / 2^s|_1 <= 1/2, a
+ * degree-12 Taylor polynomial, s squarings; rocBLAS FP64 GEMMs).  The windows
+ * cover nsteps dt; the first is freeze_every dt long.
+ *   adaptive = 0: every window has that length (the last one may be shorter).
+ *   adaptive != 0: after each window the energy law of the reconstructed
+ *   states q~ = U p is checked with the trapezoid rule,
+ *     |F(e) - F(s) - t_w ((W - D)(s) + (W - D)(e)) / 2|
+ *         <= energy_tol t_w ((|W| + D)(s) + (|W| + D)(e)) / 2,
+ *   a window that fails is halved and redone (down to dt, where it is accepted
+ *   and counted as truncated), and one whose gap is under a quarter of its
+ *   bound doubles the next, up to freeze_every dt: the check only ever shortens
+ *   the requested freeze interval.  (The energy law bounds the freeze error of a
+ *   window, not the truncation error of the basis, which grows when a long
+ *   window runs into the part of the trajectory the snapshots did not cover.)
+ * windows_host[max_windows] (NULL with max_windows = 0) receives the accepted
+ * window lengths in order, so the run can be replayed; stats (may be NULL) the
+ * counts.  ws_dev: vds_rom_exact_workspace_bytes bytes of device scratch.
+ * tau_host (may be NULL) as for vds_rom_run.  Synchronises. */
+typedef struct vds_rom_window_stats {
+  int32_t windows;        /* accepted windows */
+  int32_t rejected;       /* windows halved and redone */
+  int32_t truncated;      /* windows accepted at the smallest length dt despite the check */
+  int32_t recorded;       /* entries written to windows_host */
+  double t_reached;       /* time covered */
+  double max_energy_gap;  /* largest accepted gap relative to its bound, times energy_tol */
+} vds_rom_window_stats;
+
+size_t vds_rom_exact_workspace_bytes(const vds_problem *prob, int32_t R);
+vds_status vds_rom_run_exact(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every, int32_t adaptive,
+                             double energy_tol, double *windows_host, int32_t max_windows, void *ws_dev,
+                             size_t ws_bytes, double *tau_host, vds_rom_window_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

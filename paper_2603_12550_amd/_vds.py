@@ -89,6 +89,18 @@ _sigs.update({
     "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_stress": ([_P, _P, C.POINTER(C.c_double)], C.c_int),
 })
+
+
+class vds_rom_window_stats(C.Structure):
+    _fields_ = [("windows", C.c_int32), ("rejected", C.c_int32), ("truncated", C.c_int32), ("recorded", C.c_int32),
+                ("t_reached", C.c_double), ("max_energy_gap", C.c_double)]
+
+
+_sigs.update({
+    "vds_rom_exact_workspace_bytes": ([_P, C.c_int32], C.c_size_t),
+    "vds_rom_run_exact": ([_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_double), C.c_int32,
+                           _P, C.c_size_t, C.POINTER(C.c_double), C.POINTER(vds_rom_window_stats)], C.c_int),
+})
 _sigs.update({
     "vds_batch_workspace_bytes": ([C.c_int32, C.POINTER(C.c_int64), C.c_int32], C.c_size_t),
     "vds_batch_create": ([C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -341,6 +353,21 @@ class Rom:
         tau = (C.c_double * 9)()
         _check(_lib.vds_rom_stress(self.rom, _ptr(p), tau), self.ctx.ctx)
         return np.array(tau[:]).reshape(3, 3)
+
+    def run_exact(self, p, nsteps, freeze_every, adaptive=False, energy_tol=0.1, max_windows=4096):
+        """Windows integrated exactly (see vds_rom_run_exact); returns the
+        stress, the accepted window lengths and the counts."""
+        n = _lib.vds_rom_exact_workspace_bytes(C.byref(self.ctx.prob), self.R)
+        if getattr(self, "ws_exact", None) is None or self.ws_exact.numel() < n:
+            self.ws_exact = torch.empty(n, dtype=torch.uint8, device=self.ctx.device)
+        tau = (C.c_double * 9)()
+        win = (C.c_double * max_windows)()
+        st = vds_rom_window_stats()
+        _check(_lib.vds_rom_run_exact(self.rom, _ptr(p), int(nsteps), int(freeze_every), 1 if adaptive else 0,
+                                      float(energy_tol), win, int(max_windows), _ptr(self.ws_exact), n, tau,
+                                      C.byref(st)), self.ctx.ctx)
+        stats = {f: getattr(st, f) for f, _ in vds_rom_window_stats._fields_}
+        return np.array(tau[:]).reshape(3, 3), list(win[:st.recorded]), stats
 
 
 def _bcheck(status, b=None):

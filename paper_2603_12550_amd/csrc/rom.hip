@@ -10,6 +10,8 @@
 #include <new>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "vds_ctx.h"
 #include "vds_linalg.h"
 #include "vds_pod.h"
@@ -507,6 +509,49 @@ void launch_steps_reg(int nb, const float *XH, const float *XB, float *p, int R,
   }
 }
 
+// ---- exact integration of a frozen window --------------------------------
+//
+// Generator of eq. model_DymReduced on vec(p) (index i = k R + s), column-major:
+// L[i + l n] with l = j R + u,
+//   delta_kj X^H_su - (kT/zeta) A_kj X^B_su - (1/zeta) A_kj H_j delta_su.
+__global__ void k_generator(const float *__restrict__ XH, const float *__restrict__ XB, int nb, int R,
+                            EvalParams ep, double *__restrict__ Lm) {
+  const int64_t n = (int64_t)nb * R;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t i = t % n, l = t / n;
+  const int k = (int)(i / R), s = (int)(i % R), j = (int)(l / R), u = (int)(l % R);
+  const double A = k == j ? 2.0 : ((k - j == 1 || j - k == 1) ? -1.0 : 0.0);
+  double v = -(double)ep.kT * (double)ep.inv_zeta * A * (double)XB[(int64_t)s * R + u];
+  if (k == j) v += (double)XH[(int64_t)s * R + u];
+  if (s == u) v -= (double)ep.inv_zeta * A * (double)ep.H[j];
+  Lm[t] = v;
+}
+
+// Largest absolute column sum of a column-major n x n matrix, per column.
+__global__ void k_colabs(const double *__restrict__ Lm, int64_t n, double *__restrict__ cs) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= n) return;
+  double a = 0.0;
+  for (int64_t i = 0; i < n; ++i) a += fabs(Lm[i + l * n]);
+  cs[l] = a;
+}
+
+__global__ void k_scale64(const double *__restrict__ a, double f, int64_t n, double *__restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) b[t] = f * a[t];
+}
+
+__global__ void k_identity64(int64_t n, double *__restrict__ M) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n * n) M[t] = (t % n == t / n) ? 1.0 : 0.0;
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ a, int64_t n, float *__restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) b[t] = (float)a[t];
+}
+
 // tau_ab = (n / P) sum_k H_k p_k^T M_ab p_k (uniform weights), FP64 sums.
 __global__ __launch_bounds__(256) void k_rom_stress(const float *__restrict__ Mbig, const float *__restrict__ p, int nb,
                                                     int R, EvalParams ep, double *__restrict__ out) {
@@ -551,28 +596,32 @@ vds_status rom_gemm(vds_rom r, GemmShape g, double flops) {
 }
 
 // X^B1, X^B2 (and X^B = X^B1 + X^B2) at q~ = U p.
+// q~ = U p into r->qt.
+void reconstruct_qt(vds_rom r, const float *p) {
+  vds_ctx c = r->ctx;
+  const int64_t m = 3 * c->prob.P;
+  GemmShape g;
+  g.M = (int)m;
+  g.N = c->prob.nb;
+  g.K = r->R;
+  g.A = r->U;
+  g.lda = m;
+  g.a_mn = true;
+  g.B = p;
+  g.ldb = r->R;
+  g.C = r->qt;
+  g.ldc = m;
+  g.c_colmajor = true;
+  timed(c, VDS_TIMER_PROJ, 4.0 * m * r->R, [&] { launch_gemm(g, r->part, c->stream); });
+}
+
 vds_status freeze(vds_rom r, const float *p) {
   vds_ctx c = r->ctx;
   const int R = r->R;
-  const int64_t P = c->prob.P, Ppad = c->ep.Ppad, m = 3 * P;
+  const int64_t P = c->prob.P, Ppad = c->ep.Ppad;
   const RomLayout &L = r->L;
   hipStream_t s = c->stream;
-  // q~ = U p
-  {
-    GemmShape g;
-    g.M = (int)m;
-    g.N = c->prob.nb;
-    g.K = R;
-    g.A = r->U;
-    g.lda = m;
-    g.a_mn = true;
-    g.B = p;
-    g.ldb = R;
-    g.C = r->qt;
-    g.ldc = m;
-    g.c_colmajor = true;
-    timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] { launch_gemm(g, r->part, s); });
-  }
+  reconstruct_qt(r, p);
   // S and T at q~ (uniform weights), Q/K operands for Z
   eval_pass_a(c, r->qt, nullptr, nullptr);
   eval_pass_b(c, nullptr);
@@ -758,6 +807,139 @@ vds_status vds_rom_stress(vds_rom r, const float *p, double *tau) {
   vds_status st = hip_check(c, hipMemcpyAsync(tau, r->red, sizeof(double) * 9, hipMemcpyDeviceToHost, c->stream), "copy");
   if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
   return st;
+}
+
+size_t vds_rom_exact_workspace_bytes(const vds_problem *prob, int32_t R) {
+  if (prob == nullptr || R < 1 || prob->nb < 1) return 0;
+  const size_t n = (size_t)prob->nb * R;
+  return sizeof(double) * (4 * n * n + 4 * n) + 8 * 256;
+}
+
+vds_status vds_rom_run_exact(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, int32_t adaptive,
+                             double energy_tol, double *windows_host, int32_t max_windows, void *ws,
+                             size_t ws_bytes, double *tau, vds_rom_window_stats *stats) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  vds_ctx c = r->ctx;
+  if (!p || nsteps < 0 || freeze_every < 1 || !ws || (windows_host == nullptr) != (max_windows <= 0) ||
+      (adaptive && !(energy_tol > 0.0)))
+    return set_err(c, VDS_ERR_ARG, "bad arguments");
+  const int nb = c->prob.nb, R = r->R;
+  const int64_t n = (int64_t)nb * R;
+  if (ws_bytes < vds_rom_exact_workspace_bytes(&c->prob, R)) return set_err(c, VDS_ERR_NOMEM, "workspace too small");
+  hipStream_t s = c->stream;
+  // workspace: generator, B = scaled generator, two Horner / squaring buffers, vectors
+  auto take = [&, off = size_t(0)](size_t bytes) mutable {
+    char *q = static_cast<char *>(ws) + off;
+    off += (bytes + 255) / 256 * 256;
+    return reinterpret_cast<double *>(q);
+  };
+  double *Lm = take(sizeof(double) * n * n), *Bm = take(sizeof(double) * n * n);
+  double *Tm = take(sizeof(double) * n * n), *Cm = take(sizeof(double) * n * n);
+  double *pv = take(sizeof(double) * n), *pw = take(sizeof(double) * n), *cs = take(sizeof(double) * n);
+  float *ptrial = reinterpret_cast<float *>(take(sizeof(float) * n));  // trial state of an adaptive window
+  rocblas_handle hb = nullptr;
+  if (rocblas_create_handle(&hb) != rocblas_status_success) return set_err(c, VDS_ERR_HIP, "rocblas_create_handle");
+  rocblas_set_stream(hb, s);
+  rocblas_set_pointer_mode(hb, rocblas_pointer_mode_host);
+  vds_status st = VDS_OK;
+  const unsigned nn_blocks = (unsigned)nblk256(n * n);
+  std::vector<double> hcs(n);
+
+  // p <- exp(tw L) p with the generator L frozen at the window start (in Lm)
+  auto advance = [&](double tw, float *pout) -> vds_status {
+    k_colabs<<<(unsigned)nblk256(n), 256, 0, s>>>(Lm, n, cs);
+    vds_status e = hip_check(c, hipMemcpyAsync(hcs.data(), cs, sizeof(double) * n, hipMemcpyDeviceToHost, s), "copy");
+    if (e == VDS_OK) e = hip_check(c, hipStreamSynchronize(s), "synchronise");
+    if (e != VDS_OK) return e;
+    const double norm = tw * *std::max_element(hcs.begin(), hcs.end());
+    // scaling: |B|_1 <= 1/2, where the degree-12 Taylor remainder is below 2e-14
+    int sq = 0;
+    while (norm / std::ldexp(1.0, sq) > 0.5) ++sq;
+    k_scale64<<<nn_blocks, 256, 0, s>>>(Lm, tw / std::ldexp(1.0, sq), n * n, Bm);
+    k_identity64<<<nn_blocks, 256, 0, s>>>(n, Tm);
+    double *T = Tm, *C = Cm;
+    const double one = 1.0, zero = 0.0;
+    for (int k = 12; k >= 1; --k) {  // Horner: T <- I + B T / k
+      k_identity64<<<nn_blocks, 256, 0, s>>>(n, C);
+      const double a = 1.0 / k;
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, (int)n, (int)n, &a, Bm, (int)n,
+                        T, (int)n, &one, C, (int)n) != rocblas_status_success)
+        return set_err(c, VDS_ERR_HIP, "rocblas_dgemm");
+      std::swap(T, C);
+    }
+    for (int i = 0; i < sq; ++i) {  // squaring: T <- T T
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, (int)n, (int)n, &one, T, (int)n,
+                        T, (int)n, &zero, C, (int)n) != rocblas_status_success)
+        return set_err(c, VDS_ERR_HIP, "rocblas_dgemm");
+      std::swap(T, C);
+    }
+    launch_f32_to_f64(p, pv, n, s);
+    if (rocblas_dgemv(hb, rocblas_operation_none, (int)n, (int)n, &one, T, (int)n, pv, 1, &zero, pw, 1) !=
+        rocblas_status_success)
+      return set_err(c, VDS_ERR_HIP, "rocblas_dgemv");
+    k_f64_to_f32<<<(unsigned)nblk256(n), 256, 0, s>>>(pw, n, pout);
+    return hip_check(c, hipGetLastError(), "window");
+  };
+  // F, dissipation, work of the reconstructed state q~ = U p
+  auto energy = [&](const float *pp, double *F, double *Dg, double *W) {
+    reconstruct_qt(r, pp);
+    return vds_energy(c, r->qt, nullptr, F, Dg, W);
+  };
+
+  const double dt = c->prob.dt, t_total = nsteps * dt, tw_max = freeze_every * dt;
+  double t = 0.0, tw = tw_max, max_gap = 0.0;
+  int windows = 0, rejected = 0, recorded = 0, truncated = 0;
+  double F0 = 0, D0 = 0, W0 = 0;
+  if (adaptive && nsteps > 0) st = energy(p, &F0, &D0, &W0);
+  while (st == VDS_OK && t < t_total - 0.5 * dt) {
+    tw = std::min(tw, t_total - t);
+    st = freeze(r, p);
+    if (st != VDS_OK) break;
+    k_generator<<<nn_blocks, 256, 0, s>>>(r->XH, r->XB, nb, R, c->ep, Lm);
+    double gap = 0.0;
+    for (;;) {
+      st = advance(tw, adaptive ? ptrial : p);
+      if (st != VDS_OK || !adaptive) break;
+      double F1, D1, W1;
+      st = energy(ptrial, &F1, &D1, &W1);
+      if (st != VDS_OK) break;
+      const double bound = energy_tol * tw * 0.5 * (std::fabs(W0) + D0 + std::fabs(W1) + D1);
+      gap = std::fabs(F1 - F0 - tw * 0.5 * ((W0 - D0) + (W1 - D1)));
+      if (gap <= bound || tw <= dt * (1.0 + 1e-9)) {
+        if (gap > bound) ++truncated;  // accepted at the smallest window
+        st = hip_check(c, hipMemcpyAsync(p, ptrial, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "copy");
+        max_gap = std::max(max_gap, bound > 0 ? gap / bound * energy_tol : gap);
+        F0 = F1;
+        D0 = D1;
+        W0 = W1;
+        break;
+      }
+      ++rejected;
+      tw = std::max(dt, 0.5 * tw);
+    }
+    if (st != VDS_OK) break;
+    t += tw;
+    ++windows;
+    if (windows_host && recorded < max_windows) windows_host[recorded++] = tw;
+    if (adaptive) {
+      const double bound = energy_tol * tw * 0.5 * (std::fabs(W0) + D0);
+      if (gap < 0.25 * bound) tw = std::min(2.0 * tw, tw_max);  // grows back, up to the requested interval
+    }
+  }
+  rocblas_destroy_handle(hb);
+  if (st != VDS_OK) return st;
+  if (stats) {
+    stats->windows = windows;
+    stats->rejected = rejected;
+    stats->truncated = truncated;
+    stats->recorded = recorded;
+    stats->t_reached = t;
+    stats->max_energy_gap = max_gap;
+  }
+  st = hip_check(c, hipGetLastError(), "exact windows");
+  if (st != VDS_OK) return st;
+  if (tau) return vds_rom_stress(r, p, tau);
+  return hip_check(c, hipStreamSynchronize(s), "synchronise");
 }
 
 vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {

@@ -236,3 +236,61 @@ def test_rom_operators_match_projected_kernel_terms_full_size(lib):
         assert _rel(lhs2, rhs2) < 1e-4, j
         assert _rel(lhsH, rhsH) < 1e-4, j
     assert np.abs(Un @ Un.T - np.eye(R)).max() < 1e-4
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_rom_exact_windows_match_oracle(lib, tuning):
+    # windows integrated exactly (matrix exponential of the frozen generator)
+    P, R = 300, 12
+    U32, Uf, p32, prob = _small_rom_case(P, R, seed=7)
+    ctx = _tuned(lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True), tuning)
+    _say(f"exact reduced windows P=300 R=12 tuning {tuning}")
+    rom = lib.Rom(ctx, _dev(U32))
+    p = _dev(p32)
+    tau, windows, stats = rom.run_exact(p, nsteps=30, freeze_every=10)
+    assert stats["windows"] == 3 and stats["rejected"] == 0 and np.allclose(windows, [0.01] * 3)
+    q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    w = ovds.uniform_weights(P)
+    p_o = orom.rom_run_windows(Uf, q0, w, prob, windows)
+    assert _rel(_np(p), p_o) < 1e-4
+    tau_o = orom.reduced_stress(Uf, p_o, w, prob, P)
+    assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
+
+
+def test_rom_exact_adaptive_windows_replay_in_oracle(lib):
+    # the adaptive run picks its windows from the energy law; given that schedule
+    # the result is unique, so the oracle replays it
+    P, R = 300, 12
+    U32, Uf, p32, prob = _small_rom_case(P, R, seed=8)
+    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    rom = lib.Rom(ctx, _dev(U32))
+    p = _dev(p32)
+    _say("adaptive exact reduced windows P=300 R=12")
+    tau, windows, stats = rom.run_exact(p, nsteps=200, freeze_every=20, adaptive=True, energy_tol=0.2)
+    _say(stats, windows)
+    assert stats["windows"] == len(windows) and abs(sum(windows) - 0.2) < 1e-9
+    assert stats["t_reached"] == pytest.approx(0.2, rel=1e-9)
+    q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    w = ovds.uniform_weights(P)
+    p_o = orom.rom_run_windows(Uf, q0, w, prob, windows)
+    assert _rel(_np(p), p_o) < 1e-4
+
+
+def test_rom_exact_windows_closed_form_without_noise_or_flow(lib):
+    # kT = 0, G = 0, q(0) in span U: p(t) = exp(-t A diag(H) / zeta) p(0) for any windows
+    P, R = 40, 6
+    rng = np.random.default_rng(21)
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, R)))
+    U32 = wl.to_f32(U.T)
+    Uf = U32.astype(np.float64).T
+    p0 = rng.standard_normal((2, R))
+    H = np.array([1.0, 3.0])
+    ctx = lib.Context(2, P, 0.5, H=H, G=np.zeros((3, 3)), dt=1e-3, kT=0.0, scheme="explicit", poison=True)
+    rom = lib.Rom(ctx, _dev(U32))
+    q0 = opod.reconstruct(Uf, p0, P)
+    p = ctx.pod_project(_dev(U32), _dev(q0))
+    p_start = _np(p)
+    rom.run_exact(p, nsteps=700, freeze_every=250)
+    lam, V = np.linalg.eig(-ovds.rouse_matrix(2) @ np.diag(H) / 4.0)
+    expect = np.real(V @ np.diag(np.exp(0.7 * lam)) @ np.linalg.inv(V)) @ p_start
+    assert _rel(_np(p), expect) < 1e-5
