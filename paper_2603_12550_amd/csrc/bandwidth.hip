@@ -86,7 +86,7 @@ vds_status vds_median_bandwidth(vds_ctx c, const float *q, double *med_out, doub
   if (P < 2) return set_err(c, VDS_ERR_ARG, "the median rule needs P >= 2");
   const EvalParams &e = c->ep;
   // centred particle-major coordinates (differences are unchanged by centring)
-  launch_mean_partials(e, q, nullptr, c->meanp, nullptr, c->stream);
+  launch_mean_partials(e, q, nullptr, c->meanp, nullptr, nullptr, c->stream);
   launch_prep(e, q, nullptr, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr,
               c->stream);
 

@@ -111,8 +111,18 @@ __device__ void mean_partials_body(const EvalParams &p, int64_t lb, const float 
 
 __global__ __launch_bounds__(kRedBlock) void k_mean_partials(EvalParams p, const float *__restrict__ q,
                                                              const float *__restrict__ w, double *__restrict__ meanp,
-                                                             const int *__restrict__ done) {
+                                                             const int *done, Ctrl *begin) {
   if (done != nullptr && *done) return;
+  if (begin != nullptr) {
+    // opens a queued implicit step (no other block of this launch reads
+    // the fields that block 0 clears)
+    if (begin->halted) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      begin->done = 0;
+      begin->conv_iter = -1;
+      begin->checked = 0;
+    }
+  }
   mean_partials_body(p, blockIdx.x, q, w, meanp);
 }
 
@@ -152,6 +162,43 @@ __device__ inline float gsum(float v) {
 #pragma unroll
   for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
   return v;
+}
+
+// Convergence test of fixed-point iteration chk.iter from the combine kernel's
+// block maxima of |dx| and |x|: max|dx| <= rtol * max(1, max|x|).  Every block
+// of the calling launch evaluates it (the maxima are the previous kernel's
+// output, so the launch boundary orders them) and gets the same answer;
+// *resid receives max|dx|.
+__device__ bool picard_converged(const PicardCheck &chk, const float *__restrict__ blockmax, int nblk,
+                                 float *resid) {
+  __shared__ float sr[kRedBlock / 64], sx[kRedBlock / 64];
+  __shared__ int conv;
+  __shared__ float rr;
+  float r = 0.f, x = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
+    r = fmaxf(r, blockmax[2 * b]);
+    x = fmaxf(x, blockmax[2 * b + 1]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    r = fmaxf(r, __shfl_xor(r, off));
+    x = fmaxf(x, __shfl_xor(x, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sr[threadIdx.x >> 6] = r;
+    sx[threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kRedBlock / 64; ++i) {
+      r = fmaxf(r, sr[i]);
+      x = fmaxf(x, sx[i]);
+    }
+    rr = r;
+    conv = r <= chk.rtol * fmaxf(1.f, x) ? 1 : 0;
+  }
+  __syncthreads();
+  *resid = rr;
+  return conv != 0;
 }
 
 // Centre, pack Q/K operands and the pass-A V operand (weights w; over their
@@ -215,8 +262,35 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
                                                     int nmeanp, float *__restrict__ xc, float *__restrict__ wv,
                                                     float *__restrict__ QB, float *__restrict__ KA,
                                                     float *__restrict__ VA, float *__restrict__ wscale,
-                                                    F16Operands f16, const int *__restrict__ done) {
-  if (done != nullptr && *done) return;
+                                                    F16Operands f16, PicardCheck chk,
+                                                    const float *__restrict__ blockmax, int nblk_chk,
+                                                    const int *done) {
+  if (chk.ctrl != nullptr) {
+    // block 0 of this launch may set *done: one read per block keeps the
+    // block's waves together (a block that sees it set returns, as it would
+    // after the test below)
+    __shared__ int skip;
+    if (threadIdx.x == 0) skip = done != nullptr ? *done : 0;
+    __syncthreads();
+    if (skip) return;
+  } else if (done != nullptr && *done) {
+    return;
+  }
+  if (chk.ctrl != nullptr) {
+    // test the previous iteration first: once it has converged this one and
+    // every later kernel of the step do nothing
+    float r;
+    const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      chk.ctrl->last_resid = r;
+      chk.ctrl->checked = chk.iter + 1;
+      if (conv) {
+        chk.ctrl->conv_iter = chk.iter;
+        chk.ctrl->done = 1;
+      }
+    }
+    if (conv) return;
+  }
   prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16);
 }
 
@@ -266,12 +340,13 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const fl
 
 // Pass-B finalisation and everything local: term2, b = term1 + term2,
 // g = kT b + grad Psi, u = -(1/zeta)(A (x) I) g, flow G q, and by mode the
-// terms, the velocity, an explicit update or a fixed-point update.  With `obs`
-// it also accumulates F_h, dissipation, work and stress in FP64.
+// terms, the velocity, an explicit update or a fixed-point update (whose flow
+// term is taken at the step's start state qs).  With `obs` it also
+// accumulates F_h, dissipation, work and stress in FP64.
 __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs, const float *__restrict__ partial,
                              int splits, const float *__restrict__ xc, const float *__restrict__ t1,
                              const float *__restrict__ S, const float *__restrict__ wv, const float *qin,
-                             const float *__restrict__ qstar, float *out, float *out2, double *__restrict__ redp,
+                             const float *__restrict__ qs, float *out, float *out2, double *__restrict__ redp,
                              float *__restrict__ blockmax) {
   __shared__ double sm[12][kRedBlock];
   const int64_t I = group_particle(lb);
@@ -316,6 +391,12 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
     if (k > 0) Ag -= gm;
     if (k + 1 < p.nb) Ag -= gpl;
     const float flow = p.G[3 * (al % 3)] * q0 + p.G[3 * (al % 3) + 1] * q1 + p.G[3 * (al % 3) + 2] * q2;
+    float qstart = 0.f, flow0 = 0.f;
+    if (mode == MODE_PICARD) {
+      qstart = comp ? qs[idx] : 0.f;
+      const float s0 = gshfl(qstart, base), s1 = gshfl(qstart, base + 1), s2 = gshfl(qstart, base + 2);
+      flow0 = p.G[3 * (al % 3)] * s0 + p.G[3 * (al % 3) + 1] * s1 + p.G[3 * (al % 3) + 2] * s2;
+    }
     const float u = -p.inv_zeta * Ag;
     if (comp) {
       if (mode == MODE_VELOCITY) {
@@ -323,7 +404,7 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
       } else if (mode == MODE_EXPLICIT) {
         out[idx] = qv + p.dt * (flow + u);
       } else if (mode == MODE_PICARD) {
-        const float xn = qstar[idx] + p.dt * u;
+        const float xn = qstart + p.dt * (flow0 + u);
         out[idx] = xn;
         resid = fabsf(xn - qv);
         xmax = fabsf(xn);
@@ -377,11 +458,11 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
                                                        const float *__restrict__ partial, int splits,
                                                        const float *__restrict__ xc, const float *__restrict__ t1,
                                                        const float *__restrict__ S, const float *__restrict__ wv,
-                                                       const float *qin, const float *__restrict__ qstar,
+                                                       const float *qin, const float *__restrict__ qs,
                                                        float *out, float *out2, double *__restrict__ redp,
                                                        float *__restrict__ blockmax, const int *__restrict__ done) {
   if (done != nullptr && *done) return;
-  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qstar, out, out2, redp, blockmax);
+  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qs, out, out2, redp, blockmax);
 }
 
 __global__ void k_reduce_final(const double *__restrict__ redp, int nblk, int nslots, double *__restrict__ out,
@@ -394,44 +475,19 @@ __global__ void k_reduce_final(const double *__restrict__ redp, int nblk, int ns
   out[s] = acc;
 }
 
-// q* = q + dt G q (the flow term of the implicit step is taken at t).
-__global__ __launch_bounds__(kRedBlock) void k_qstar(EvalParams p, const float *__restrict__ q,
-                                                     float *__restrict__ qstar) {
-  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
-  if (i >= (int64_t)p.nb * p.P) return;
-  const float a = q[i * 3], b = q[i * 3 + 1], c = q[i * 3 + 2];
-#pragma unroll
-  for (int al = 0; al < 3; ++al)
-    qstar[i * 3 + al] = q[i * 3 + al] + p.dt * (p.G[3 * al] * a + p.G[3 * al + 1] * b + p.G[3 * al + 2] * c);
-}
-
-// Convergence test of the fixed-point iteration: max over the combine kernel's
-// block maxima, then max|dx| <= rtol * max(1, max|x|).
-__global__ __launch_bounds__(kRedBlock) void k_picard_check(Ctrl *ctrl, const float *__restrict__ blockmax, int nblk,
-                                                            float rtol, int iter) {
-  __shared__ float sr[kRedBlock], sx[kRedBlock];
+// Stand-alone convergence test (host-driven iterations).
+__global__ __launch_bounds__(kRedBlock) void k_picard_check(PicardCheck chk, const float *__restrict__ blockmax,
+                                                            int nblk_chk) {
+  Ctrl *ctrl = chk.ctrl;
   if (ctrl->done) return;
-  float r = 0.f, x = 0.f;
-  for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
-    r = fmaxf(r, blockmax[2 * b]);
-    x = fmaxf(x, blockmax[2 * b + 1]);
-  }
-  sr[threadIdx.x] = r;
-  sx[threadIdx.x] = x;
-  __syncthreads();
-  for (int st = kRedBlock / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      sr[threadIdx.x] = fmaxf(sr[threadIdx.x], sr[threadIdx.x + st]);
-      sx[threadIdx.x] = fmaxf(sx[threadIdx.x], sx[threadIdx.x + st]);
-    }
-    __syncthreads();
-  }
+  float r;
+  const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
   if (threadIdx.x != 0) return;
-  ctrl->last_resid = sr[0];
-  ctrl->checked = iter + 1;
-  if (sr[0] <= rtol * fmaxf(1.f, sx[0])) {
+  ctrl->last_resid = r;
+  ctrl->checked = chk.iter + 1;
+  if (conv) {
+    ctrl->conv_iter = chk.iter;
     ctrl->done = 1;
-    ctrl->conv_iter = iter;
   }
 }
 
@@ -441,6 +497,56 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
   ctrl->conv_iter = -1;
   ctrl->last_resid = 0.f;
   ctrl->checked = 0;
+  ctrl->halted = 0;
+  ctrl->steps_done = 0;
+  ctrl->last_iters = 0;
+  ctrl->total_iters = 0;
+}
+
+// End of a queued implicit step (see launch_step_end).  Only block 0 writes
+// *ctrl.  If another block sees its `halted` or `done` of this launch, the
+// step did not converge (conv_iter is still -1 then) and it returns as block
+// 0 does.
+__global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck chk, const float *__restrict__ blockmax,
+                                                        int nblk_chk, const float *__restrict__ xb0,
+                                                        const float *__restrict__ xb1, float *__restrict__ q,
+                                                        int64_t n) {
+  // block 0 may set `halted` and `done` during this launch: one read per
+  // block keeps the block's waves together
+  __shared__ int st[3];
+  if (threadIdx.x == 0) {
+    st[0] = ctrl->halted;
+    st[1] = ctrl->done;
+    st[2] = ctrl->conv_iter;
+  }
+  __syncthreads();
+  if (st[0]) return;
+  int it;
+  if (st[1]) {
+    it = st[2];  // converged at an earlier test of this step
+    if (it < 0) return;
+  } else {
+    float r;
+    const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->last_resid = r;
+      ctrl->checked = chk.iter + 1;
+      if (!conv) {
+        ctrl->halted = 1;
+        ctrl->done = 1;
+      }
+    }
+    if (!conv) return;
+    it = chk.iter;
+  }
+  const float *src = (it & 1) ? xb1 : xb0;
+  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (i < n) q[i] = src[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->steps_done += 1;
+    ctrl->last_iters = it + 1;
+    ctrl->total_iters += it + 1;
+  }
 }
 
 __device__ void stress_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
@@ -587,35 +693,38 @@ __global__ void k_batch_stress_sum(const EnsDesc *__restrict__ ens, const double
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + kRedBlock - 1) / kRedBlock); }
 
 void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done,
-                          hipStream_t s) {
-  k_mean_partials<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, meanp, done);
+                          Ctrl *begin, hipStream_t s) {
+  k_mean_partials<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, meanp, done, begin);
 }
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
                  float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16, const int *done,
-                 hipStream_t s) {
+                 hipStream_t s, const PicardCheck *chk, const float *blockmax, int nblk_chk) {
   const F16Operands ops = f16 != nullptr ? *f16 : F16Operands{nullptr, nullptr, nullptr};
-  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, done);
+  const PicardCheck c = chk != nullptr ? *chk : PicardCheck{nullptr, 0.f, 0};
+  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, c,
+                                                    blockmax, nblk_chk, done);
 }
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {
   k_finalize_a<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, partial, splits, xc, wv, S, t1, VB, done);
 }
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
-                    const float *t1, const float *S, const float *wv, const float *qin, const float *qstar,
+                    const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
                     float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s) {
-  k_combine<<<nblocks(p.P * 16), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, qstar,
+  k_combine<<<nblocks(p.P * 16), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, q0,
                                                     out, out2, redp, blockmax, done);
 }
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s) {
   k_reduce_final<<<1, 64, 0, s>>>(redp, nblk, nslots, out, done);
 }
-void launch_qstar(const EvalParams &p, const float *q, float *qstar, hipStream_t s) {
-  k_qstar<<<nblocks((int64_t)p.nb * p.P), kRedBlock, 0, s>>>(p, q, qstar);
-}
-void launch_picard_check(Ctrl *ctrl, const float *blockmax, int nblk, float rtol, int iter, hipStream_t s) {
-  k_picard_check<<<1, kRedBlock, 0, s>>>(ctrl, blockmax, nblk, rtol, iter);
-}
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s) { k_ctrl_reset<<<1, 64, 0, s>>>(ctrl); }
+void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
+                     const float *xb1, float *q, int64_t n, hipStream_t s) {
+  k_step_end<<<nblocks(n), kRedBlock, 0, s>>>(ctrl, chk, blockmax, nblk_chk, xb0, xb1, q, n);
+}
+void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s) {
+  k_picard_check<<<1, kRedBlock, 0, s>>>(chk, blockmax, nblk_chk);
+}
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s) {
   k_stress<<<nblocks(p.P), kRedBlock, 0, s>>>(p, q, w, redp);
 }

@@ -65,10 +65,11 @@ void apply_tuning(vds_ctx c, const vds_tuning &t) {
   c->ep.qhalf = t.impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
 }
 
-void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done) {
+void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre, const PicardCheck *chk) {
   const EvalParams &e = c->ep;
-  launch_mean_partials(e, q, w, c->meanp, done, c->stream);
-  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done, c->stream);
+  if (centre) launch_mean_partials(e, q, w, c->meanp, done, nullptr, c->stream);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done, c->stream,
+              chk, c->blockmax, c->nblk_comb);
   pair_pass(c, c->VA, c->wscale, done);
   launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
 }
@@ -138,7 +139,6 @@ Layout make_layout(const vds_problem &p) {
   L.KH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
   L.RN = take(sizeof(float) * Ppad);
   L.hist = take(sizeof(unsigned long long) * 2 * kHistBins);
-  L.qstar = take(sizeof(float) * p.P * D);
   L.xb0 = take(sizeof(float) * p.P * D);
   L.xb1 = take(sizeof(float) * p.P * D);
   L.total = off;
@@ -189,13 +189,17 @@ void drain_timers(vds_ctx c) {
   }
 }
 
-// Prep + pass A + finalize A + pass B + combine(mode).
-void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, const float *qstar, float *out,
-              float *out2, const int *done) {
+// Prep + pass A + finalize A + pass B + combine(mode).  Without `centre` the
+// centring partials already in the workspace are used (the fixed-point
+// iterations of a step all centre at the step's start state: the sums are
+// differences, so any centre near the particles gives the same result).
+// `chk` (fixed-point mode) makes the prep kernel test the previous iteration.
+void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, const float *q0, float *out,
+              float *out2, const int *done, const PicardCheck *chk = nullptr, bool centre = true) {
   const EvalParams &e = c->ep;
-  eval_pass_a(c, q, w, done);
+  eval_pass_a(c, q, w, done, centre, chk);
   eval_pass_b(c, done);
-  launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, qstar, out, out2, c->redp,
+  launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, q0, out, out2, c->redp,
                  c->blockmax, done, c->stream);
   if (obs) launch_reduce_final(c->redp, c->nblk_comb, 12, c->redout, done, c->stream);
 }
@@ -309,7 +313,6 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->wscale = reinterpret_cast<float *>(c->ws + L.wscale);
   c->f16 = F16Operands{c->ws + L.QH, c->ws + L.KH, reinterpret_cast<float *>(c->ws + L.RN)};
   c->hist = reinterpret_cast<unsigned long long *>(c->ws + L.hist);
-  c->qstar = reinterpret_cast<float *>(c->ws + L.qstar);
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
   c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);
   return VDS_OK;
@@ -348,68 +351,143 @@ vds_status vds_velocity(vds_ctx c, const float *q, const float *w, float *v, vds
   return fetch_obs(c, d);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Implicit steps queued on the stream between two host synchronisations.
+constexpr int kQueueSteps = 64;
+
+struct StepCounts {
+  int total_iters = 0, last_iters = 0;
+  float last_resid = 0.f;
+};
+
+// Finishes the fixed-point iteration of one implicit step from iteration m0
+// (xb[(m0 - 1) & 1] holds iterate m0 - 1 when m0 > 0; q holds the step's start
+// state), checking convergence on the host every picard_batch iterations, and
+// writes the converged iterate to q.
+vds_status finish_step(vds_ctx c, float *q, const float *w, int m0, StepCounts &n) {
+  const vds_problem &p = c->prob;
+  const int64_t nq = (int64_t)p.P * c->ep.D;
+  launch_ctrl_reset(c->ctrl, c->stream);
+  launch_mean_partials(c->ep, q, w, c->meanp, nullptr, nullptr, c->stream);
+  const int *done = &c->ctrl->done;
+  int m = m0;
+  Ctrl h{};
+  h.last_resid = n.last_resid;  // the residual of iteration m0 - 1, if no further one runs
+  bool converged = false;
+  while (m < p.picard_max) {
+    const int batch = std::min(p.picard_batch, p.picard_max - m);
+    for (int b = 0; b < batch; ++b, ++m) {
+      const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
+      evaluate(c, xin, w, MODE_PICARD, false, q, c->xb[m & 1], nullptr, done, nullptr, false);
+      launch_picard_check(PicardCheck{c->ctrl, (float)p.picard_rtol, m}, c->blockmax, c->nblk_comb, c->stream);
+    }
+    vds_status st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream),
+                              "copy ctrl");
+    if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+    if (st != VDS_OK) return st;
+    if (h.done) {
+      converged = true;
+      break;
+    }
+  }
+  const int final_iter = converged ? h.conv_iter : m - 1;
+  if (final_iter >= 0) {
+    vds_status st = hip_check(
+        c, hipMemcpyAsync(q, c->xb[final_iter & 1], sizeof(float) * nq, hipMemcpyDeviceToDevice, c->stream),
+        "copy state");
+    if (st != VDS_OK) return st;
+  }
+  n.last_iters = final_iter + 1;
+  n.total_iters += n.last_iters;
+  n.last_resid = h.last_resid;
+  if (!converged) return set_err(c, VDS_ERR_NOT_CONVERGED, "fixed-point iteration reached picard_max");
+  return VDS_OK;
+}
+
+// Implicit Euler steps (eq. implicit) with the fixed-point iteration run from
+// the device: each step is queued with picard_batch iterations, the prep
+// kernel of each iteration tests the one before (the step-end kernel tests
+// the last), the iterations queued past convergence return at once, and the
+// step-end kernel writes the converged iterate back.  A step
+// that has not converged after its queued iterations halts the queue (every
+// later kernel returns at once); the host then finishes that step and queues
+// the rest.  The host synchronises once per kQueueSteps steps.
+vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepCounts &n, int &steps_taken) {
+  const vds_problem &p = c->prob;
+  const int64_t nq = (int64_t)p.P * c->ep.D;
+  const int batch = std::min(p.picard_batch, p.picard_max);
+  const int *done = &c->ctrl->done;
+  steps_taken = 0;
+  while (steps_taken < nsteps) {
+    const int chunk = std::min(nsteps - steps_taken, kQueueSteps);
+    launch_ctrl_reset(c->ctrl, c->stream);
+    for (int j = 0; j < chunk; ++j) {
+      launch_mean_partials(c->ep, q, w, c->meanp, nullptr, c->ctrl, c->stream);
+      for (int m = 0; m < batch; ++m) {
+        // iteration m's prep tests iteration m - 1
+        const PicardCheck chk{c->ctrl, (float)p.picard_rtol, m - 1};
+        const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
+        evaluate(c, xin, w, MODE_PICARD, false, q, c->xb[m & 1], nullptr, done, m > 0 ? &chk : nullptr, false);
+      }
+      launch_step_end(c->ctrl, PicardCheck{c->ctrl, (float)p.picard_rtol, batch - 1}, c->blockmax, c->nblk_comb,
+                      c->xb[0], c->xb[1], q, nq, c->stream);
+    }
+    Ctrl h{};
+    vds_status st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream),
+                              "copy ctrl");
+    if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+    if (st != VDS_OK) return st;
+    n.total_iters += (int)h.total_iters;
+    if (h.steps_done > 0) n.last_iters = h.last_iters;
+    n.last_resid = h.last_resid;  // of the last iteration checked
+    steps_taken += h.steps_done;
+    if (h.halted) {
+      st = finish_step(c, q, w, batch, n);
+      steps_taken += 1;
+      if (st != VDS_OK) return st;
+    } else if (h.steps_done != chunk) {
+      return set_err(c, VDS_ERR_HIP, "queued implicit steps lost count");
+    }
+  }
+  return VDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 vds_status vds_step(vds_ctx c, float *q, const float *w, int32_t nsteps, vds_diag *d) {
   vds_status st = ready(c);
   if (st != VDS_OK) return st;
   if (!q) return set_err(c, VDS_ERR_ARG, "null state");
   if (nsteps < 0) return set_err(c, VDS_ERR_ARG, "nsteps < 0");
   const vds_problem &p = c->prob;
-  const int64_t nq = (int64_t)p.P * c->ep.D;
-  int total_iters = 0, last_iters = 0;
-  float last_resid = 0.f;
-  for (int s = 0; s < nsteps; ++s) {
-    if (p.scheme == VDS_EXPLICIT) {
-      evaluate(c, q, w, MODE_EXPLICIT, false, nullptr, q, nullptr, nullptr);
-      continue;
+  StepCounts n;
+  if (p.scheme == VDS_EXPLICIT) {
+    for (int s = 0; s < nsteps; ++s) evaluate(c, q, w, MODE_EXPLICIT, false, nullptr, q, nullptr, nullptr);
+  } else if (nsteps > 0) {
+    int taken = 0;
+    st = implicit_steps(c, q, w, nsteps, n, taken);
+    if (st == VDS_ERR_NOT_CONVERGED && d != nullptr) {
+      std::memset(d, 0, sizeof(*d));
+      d->steps = taken;
+      d->iters = n.total_iters;
+      d->last_iters = n.last_iters;
+      d->resid = n.last_resid;
     }
-    launch_qstar(c->ep, q, c->qstar, c->stream);
-    launch_ctrl_reset(c->ctrl, c->stream);
-    const int *done = &c->ctrl->done;
-    int m = 0;
-    Ctrl h{};
-    bool converged = false;
-    while (m < p.picard_max) {
-      const int batch = std::min(p.picard_batch, p.picard_max - m);
-      for (int b = 0; b < batch; ++b, ++m) {
-        const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
-        float *xout = c->xb[m & 1];
-        evaluate(c, xin, w, MODE_PICARD, false, c->qstar, xout, nullptr, done);
-        launch_picard_check(c->ctrl, c->blockmax, c->nblk_comb, (float)p.picard_rtol, m, c->stream);
-      }
-      st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream), "copy ctrl");
-      if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
-      if (st != VDS_OK) return st;
-      if (h.done) {
-        converged = true;
-        break;
-      }
-    }
-    const int final_iter = converged ? h.conv_iter : m - 1;
-    st = hip_check(c,
-                   hipMemcpyAsync(q, c->xb[final_iter & 1], sizeof(float) * nq, hipMemcpyDeviceToDevice, c->stream),
-                   "copy state");
     if (st != VDS_OK) return st;
-    last_iters = final_iter + 1;
-    total_iters += last_iters;
-    last_resid = h.last_resid;
-    if (!converged) {
-      if (d) {
-        d->steps = s + 1;
-        d->iters = total_iters;
-        d->last_iters = last_iters;
-        d->resid = last_resid;
-      }
-      return set_err(c, VDS_ERR_NOT_CONVERGED, "fixed-point iteration reached picard_max");
-    }
   }
   st = hip_check(c, hipGetLastError(), "launch");
   if (st != VDS_OK) return st;
   if (d != nullptr) {
     std::memset(d, 0, sizeof(*d));
     d->steps = nsteps;
-    d->iters = total_iters;
-    d->last_iters = last_iters;
-    d->resid = last_resid;
+    d->iters = n.total_iters;
+    d->last_iters = n.last_iters;
+    d->resid = n.last_resid;
     return stress_into(c, q, w, d->tau);
   }
   return VDS_OK;
@@ -442,7 +520,7 @@ vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float
   if (!q || !y || !f || ny < 0) return set_err(c, VDS_ERR_ARG, "bad arguments");
   if (ny == 0) return VDS_OK;
   const EvalParams &e = c->ep;
-  launch_mean_partials(e, q, w, c->meanp, nullptr, c->stream);
+  launch_mean_partials(e, q, w, c->meanp, nullptr, nullptr, c->stream);
   launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr, c->stream);
   const float norm = (float)std::pow(2.0 * M_PI * c->prob.h * c->prob.h, -0.5 * e.D);
   // foreign rows go through the Q-operand buffer in blocks of Ppad rows
@@ -501,7 +579,7 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
     if (!pair_shape_ok(t, c->ep.D)) continue;
     apply_tuning(c, t);
     if (c->ep.vhalf + 2 * c->ep.qhalf != prepared) {  // operand formats follow the implementation
-      launch_mean_partials(c->ep, q, w, c->meanp, nullptr, c->stream);
+      launch_mean_partials(c->ep, q, w, c->meanp, nullptr, nullptr, c->stream);
       launch_prep(c->ep, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr,
                   c->stream);
       prepared = c->ep.vhalf + 2 * c->ep.qhalf;

@@ -9,7 +9,7 @@
 namespace vds {
 
 struct Layout {
-  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, hist, qstar, xb0, xb1, total;
+  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, hist, xb0, xb1, total;
 };
 
 struct TimerAcc {
@@ -37,7 +37,7 @@ struct vds_ctx_s {
   std::vector<hipEvent_t> event_pool;
 
   // workspace views
-  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *qstar, *xb[2], *blockmax, *wscale;
+  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *xb[2], *blockmax, *wscale;
   vds::F16Operands f16{};
   unsigned long long *hist;  // median-bandwidth histograms [2][kHistBins]
   double *meanp, *redp, *redout;
@@ -69,8 +69,10 @@ void timed(vds_ctx c, int which, double work, F &&fn) {
   c->timers[which].pending_work.push_back(work);
 }
 // Centring, operand packing and pass A at the state q (weights w or uniform):
-// leaves S, term1 and the pass-B operand in the workspace.
-void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done);
+// leaves S, term1 and the pass-B operand in the workspace.  Without `centre`
+// the centring partials already in the workspace are reused.
+void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre = true,
+                 const PicardCheck *chk = nullptr);
 // Pass B with the operand eval_pass_a left; partial sums stay in c->part.
 void eval_pass_b(vds_ctx c, const int *done);
 

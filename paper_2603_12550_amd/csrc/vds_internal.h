@@ -22,12 +22,26 @@ constexpr int kNumRed = 16;        // FP64 reduction slots: F, diss, work, tau[9
 // Reduction slot indices.
 enum { RED_F = 0, RED_DISS = 1, RED_WORK = 2, RED_TAU = 3 };
 
-// Device control block of the implicit iteration.
+// Device control block of the implicit iteration.  Every kernel of a step
+// returns at once while `done` is set, so iterations queued past convergence
+// cost a launch each and nothing more.
 struct Ctrl {
-  int done;           // set once the iteration has converged
-  int conv_iter;      // iteration index (0-based) that converged
-  float last_resid;   // max |x_new - x_old| of the last checked iteration
-  int checked;        // iterations checked so far in this step
+  int done;               // the current step converged, or the queue halted
+  int conv_iter;          // iteration (0-based) that converged in this step, -1 before
+  float last_resid;       // max |x_new - x_old| of the last checked iteration
+  int checked;            // iterations checked so far in this step
+  int halted;             // a queued step used its iterations without converging
+  int steps_done;         // queued steps written back since the last reset
+  int last_iters;         // iterations of the last step written back
+  long long total_iters;  // iterations of the steps written back since the last reset
+};
+
+// Convergence test of one fixed-point iteration, taken from the combine
+// kernel's block maxima by the next kernel in stream order.
+struct PicardCheck {
+  Ctrl *ctrl;
+  float rtol;     // converged when max|dx| <= rtol * max(1, max|x|)
+  int iter;    // index of the tested iteration within the step
 };
 
 // Kernel-side description of one evaluation.
@@ -97,22 +111,35 @@ void launch_batch_pair(int impl, int rb, int grid, int KK, int D, const int2 *it
                        const float *xc, float *partial, hipStream_t s);
 
 // ---- launchers (local_kernels.hip) ----
-void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done, hipStream_t s);
+// With `begin`, the launch also opens a queued implicit step: it does nothing
+// once the queue has halted, and otherwise clears the step's fields of *begin.
+void launch_mean_partials(const EvalParams &p, const float *q, const float *w, double *meanp, const int *done,
+                          Ctrl *begin, hipStream_t s);
 // With p.vhalf, VA is written as FP16 halves (see pair_kernels.hip) with the
 // weights divided by their maximum, which goes to *wscale; with p.qhalf the
 // FP16 distance operands and row norms too (f16 may be null otherwise).
+// With `chk`, the launch first tests iteration chk->iter (block maxima of
+// nblk_chk combine blocks) and does nothing once it has converged.
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp,
                  float *xc, float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16,
-                 const int *done, hipStream_t s);
+                 const int *done, hipStream_t s, const PicardCheck *chk = nullptr, const float *blockmax = nullptr,
+                 int nblk_chk = 0);
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
+// In MODE_PICARD, q0 is the state at the start of the step (the flow term is
+// taken there) and each block leaves its maxima of |dx| and |x| in blockmax.
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
-                    const float *t1, const float *S, const float *wv, const float *qin, const float *qstar,
+                    const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
                     float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s);
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s);
-void launch_qstar(const EvalParams &p, const float *q, float *qstar, hipStream_t s);
-void launch_picard_check(Ctrl *ctrl, const float *blockmax, int nblk, float rtol, int iter, hipStream_t s);
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
+// Closes a queued implicit step whose last queued iteration is chk.iter: tests
+// it unless an earlier test converged, then copies the converged iterate
+// (xb[conv_iter & 1]) into q and counts the step, or halts the queue.
+void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
+                     const float *xb1, float *q, int64_t n, hipStream_t s);
+// Stand-alone test of iteration chk.iter (host-driven iterations).
+void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s);
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s);
 void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,
                          float *QB, const F16Operands *f16, hipStream_t s);

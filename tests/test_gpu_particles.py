@@ -196,6 +196,64 @@ def test_implicit_steps_match_oracle_trajectory(lib, tuning):
         assert np.linalg.norm(d["tau"] - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
+def test_queued_implicit_steps_match_oracle(lib):
+    # several implicit steps in one call run queued on the device (the
+    # convergence test in the combine kernel, the write-back in a step-end
+    # kernel); the trajectory still follows the oracle step by step
+    cfg = wl.chain4_shear(P=1500, seed=21)
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    qo = wl.f32_as_f64(q32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    _say("queued implicit steps chain4 P=1500, 6 steps in one call")
+    d = ctx.step(qg, nsteps=6)
+    iters = 0
+    for _ in range(6):
+        qo, m = ovds.step_implicit(qo, w, prob, threads=8)
+        iters += m
+    assert d["steps"] == 6
+    assert _rel(qg.cpu().numpy(), qo) < 1e-5
+    # the device stops at rtol 1e-6, the oracle at 1e-13: the device never
+    # takes more iterations
+    assert 6 <= d["iters"] <= iters
+
+
+@pytest.mark.parametrize("batch", [1, 2, 3])
+def test_queued_implicit_steps_do_not_depend_on_batching(lib, batch):
+    # 70 steps (more than one queue of 64): with picard_batch below the
+    # iterations a step needs, every step halts the queue and the host
+    # finishes it; the iterates are the same kernels on the same inputs, so
+    # the trajectory and the iteration counts are identical bit for bit to
+    # those of a batch that never halts, and to one step per call
+    cfg = wl.chain4_shear(P=700, seed=22)
+    P = cfg["P"]
+    q32 = wl.to_f32(cfg["q0"])
+    kw = dict(H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit", picard_rtol=1e-6)
+    ref = _dev(q32)
+    ctx_ref = _ctx(lib, 3, P, cfg["h"], picard_batch=12, **kw)
+    d_ref = ctx_ref.step(ref, nsteps=70)
+    _say(f"queued implicit steps chain4 P=700, 70 steps, picard_batch={batch}")
+    qg = _dev(q32)
+    ctx = _ctx(lib, 3, P, cfg["h"], picard_batch=batch, **kw)
+    d = ctx.step(qg, nsteps=70)
+    assert torch_equal(qg, ref)
+    assert (d["steps"], d["iters"], d["last_iters"]) == (d_ref["steps"], d_ref["iters"], d_ref["last_iters"])
+    assert d["resid"] == d_ref["resid"]
+    q1 = _dev(q32)
+    total = 0
+    for _ in range(70):
+        total += ctx.step(q1)["last_iters"]
+    assert torch_equal(q1, ref)
+    assert total == d_ref["iters"]
+
+
+def torch_equal(a, b):
+    return bool((a == b).all().item())
+
+
 @pytest.mark.parametrize("tuning", IMPLS)
 def test_implicit_dumbbell_trajectory_and_stress(lib, tuning):
     cfg = wl.dumbbell_shear()
