@@ -81,7 +81,7 @@ typedef struct vds_problem {
   int32_t scheme;        /* VDS_EXPLICIT (q+ = q + dt v(q)) or VDS_IMPLICIT */
   int32_t picard_max;    /* implicit: iteration cap (>= 1) */
   double picard_rtol;    /* implicit: stop when max|dx| <= rtol * max(1, max|x|) */
-  int32_t picard_batch;  /* implicit: iterations queued per host convergence check (>= 1) */
+  int32_t picard_batch;  /* implicit: iterations queued per step before the host checks (>= 1) */
   int32_t reserved;
 } vds_problem;
 
@@ -146,9 +146,13 @@ vds_status vds_velocity(vds_ctx ctx, const float *q_dev, const float *w_dev, flo
 /* Advances q_dev in place by `nsteps` steps of the problem's scheme
  * (explicit Euler of Appendix A, or the implicit Euler of Appendix A with the
  * flow term at t and the kernel and spring terms at t+, solved by fixed-point
- * iteration from q).  Implicit steps synchronise once per picard_batch
- * iterations.  On VDS_ERR_NOT_CONVERGED q_dev holds the last iterate of the
- * failing step.  `diag` (host, may be NULL) gets iteration counts, the last
+ * iteration from q).  Implicit steps are queued on the device with
+ * picard_batch iterations each: the convergence test runs in the kernels, the
+ * iterations queued past convergence return at once, and the host
+ * synchronises once per 64 steps, plus once per picard_batch further
+ * iterations for a step that needs more than picard_batch.  The iterates, and
+ * so the result, do not depend on picard_batch.  On VDS_ERR_NOT_CONVERGED
+ * q_dev holds the last iterate of the failing step.  `diag` (host, may be NULL) gets iteration counts, the last
  * residual and the stress after the last step. */
 vds_status vds_step(vds_ctx ctx, float *q_dev, const float *w_dev, int32_t nsteps, vds_diag *diag);
 
