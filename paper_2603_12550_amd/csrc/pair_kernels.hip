@@ -209,7 +209,7 @@ __device__ inline half8 as_half8(uint4 u) {
 // row norm -kappa |x_I|^2 (RN) enters exactly, in FP32, through the
 // accumulator's initial value.
 template <int KK, int KQ, int RB>
-__device__ void pair_rows_f16(const float *__restrict__ QB, const uint4 *__restrict__ QH,
+__device__ __forceinline__ void pair_rows_f16(const float *__restrict__ QB, const uint4 *__restrict__ QH,
                               const float *__restrict__ RN, int nrow_blocks, const float *__restrict__ KA,
                               const uint4 *__restrict__ KH, const uint4 *__restrict__ VH, int64_t lo_off, int p0,
                               int p1, const float *__restrict__ xc, int D, int exclude_self, double out_scale,
@@ -245,88 +245,96 @@ __device__ void pair_rows_f16(const float *__restrict__ QB, const uint4 *__restr
 #pragma unroll
     for (int i = 0; i < 4; ++i) tot[r][i] = 0.0;
 
-  float ka[2][NK];
-  uint4 kh[2][NQ];
-  uint4 vh, vl;
-  auto load_cols = [&](int cp, float (&fa)[2][NK], uint4 (&ha)[2][NQ], uint4 &h, uint4 &l) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if constexpr (kQ16) {
-#pragma unroll
-        for (int m = 0; m < KQ; ++m) ha[s][m] = KH[((int64_t)(2 * cp + s) * KQ + m) * 64 + lane];
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) fa[s][kk] = KA[((int64_t)(2 * cp + s) * KK + kk) * 64 + lane];
-      }
-    }
-    h = VH[(int64_t)cp * 64 + lane];
-    l = VH[lo_off + (int64_t)cp * 64 + lane];
+  // Operands of one chunk pair (32 columns): distance operands of its two
+  // 16-column slices and the V highs and lows.  Two of them alternate so that
+  // the loads of the next chunk pair overlap this one's arithmetic without
+  // register copies; addresses are a wave-uniform base plus the lane offset.
+  struct ColOps {
+    float fa[2][NK];
+    uint4 ha[2][NQ];
+    uint4 h, l;
   };
-  if (p0 < p1) load_cols(p0, ka, kh, vh, vl);
-  for (int cp = p0; cp < p1;) {
-    const int g_end = min(p1, cp + kFlushPairs);
-    floatx4 acc[RB];
+  auto load_cols = [&](int cp, ColOps &o) {
+    if constexpr (kQ16) {
+      const uint4 *kb = KH + (int64_t)(2 * cp) * KQ * 64;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (; cp < g_end; ++cp) {
-      // prefetch the next chunk pair's operands while this one computes
-      float kan[2][NK];
-      uint4 khn[2][NQ];
-      uint4 vhn, vln;
-      load_cols((cp + 1 < p1) ? cp + 1 : cp, kan, khn, vhn, vln);
-      const half8 h8 = as_half8(vh), l8 = as_half8(vl);
-
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        float e[8];
+        for (int m = 0; m < KQ; ++m) o.ha[s][m] = kb[(s * KQ + m) * 64 + lane];
+    } else {
+      const float *kb = KA + (int64_t)(2 * cp) * KK * 64;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          floatx4 t = {rinit[r], rinit[r], rinit[r], rinit[r]};
-          if constexpr (kQ16) {
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int m = 0; m < KQ; ++m)
-              t = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(kh[s][m]), qh[r][m], t, 0, 0, 0);
-          } else {
+        for (int kk = 0; kk < KK; ++kk) o.fa[s][kk] = kb[(s * KK + kk) * 64 + lane];
+    }
+    const uint4 *vb = VH + (int64_t)cp * 64;
+    o.h = vb[lane];
+    o.l = vb[lo_off + lane];
+  };
+  floatx4 acc[RB];
+  auto compute = [&](int cp, const ColOps &o) {
+    const half8 h8 = as_half8(o.h), l8 = as_half8(o.l);
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) t = __builtin_amdgcn_mfma_f32_16x16x4f32(ka[s][kk], qv[r][kk], t, 0, 0, 0);
-          }
-          // no clamp: e exceeds 2^15 only by the rounding of t, and the RTZ
-          // conversion of the split saturates at the FP16 maximum
-#pragma unroll
-          for (int i = 0; i < 4; ++i) e[4 * s + i] = __builtin_amdgcn_exp2f(t[i]);
-        }
-        if (exclude_self && (2 * cp == rb0 + r || 2 * cp + 1 == rb0 + r)) {  // scalar branch: diagonal tile
-          // an empty volatile asm keeps this a branch: if-converted into
-          // selects it would cost four VALU instructions on every tile
-          asm volatile("" ::: "memory");
-          const int sd = 2 * cp == rb0 + r ? 0 : 4;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) e[sd + i] = diag_i == i ? 0.f : e[sd + i];
-        }
-        half8 eh, el;
-#pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-          half2v h, l;
-          split_pair(e[j], e[j + 1], one, h, l);
-          eh[j] = h.x;
-          eh[j + 1] = h.y;
-          el[j] = l.x;
-          el[j + 1] = l.y;
-        }
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, h8, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, l8, acc[r], 0, 0, 0);
-        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(el, h8, acc[r], 0, 0, 0);
-      }
+    for (int r = 0; r < RB; ++r) {
+      float e[8];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
+        floatx4 t = {rinit[r], rinit[r], rinit[r], rinit[r]};
+        if constexpr (kQ16) {
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk) ka[s][kk] = kan[s][kk];
+          for (int m = 0; m < KQ; ++m)
+            t = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(o.ha[s][m]), qh[r][m], t, 0, 0, 0);
+        } else {
 #pragma unroll
-        for (int m = 0; m < NQ; ++m) kh[s][m] = khn[s][m];
+          for (int kk = 0; kk < KK; ++kk) t = __builtin_amdgcn_mfma_f32_16x16x4f32(o.fa[s][kk], qv[r][kk], t, 0, 0, 0);
+        }
+        // no clamp: e exceeds 2^15 only by the rounding of t, and the RTZ
+        // conversion of the split saturates at the FP16 maximum
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[4 * s + i] = __builtin_amdgcn_exp2f(t[i]);
       }
-      vh = vhn;
-      vl = vln;
+      if (exclude_self && (2 * cp == rb0 + r || 2 * cp + 1 == rb0 + r)) {  // scalar branch: diagonal tile
+        // an empty volatile asm keeps this a branch: if-converted into
+        // selects it would cost four VALU instructions on every tile
+        asm volatile("" ::: "memory");
+        const int sd = 2 * cp == rb0 + r ? 0 : 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) e[sd + i] = diag_i == i ? 0.f : e[sd + i];
+      }
+      half8 eh, el;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        half2v h, l;
+        split_pair(e[j], e[j + 1], one, h, l);
+        eh[j] = h.x;
+        eh[j + 1] = h.y;
+        el[j] = l.x;
+        el[j + 1] = l.y;
+      }
+      acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, h8, acc[r], 0, 0, 0);
+      acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh, l8, acc[r], 0, 0, 0);
+      acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_f16(el, h8, acc[r], 0, 0, 0);
     }
+  };
+  ColOps b0, b1;
+  if (p0 < p1) load_cols(p0, b0);
+  // groups of kFlushPairs (even) chunk pairs, so every group but the last
+  // starts with its operands in b0; loads past the end re-read the last
+  // chunk pair
+  for (int cp = p0; cp < p1;) {
+    const int g_end = min(p1, cp + kFlushPairs);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; cp < g_end; cp += 2) {
+      load_cols(min(cp + 1, p1 - 1), b1);
+      compute(cp, b0);
+      if (cp + 1 < g_end) {
+        load_cols(min(cp + 2, p1 - 1), b0);
+        compute(cp + 1, b1);
+      }
+    }
+    cp = g_end;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -360,7 +368,7 @@ struct PairF16Ops {
 };
 
 template <int KK, int KQ, int RB>
-__global__ __launch_bounds__(256) void k_pair_mfma16(PairF16Ops ops, int nrow_blocks, int ncol_pairs,
+__global__ __launch_bounds__(256, 4) void k_pair_mfma16(PairF16Ops ops, int nrow_blocks, int ncol_pairs,
                                                      int pairs_per_split, const float *__restrict__ xc, int D,
                                                      int exclude_self, const float *__restrict__ wscale, float one,
                                                      float *__restrict__ partial, int64_t part_stride_rows,
