@@ -43,6 +43,15 @@ vds_status vds_mlp_get_grads(vds_mlp m, float *grads_dev);
  * (refreshed from the FP32 parameters whenever they change). n <= max_batch. */
 vds_status vds_mlp_forward(vds_mlp m, const float *X_dev, int32_t n, float *Y_dev, int32_t bf16);
 
+/* nsteps learned reduced steps in place (the step of the learned reduced model
+ * that replaces the POD-Galerkin step of Section 3): p_dev[nout] +=
+ * network((p_dev, log_rate)) through the scaling, nsteps times, in the BF16
+ * inference arithmetic of vds_mlp_forward (inputs and hidden activations
+ * rounded to BF16, FP32 sums).  Needs nin = nout + 1.  Runs as one launch of
+ * one workgroup that keeps the state and activations in LDS while
+ * nin + 2 width + 2 nout <= 16384 floats, else layer by layer.  Asynchronous. */
+vds_status vds_mlp_predict_steps(vds_mlp m, float *p_dev, float log_rate, int32_t nsteps);
+
 /* FP32 forward and backward pass of the mean squared error against T_dev[n][nout];
  * keeps the gradient; loss_host (may be NULL) gets the loss (FP64 sum).  Synchronises
  * when loss_host is given. */

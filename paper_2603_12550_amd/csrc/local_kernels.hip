@@ -465,14 +465,24 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
   combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qs, out, out2, redp, blockmax);
 }
 
-__global__ void k_reduce_final(const double *__restrict__ redp, int nblk, int nslots, double *__restrict__ out,
-                               const int *__restrict__ done) {
+// Sum over blocks of the FP64 block partials, slot by slot: wave s takes slot s,
+// lane l folds blocks l, l + 64, ... in order, then a fixed butterfly over the
+// wave (deterministic; the latency is that of nblk / 64 loads, not nblk).
+__global__ __launch_bounds__(1024) void k_reduce_final(const double *__restrict__ redp, int nblk, int nslots,
+                                                       double *__restrict__ out, const int *__restrict__ done) {
   if (done != nullptr && *done) return;
-  const int s = threadIdx.x;
+  const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (s >= nslots) return;
-  double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += redp[(int64_t)b * 16 + s];
-  out[s] = acc;
+  double a0 = 0.0, a1 = 0.0;
+  int b = lane;
+  for (; b + 64 < nblk; b += 128) {
+    a0 += redp[(int64_t)b * 16 + s];
+    a1 += redp[(int64_t)(b + 64) * 16 + s];
+  }
+  if (b < nblk) a0 += redp[(int64_t)b * 16 + s];
+  double acc = a0 + a1;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) out[s] = acc;
 }
 
 // Stand-alone convergence test (host-driven iterations).
@@ -715,7 +725,7 @@ void launch_combine(const EvalParams &p, int mode, bool obs, const float *partia
                                                     out, out2, redp, blockmax, done);
 }
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s) {
-  k_reduce_final<<<1, 64, 0, s>>>(redp, nblk, nslots, out, done);
+  k_reduce_final<<<1, 1024, 0, s>>>(redp, nblk, nslots, out, done);
 }
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s) { k_ctrl_reset<<<1, 64, 0, s>>>(ctrl); }
 void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,

@@ -23,8 +23,25 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 thread_local std::string g_mlp_create_error;
 
 struct MlpLayout {
-  size_t params, grads, adam_m, adam_v, wbf, Z1, A1, Z2, A2, Y, dY, dA, dZ, xs, xsc, ys, ysc, xin, tin, part, lossp, total;
+  size_t params, grads, adam_m, adam_v, wbf, wpk, Z1, A1, Z2, A2, Y, dY, dA, dZ, xs, xsc, ys, ysc, xin, tin, part, lossp,
+      total;
 };
+
+// Resident learned steps (k_learned_steps_reg): one workgroup of 1024 threads
+// keeps the BF16 weights on chip for a whole window of steps, layers 1 and 2
+// in registers and layer 3 in LDS (gfx950 gives a workgroup 160 KiB).  Layer l
+// splits a row over G_l consecutive lanes, each taking CK_l consecutive
+// inputs; layer 3 has up to kNout3 * G3 row chunks ("slots"), slot s for
+// thread s % 1024.  Shapes that fit: nin <= 8 * 68, width <= 128, nout <= 576.
+constexpr int kRegThreads = 1024;
+constexpr int kG1 = 8, kCK1 = 68, kG2 = 8, kCK2 = 16, kG3 = 4, kCK3 = 32, kNout3 = 576;
+constexpr int kSlots3 = kNout3 * kG3;
+constexpr int kS3 = (kSlots3 + kRegThreads - 1) / kRegThreads;
+constexpr int64_t kPk1 = (int64_t)kRegThreads * kCK1, kPk2 = (int64_t)kRegThreads * kCK2,
+                  kPk3 = (int64_t)kSlots3 * kCK3;  // BF16 elements
+bool reg_steps_fit(int nin, int w, int nout) {
+  return nin <= kG1 * kCK1 && w <= kRegThreads / kG1 && w <= kG2 * kCK2 && w <= kG3 * kCK3 && nout <= kNout3;
+}
 
 int64_t nparams(int nin, int w, int nout) {
   return (int64_t)w * nin + w + (int64_t)w * w + w + (int64_t)nout * w + nout;
@@ -45,6 +62,7 @@ MlpLayout mlp_layout(int nin, int w, int nout, int B) {
   L.adam_m = take(sizeof(float) * np);
   L.adam_v = take(sizeof(float) * np);
   L.wbf = take(sizeof(uint16_t) * np);
+  L.wpk = take(sizeof(uint16_t) * (kPk1 + kPk2 + kPk3));
   L.Z1 = take(sizeof(float) * Bp * w);
   L.A1 = take(sizeof(float) * Bp * w);
   L.Z2 = take(sizeof(float) * Bp * w);
@@ -195,6 +213,234 @@ __global__ void k_rollout_update(float *__restrict__ p, const float *__restrict_
   else p[i] += d;
 }
 
+// ---- fused learned steps: one workgroup runs whole windows of steps ----
+
+constexpr int kFusedThreads = 1024;
+constexpr int kFusedMaxLdsFloats = 16384;  // 64 KiB of LDS per workgroup
+
+__device__ inline float bf2f(short b) { return __uint_as_float((unsigned)(unsigned short)b << 16); }
+__device__ inline float bf_round(float f) { return bf2f(f2bf(f)); }
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// out[j] = act(sum_k W[j][k] x[k] + bias[j]) for j < N: W in BF16 (row-major,
+// N x K), x in LDS already rounded to BF16, FP32 sums (each lane takes
+// k = lane, lane + 64, ..., then a butterfly over the wave); wave w of the
+// block takes rows w, w + nw, ...  With `round_out` the result is stored
+// rounded to BF16 (it is the next layer's input).
+__device__ void gemv_bf16(const short *__restrict__ W, int N, int K, const float *x, const float *__restrict__ bias,
+                          int act, bool round_out, float *out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kFusedThreads / 64;
+  for (int j0 = wave; j0 < N; j0 += 2 * nw) {
+    const int j1 = j0 + nw;
+    const short *r0 = W + (int64_t)j0 * K;
+    const short *r1 = W + (int64_t)(j1 < N ? j1 : j0) * K;
+    float s0 = 0.f, s1 = 0.f;
+    for (int k = lane; k < K; k += 64) {
+      const float xk = x[k];
+      s0 = fmaf(bf2f(r0[k]), xk, s0);
+      s1 = fmaf(bf2f(r1[k]), xk, s1);
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) {
+      float z = s0 + bias[j0];
+      z = act ? silu(z) : z;
+      out[j0] = round_out ? bf_round(z) : z;
+      if (j1 < N) {
+        z = s1 + bias[j1];
+        z = act ? silu(z) : z;
+        out[j1] = round_out ? bf_round(z) : z;
+      }
+    }
+  }
+}
+
+// nsteps learned steps p += y * ysc + ys with y = network(((p, log_rate) - xs)
+// / xsc), the same arithmetic as the BF16 inference path (inputs and hidden
+// activations rounded to BF16, BF16 weights, FP32 sums and biases).  With dp
+// non-null one increment is written there and p is left unchanged.  One
+// workgroup of kFusedThreads; LDS holds x, both hidden layers and p.
+__global__ __launch_bounds__(kFusedThreads) void k_rollout_fused(float *__restrict__ p, float *__restrict__ dp,
+                                                                int np_, int w, float log_rate, int nsteps,
+                                                                const short *__restrict__ W1,
+                                                                const float *__restrict__ b1,
+                                                                const short *__restrict__ W2,
+                                                                const float *__restrict__ b2,
+                                                                const short *__restrict__ W3,
+                                                                const float *__restrict__ b3,
+                                                                const float *__restrict__ xs,
+                                                                const float *__restrict__ xsc,
+                                                                const float *__restrict__ ys,
+                                                                const float *__restrict__ ysc) {
+  extern __shared__ float lds[];
+  const int nin = np_ + 1;
+  float *x = lds, *h1 = x + nin, *h2 = h1 + w, *ps = h2 + w, *y = ps + np_;
+  for (int i = threadIdx.x; i < np_; i += kFusedThreads) ps[i] = p[i];
+  __syncthreads();
+  for (int step = 0; step < nsteps; ++step) {
+    for (int i = threadIdx.x; i < nin; i += kFusedThreads) x[i] = bf_round(((i < np_ ? ps[i] : log_rate) - xs[i]) / xsc[i]);
+    __syncthreads();
+    gemv_bf16(W1, w, nin, x, b1, 1, true, h1);
+    __syncthreads();
+    gemv_bf16(W2, w, w, h1, b2, 1, true, h2);
+    __syncthreads();
+    gemv_bf16(W3, np_, w, h2, b3, 0, false, y);
+    __syncthreads();
+    for (int i = threadIdx.x; i < np_; i += kFusedThreads) {
+      const float d = y[i] * ysc[i] + ys[i];
+      if (dp != nullptr) dp[i] = d;
+      else ps[i] += d;
+    }
+    __syncthreads();
+  }
+  if (dp == nullptr)
+    for (int i = threadIdx.x; i < np_; i += kFusedThreads) p[i] = ps[i];
+}
+
+// Packing of the BF16 weights for k_learned_steps_reg.  Layers 1 and 2:
+// thread t's chunk is contiguous, element kk = W_l[row][chunk * CK_l + kk]
+// with (row, chunk) = (t / G_l, t % G_l).  Layer 3, as it sits in LDS: eight
+// BF16 of slot s, group j (elements 8 j .. 8 j + 7 of its chunk) at uint4
+// j * kSlots3 + s, so that neighbouring lanes read neighbouring 16 bytes.
+// Zero outside the matrices.  One thread per packed element.
+__global__ void k_pack_infer(const float *__restrict__ W1, const float *__restrict__ W2, const float *__restrict__ W3,
+                             int nin, int w, int nout, short *__restrict__ pk) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= kPk1 + kPk2 + kPk3) return;
+  const float *W;
+  int G, CK, N, K;
+  int64_t slot, kk;
+  if (e < kPk1) {
+    W = W1, G = kG1, CK = kCK1, N = w, K = nin, slot = e / kCK1, kk = e % kCK1;
+  } else if (e < kPk1 + kPk2) {
+    W = W2, G = kG2, CK = kCK2, N = w, K = w, slot = (e - kPk1) / kCK2, kk = (e - kPk1) % kCK2;
+  } else {
+    const int64_t f = e - kPk1 - kPk2, j = f / (8 * kSlots3);
+    W = W3, G = kG3, CK = kCK3, N = nout, K = w, slot = (f / 8) % kSlots3, kk = 8 * j + f % 8;
+  }
+  const int64_t row = slot / G, k = (slot % G) * CK + kk;
+  pk[e] = (row < N && k < K) ? f2bf(W[row * K + k]) : (short)0;
+}
+
+// Dot product of CK packed BF16 weights (registers) with CK floats of LDS.
+template <int CK>
+__device__ inline float dot_bf16(const uint2 (&wr)[CK / 4], const float *x) {
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < CK / 4; ++j) {
+    const float4 xv = *reinterpret_cast<const float4 *>(x + 4 * j);
+    s = fmaf(__uint_as_float(wr[j].x << 16), xv.x, s);
+    s = fmaf(__uint_as_float(wr[j].x & 0xffff0000u), xv.y, s);
+    s = fmaf(__uint_as_float(wr[j].y << 16), xv.z, s);
+    s = fmaf(__uint_as_float(wr[j].y & 0xffff0000u), xv.w, s);
+  }
+  return s;
+}
+
+template <int G>
+__device__ inline float group_sum(float v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// nsteps learned steps with the weights on chip (layout of k_pack_infer), the
+// arithmetic of the BF16 inference path: inputs and hidden activations
+// rounded to BF16, FP32 products and sums (each lane sums its chunk in order,
+// then a fixed butterfly over the row's lanes), FP32 biases.  With dp non-null
+// one increment goes to dp and p is unchanged.
+__global__ __launch_bounds__(kRegThreads) void k_learned_steps_reg(float *__restrict__ p, float *__restrict__ dp,
+                                                                  int np_, int w, float log_rate, int nsteps,
+                                                                  const short *__restrict__ pk,
+                                                                  const float *__restrict__ b1,
+                                                                  const float *__restrict__ b2,
+                                                                  const float *__restrict__ b3,
+                                                                  const float *__restrict__ xs,
+                                                                  const float *__restrict__ xsc,
+                                                                  const float *__restrict__ ys,
+                                                                  const float *__restrict__ ysc) {
+  __shared__ uint4 w3[kCK3 / 8 * kSlots3];
+  __shared__ __align__(16) float x[kG1 * kCK1];
+  __shared__ __align__(16) float h1[kG2 * kCK2];
+  __shared__ __align__(16) float h2[kG3 * kCK3];
+  __shared__ float ps[kNout3];
+  __shared__ float y[kNout3];
+  const int t = threadIdx.x, nin = np_ + 1;
+  uint2 w1[kCK1 / 4], w2[kCK2 / 4];
+  {
+    const uint2 *q1 = reinterpret_cast<const uint2 *>(pk) + (int64_t)t * (kCK1 / 4);
+    const uint2 *q2 = reinterpret_cast<const uint2 *>(pk + kPk1) + (int64_t)t * (kCK2 / 4);
+#pragma unroll
+    for (int j = 0; j < kCK1 / 4; ++j) w1[j] = q1[j];
+#pragma unroll
+    for (int j = 0; j < kCK2 / 4; ++j) w2[j] = q2[j];
+    const uint4 *q3 = reinterpret_cast<const uint4 *>(pk + kPk1 + kPk2);
+    for (int i = t; i < kCK3 / 8 * kSlots3; i += kRegThreads) w3[i] = q3[i];
+  }
+  const int r1 = t / kG1, c1 = t % kG1, c3 = t % kG3;
+  for (int i = t; i < np_; i += kRegThreads) ps[i] = p[i];
+  // padding of the layer inputs stays zero
+  for (int i = t; i < kG1 * kCK1; i += kRegThreads) x[i] = 0.f;
+  for (int i = t; i < kG2 * kCK2; i += kRegThreads) h1[i] = 0.f;
+  for (int i = t; i < kG3 * kCK3; i += kRegThreads) h2[i] = 0.f;
+  __syncthreads();
+  for (int step = 0; step < nsteps; ++step) {
+    // the packed weights stay packed: without this the BF16-to-FP32 unpacking
+    // is hoisted out of the step loop and needs twice the registers
+#pragma unroll
+    for (int j = 0; j < kCK1 / 4; ++j) asm volatile("" : "+v"(w1[j].x), "+v"(w1[j].y));
+#pragma unroll
+    for (int j = 0; j < kCK2 / 4; ++j) asm volatile("" : "+v"(w2[j].x), "+v"(w2[j].y));
+    for (int i = t; i < nin; i += kRegThreads) x[i] = bf_round(((i < np_ ? ps[i] : log_rate) - xs[i]) / xsc[i]);
+    __syncthreads();
+    float a = group_sum<kG1>(dot_bf16<kCK1>(w1, x + c1 * kCK1));
+    if (c1 == 0 && r1 < w) h1[r1] = bf_round(silu(a + b1[r1]));
+    __syncthreads();
+    a = group_sum<kG2>(dot_bf16<kCK2>(w2, h1 + c1 * kCK2));
+    if (c1 == 0 && r1 < w) h2[r1] = bf_round(silu(a + b2[r1]));
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kS3; ++i) {
+      const int slot = t + kRegThreads * i;  // uniform over each group of kG3 lanes
+      if (slot < kSlots3) {
+        const float *hx = h2 + c3 * kCK3;
+        float s3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < kCK3 / 8; ++j) {
+          const uint4 wv = w3[j * kSlots3 + slot];
+          const float4 xa = *reinterpret_cast<const float4 *>(hx + 8 * j);
+          const float4 xb = *reinterpret_cast<const float4 *>(hx + 8 * j + 4);
+          s3 = fmaf(__uint_as_float(wv.x << 16), xa.x, s3);
+          s3 = fmaf(__uint_as_float(wv.x & 0xffff0000u), xa.y, s3);
+          s3 = fmaf(__uint_as_float(wv.y << 16), xa.z, s3);
+          s3 = fmaf(__uint_as_float(wv.y & 0xffff0000u), xa.w, s3);
+          s3 = fmaf(__uint_as_float(wv.z << 16), xb.x, s3);
+          s3 = fmaf(__uint_as_float(wv.z & 0xffff0000u), xb.y, s3);
+          s3 = fmaf(__uint_as_float(wv.w << 16), xb.z, s3);
+          s3 = fmaf(__uint_as_float(wv.w & 0xffff0000u), xb.w, s3);
+        }
+        a = group_sum<kG3>(s3);
+        const int row = slot / kG3;
+        if (c3 == 0 && row < np_) y[row] = a + b3[row];
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < np_; i += kRegThreads) {
+      const float d = y[i] * ysc[i] + ys[i];
+      if (dp != nullptr) dp[i] = d;
+      else ps[i] += d;
+    }
+    __syncthreads();
+  }
+  if (dp == nullptr)
+    for (int i = t; i < np_; i += kRegThreads) p[i] = ps[i];
+}
+
 // Minibatch rows i < nb: xin[i] = (X[order[i0 + i]] - xs) / xsc, tin likewise.
 __global__ void k_gather_scaled(const float *__restrict__ X, const float *__restrict__ T,
                                 const int *__restrict__ order, int i0, int nb, int nin, int nout,
@@ -253,7 +499,7 @@ struct vds_mlp_s {
   MlpLayout L{};
   char *ws = nullptr;
   float *params, *grads, *am, *av, *Z1, *A1, *Z2, *A2, *Y, *dY, *dA, *dZ, *xs, *xsc, *ys, *ysc, *xin, *tin, *part;
-  short *wbf;
+  short *wbf, *wpk;
   double *lossp;
   double *loss_out;  // one slot after the per-block partials
   int t = 0;
@@ -358,8 +604,18 @@ void backward_fp32(vds_mlp m, const float *X, const float *T, int n) {
 void refresh_bf16(vds_mlp m) {
   if (!m->bf_stale) return;
   k_to_bf16<<<nb256(m->np), 256, 0, m->s>>>(m->params, m->wbf, m->np);
+  if (reg_steps_fit(m->nin, m->w, m->nout))
+    k_pack_infer<<<nb256(kPk1 + kPk2 + kPk3), 256, 0, m->s>>>(m->W1(), m->W2(), m->W3(), m->nin, m->w, m->nout,
+                                                              m->wpk);
   m->bf_stale = false;
 }
+
+// LDS floats of the fused step kernel: x, two hidden layers, p and the output.
+int64_t fused_lds_floats(vds_mlp m) { return (int64_t)m->nin + 2 * m->w + 2 * (int64_t)m->nout; }
+
+// nsteps learned steps on p (or one increment into dp): the fused kernel when
+// its LDS fits, else the layer-by-layer BF16 kernels step by step.
+void learned_steps(vds_mlp m, float *p, float *dp, float log_rate, int nsteps);
 
 void forward_bf16(vds_mlp m, const float *X, int n, float *Y) {
   refresh_bf16(m);
@@ -369,6 +625,30 @@ void forward_bf16(vds_mlp m, const float *X, int n, float *Y) {
   k_dense_bf16<<<g1, 64, 0, m->s>>>(X, n, m->nin, W1, m->b1(), w, 1, m->A1);
   k_dense_bf16<<<g1, 64, 0, m->s>>>(m->A1, n, w, W2, m->b2(), w, 1, m->A2);
   k_dense_bf16<<<g3, 64, 0, m->s>>>(m->A2, n, w, W3, m->b3(), m->nout, 0, Y);
+}
+
+void learned_steps(vds_mlp m, float *p, float *dp, float log_rate, int nsteps) {
+  const int np_ = m->nout;
+  refresh_bf16(m);
+  if (reg_steps_fit(m->nin, m->w, m->nout)) {
+    k_learned_steps_reg<<<1, kRegThreads, 0, m->s>>>(p, dp, np_, m->w, log_rate, dp != nullptr ? 1 : nsteps, m->wpk,
+                                                     m->b1(), m->b2(), m->b3(), m->xs, m->xsc, m->ys, m->ysc);
+    return;
+  }
+  if (fused_lds_floats(m) <= kFusedMaxLdsFloats) {
+    const int w = m->w;
+    const short *W1 = m->wbf, *W2 = W1 + (int64_t)w * m->nin + w, *W3 = W2 + (int64_t)w * w + w;
+    const size_t lds = sizeof(float) * (size_t)fused_lds_floats(m);
+    k_rollout_fused<<<1, kFusedThreads, lds, m->s>>>(p, dp, np_, w, log_rate, dp != nullptr ? 1 : nsteps, W1, m->b1(),
+                                                     W2, m->b2(), W3, m->b3(), m->xs, m->xsc, m->ys, m->ysc);
+    return;
+  }
+  float *xb = m->xin, *yb = m->Y;
+  for (int i = 0; i < (dp != nullptr ? 1 : nsteps); ++i) {
+    k_rollout_input<<<nb256(np_ + 1), 256, 0, m->s>>>(p, np_, log_rate, m->xs, m->xsc, xb);
+    forward_bf16(m, xb, 1, yb);
+    k_rollout_update<<<nb256(np_), 256, 0, m->s>>>(dp != nullptr ? nullptr : p, yb, np_, m->ys, m->ysc, dp);
+  }
 }
 
 }  // namespace
@@ -418,6 +698,7 @@ vds_status vds_mlp_bind_workspace(vds_mlp m, void *ws, size_t bytes) {
   m->am = f(L.adam_m);
   m->av = f(L.adam_v);
   m->wbf = reinterpret_cast<short *>(m->ws + L.wbf);
+  m->wpk = reinterpret_cast<short *>(m->ws + L.wpk);
   m->Z1 = f(L.Z1);
   m->A1 = f(L.A1);
   m->Z2 = f(L.Z2);
@@ -484,6 +765,15 @@ vds_status vds_mlp_forward(vds_mlp m, const float *X, int32_t n, float *Y, int32
     if (st != VDS_OK) return st;
   }
   return mhip(m, hipGetLastError(), "forward");
+}
+
+vds_status vds_mlp_predict_steps(vds_mlp m, float *p, float log_rate, int32_t nsteps) {
+  if (!m || !p) return VDS_ERR_ARG;
+  if (!m->ws) return merr(m, VDS_ERR_STATE, "no workspace bound");
+  if (m->nin != m->nout + 1) return merr(m, VDS_ERR_ARG, "learned steps need nin = nout + 1");
+  if (nsteps < 0) return merr(m, VDS_ERR_ARG, "nsteps < 0");
+  if (nsteps > 0) learned_steps(m, p, nullptr, log_rate, nsteps);
+  return mhip(m, hipGetLastError(), "learned steps");
 }
 
 vds_status vds_mlp_loss_grad(vds_mlp m, const float *X, const float *T, int32_t n, double *loss) {
@@ -592,22 +882,10 @@ vds_status vds_mlp_rollout_run(vds_mlp m, vds_ctx ctx, const float *U, int32_t R
   float *p_acc = reinterpret_cast<float *>(w + 2 * qb);
   float *dp_vds = reinterpret_cast<float *>(w + 2 * qb + pb);
   float *dp_net = reinterpret_cast<float *>(w + 2 * qb + 2 * pb);
-  float *yb = reinterpret_cast<float *>(w + 2 * qb + 3 * pb);
   const size_t mapw = vds_pod_map_workspace_bytes(&pr, R);
   void *mws = w + 2 * qb + 4 * pb;
-  float *xb = reinterpret_cast<float *>(w + 2 * qb + 4 * pb + up(mapw));
 
   vds_mlp_rollout S{};
-  auto net_increment = [&](const float *pin, float *dp) {
-    k_rollout_input<<<nb256(np_ + 1), 256, 0, m->s>>>(pin, np_, log_rate, m->xs, m->xsc, xb);
-    forward_bf16(m, xb, 1, yb);
-    k_rollout_update<<<nb256(np_), 256, 0, m->s>>>(nullptr, yb, np_, m->ys, m->ysc, dp);
-  };
-  auto net_step = [&]() {
-    k_rollout_input<<<nb256(np_ + 1), 256, 0, m->s>>>(p, np_, log_rate, m->xs, m->xsc, xb);
-    forward_bf16(m, xb, 1, yb);
-    k_rollout_update<<<nb256(np_), 256, 0, m->s>>>(p, yb, np_, m->ys, m->ysc, nullptr);
-  };
   // energy at the reconstructed state, and the plain scheme's velocity there
   auto observe = [&](const float *pin, vds_diag *d) -> vds_status {
     vds_status st = vds_pod_reconstruct(ctx, U, R, pin, qt, mws, mapw);
@@ -623,11 +901,11 @@ vds_status vds_mlp_rollout_run(vds_mlp m, vds_ctx ctx, const float *U, int32_t R
     const int n = std::min(K, nsteps - s0);
     st = mhip(m, hipMemcpyAsync(p_acc, p, 4 * np_, hipMemcpyDeviceToDevice, m->s), "copy");
     if (st != VDS_OK) return st;
-    for (int i = 0; i < n; ++i) net_step();
+    learned_steps(m, p, nullptr, log_rate, n);
     st = observe(p, &d1);
     if (st != VDS_OK) return st;
     // full-step residual at the window's end state
-    net_increment(p, dp_net);
+    learned_steps(m, p, dp_net, log_rate, 1);
     st = vds_pod_project(ctx, U, R, v, dp_vds, mws, mapw);
     if (st != VDS_OK) return st;
     st = mhip(m, hipMemcpyAsync(a.data(), dp_net, 4 * np_, hipMemcpyDeviceToHost, m->s), "copy");

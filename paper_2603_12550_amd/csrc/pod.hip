@@ -20,6 +20,98 @@ using namespace vds;
 
 namespace {
 
+// q_k = U p_k for the nb bonds k: thread i sums over r in order, reading U
+// column by column (coalesced over i; eight columns in flight), so U is read
+// once.
+__global__ __launch_bounds__(64) void k_pod_reconstruct(const float *__restrict__ U, int64_t m, int R, int nb,
+                                                        const float *__restrict__ p, float *__restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= m) return;
+  float acc[kMaxNb];
+#pragma unroll
+  for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
+  const float *u = U + i;
+  int r = 0;
+  for (; r + 8 <= R; r += 8) {
+    float uv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) uv[j] = u[(int64_t)(r + j) * m];
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k)
+      if (k < nb) {
+        const float *pk = p + (int64_t)k * R + r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[k] = fmaf(uv[j], pk[j], acc[k]);
+      }
+  }
+  for (; r < R; ++r) {
+    const float u0 = u[(int64_t)r * m];
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k)
+      if (k < nb) acc[k] = fmaf(u0, p[(int64_t)k * R + r], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxNb; ++k)
+    if (k < nb) q[(int64_t)k * m + i] = acc[k];
+}
+
+constexpr int kProjThreads = 256;
+constexpr int kProjChunks = 16;
+
+// First stage of p_k[r] = U_r . q_k: block (r, c) takes chunk c of the rows,
+// threads stride over it (four rows in flight), then a fixed-order block
+// reduction per bond into part[c][k][r].
+__global__ __launch_bounds__(kProjThreads) void k_pod_project(const float *__restrict__ U, int64_t m, int R, int nb,
+                                                              const float *__restrict__ q, float *__restrict__ part) {
+  __shared__ float red[kMaxNb][kProjThreads / 64];
+  const int r = blockIdx.x, c = blockIdx.y;
+  const int64_t len = (m + kProjChunks - 1) / kProjChunks, i0 = c * len, i1 = min(m, i0 + len);
+  const float *u = U + (int64_t)r * m;
+  float acc[kMaxNb];
+#pragma unroll
+  for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
+  int64_t i = i0 + threadIdx.x;
+  for (; i + 3 * kProjThreads < i1; i += 4 * kProjThreads) {
+    float uv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) uv[j] = u[i + j * kProjThreads];
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k)
+      if (k < nb) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[k] = fmaf(uv[j], q[(int64_t)k * m + i + j * kProjThreads], acc[k]);
+      }
+  }
+  for (; i < i1; i += kProjThreads) {
+    const float ui = u[i];
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k)
+      if (k < nb) acc[k] = fmaf(ui, q[(int64_t)k * m + i], acc[k]);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kMaxNb; ++k) {
+    float v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[k][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    float v = 0.f;
+    for (int w = 0; w < kProjThreads / 64; ++w) v += red[threadIdx.x][w];
+    part[((int64_t)c * nb + threadIdx.x) * R + r] = v;
+  }
+}
+
+// Second stage: p[k][r] = sum over the chunks in order.
+__global__ void k_pod_project_sum(const float *__restrict__ part, int R, int nb, float *__restrict__ p) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nb * R) return;
+  float v = 0.f;
+  for (int c = 0; c < kProjChunks; ++c) v += part[(int64_t)c * nb * R + e];
+  p[e] = v;
+}
+
 struct PodLayout {
   size_t gram, gram64, eig, offd, info, Wt, U2, GU, GU64, Linv, work64, part, total;
 };
@@ -211,7 +303,8 @@ size_t vds_pod_map_workspace_bytes(const vds_problem *prob, int32_t R) {
   const int64_t m = 3 * prob->P;
   const size_t a = sizeof(float) * (size_t)gemm_splits(prob->nb, R, m, 2048) * prob->nb * R;
   const size_t b = sizeof(float) * (size_t)m * prob->nb;
-  return (std::max(a, b) + 255) / 256 * 256;
+  const size_t c = sizeof(float) * (size_t)kProjChunks * prob->nb * R;
+  return (std::max(std::max(a, b), c) + 255) / 256 * 256;
 }
 
 vds_status vds_pod_project(vds_ctx c, const float *U, int32_t R, const float *q, float *p, void *ws, size_t bytes) {
@@ -219,18 +312,12 @@ vds_status vds_pod_project(vds_ctx c, const float *U, int32_t R, const float *q,
   if (!U || !q || !p || !ws || R < 1) return set_err(c, VDS_ERR_ARG, "bad arguments");
   if (bytes < vds_pod_map_workspace_bytes(&c->prob, R)) return set_err(c, VDS_ERR_NOMEM, "workspace too small");
   const int64_t m = 3 * c->prob.P;
-  GemmShape g;
-  g.M = c->prob.nb;
-  g.N = R;
-  g.K = m;
-  g.A = q;
-  g.lda = m;
-  g.B = U;
-  g.ldb = m;
-  g.C = p;
-  g.ldc = R;
-  g.splits = gemm_splits(g.M, R, m, 2048);
-  timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] { launch_gemm(g, static_cast<float *>(ws), c->stream); });
+  const int nb = c->prob.nb;
+  float *part = static_cast<float *>(ws);
+  timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] {
+    k_pod_project<<<dim3((unsigned)R, kProjChunks), kProjThreads, 0, c->stream>>>(U, m, R, nb, q, part);
+    k_pod_project_sum<<<(nb * R + 255) / 256, 256, 0, c->stream>>>(part, R, nb, p);
+  });
   return hip_check(c, hipGetLastError(), "project");
 }
 
@@ -240,20 +327,10 @@ vds_status vds_pod_reconstruct(vds_ctx c, const float *U, int32_t R, const float
   if (!U || !q || !p || !ws || R < 1) return set_err(c, VDS_ERR_ARG, "bad arguments");
   if (bytes < vds_pod_map_workspace_bytes(&c->prob, R)) return set_err(c, VDS_ERR_NOMEM, "workspace too small");
   const int64_t m = 3 * c->prob.P;
-  GemmShape g;
-  g.M = (int)m;
-  g.N = c->prob.nb;
-  g.K = R;
-  g.A = U;
-  g.lda = m;
-  g.a_mn = true;
-  g.B = p;
-  g.ldb = R;
-  g.C = q;
-  g.ldc = m;
-  g.c_colmajor = true;
-  g.splits = 1;
-  timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] { launch_gemm(g, static_cast<float *>(ws), c->stream); });
+  const int nb = c->prob.nb;
+  timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] {
+    k_pod_reconstruct<<<(unsigned)((m + 63) / 64), 64, 0, c->stream>>>(U, m, R, nb, p, q);
+  });
   return hip_check(c, hipGetLastError(), "reconstruct");
 }
 

@@ -94,6 +94,38 @@ def test_bf16_inference_tracks_fp32(lib):
     assert _rel(y1, y16[:1]) < 1e-6
 
 
+@pytest.mark.parametrize("shape", [(541, 128, 540), (601, 64, 600), (4001, 32, 4000)])
+def test_fused_learned_steps_match_layer_by_layer(lib, shape):
+    # vds_mlp_predict_steps against the BF16 layer kernels (vds_mlp_forward)
+    # with the scaling and update done in torch: same roundings, FP32 sums in
+    # another order.  The shapes take the three paths: weights resident on
+    # chip (nin <= 544, width <= 128, nout <= 576), one workgroup streaming
+    # the weights from L2, and layer by layer.
+    import torch
+    nin, w, nout = shape
+    sizes, layers, _, _ = _case(nin=nin, w=w, nout=nout, n=1, seed=6)
+    layers = [(W * 0.5, b) for W, b in layers]
+    m = lib.Mlp(nin, w, nout, 16)
+    m.set_params(_dev(_flat(layers)))
+    rng = np.random.default_rng(7)
+    xs, xsc = _dev(rng.standard_normal(nin) * 0.1), _dev(0.5 + rng.random(nin))
+    ys, ysc = _dev(rng.standard_normal(nout) * 1e-3), _dev(1e-3 * (0.5 + rng.random(nout)))
+    m.set_scaling(xs, xsc, ys, ysc)
+    p0 = _dev(rng.standard_normal(nout))
+    log_rate = -0.3
+    ref = p0.clone()
+    for _ in range(5):
+        x = (torch.cat([ref, torch.tensor([log_rate], dtype=torch.float32, device=ref.device)]) - xs) / xsc
+        y = m.forward(x[None].contiguous(), bf16=True)[0]
+        ref = ref + (y * ysc + ys)
+    got = m.predict_steps(p0.clone(), log_rate, 5)
+    inc_ref = (ref - p0).cpu().numpy().astype(np.float64)
+    inc = (got - p0).cpu().numpy().astype(np.float64)
+    assert _rel(inc, inc_ref) < 1e-3
+    one = m.predict_steps(p0.clone(), log_rate, 0)
+    assert bool((one == p0).all().item())
+
+
 def test_adam_steps_match_oracle(lib):
     sizes, layers, X, T = _case(seed=5)
     m = lib.Mlp(sizes[0], sizes[1], sizes[3], 64)
