@@ -112,6 +112,16 @@ __global__ void k_pod_project_sum(const float *__restrict__ part, int R, int nb,
   p[e] = v;
 }
 
+}  // namespace
+
+namespace vds {
+void launch_pod_reconstruct(const float *U, int64_t m, int R, int nb, const float *p, float *q, hipStream_t s) {
+  k_pod_reconstruct<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(U, m, R, nb, p, q);
+}
+}  // namespace vds
+
+namespace {
+
 struct PodLayout {
   size_t gram, gram64, eig, offd, info, Wt, U2, GU, GU64, Linv, work64, part, total;
 };
@@ -328,9 +338,7 @@ vds_status vds_pod_reconstruct(vds_ctx c, const float *U, int32_t R, const float
   if (bytes < vds_pod_map_workspace_bytes(&c->prob, R)) return set_err(c, VDS_ERR_NOMEM, "workspace too small");
   const int64_t m = 3 * c->prob.P;
   const int nb = c->prob.nb;
-  timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] {
-    k_pod_reconstruct<<<(unsigned)((m + 63) / 64), 64, 0, c->stream>>>(U, m, R, nb, p, q);
-  });
+  timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] { launch_pod_reconstruct(U, m, R, nb, p, q, c->stream); });
   return hip_check(c, hipGetLastError(), "reconstruct");
 }
 

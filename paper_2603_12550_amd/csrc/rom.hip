@@ -338,6 +338,140 @@ __global__ __launch_bounds__(256) void k_kernel_gemm16(const float *__restrict__
   }
 }
 
+// The same product with FP16-split distances (the pair kernels' QH/KH/RN
+// operands), tiled for reuse: a workgroup of kLdsWaves waves owns
+// kLdsWaves x 2 row blocks (256 rows) and kNBG column blocks (128 columns);
+// per chunk pair (32 columns of Z) it stages the chunk's B highs and lows and
+// its K-side distance operands in LDS once (double buffered, one barrier), and
+// every wave generates its two 16 x 32 tiles of Z and multiplies them by all
+// kNBG column blocks.  Each B element is thus read once per 256 rows instead
+// of once per 16.  FP32 accumulation over all columns of Z (no FP64 flush: 64
+// accumulators per lane already; the error stays ~1e-6 of the sums).
+constexpr int kLdsWaves = 8;
+constexpr int kLdsRB = 2;
+
+// (at most 128 VGPRs, so that two workgroups share a CU: 2.5 instead of
+// 3.0 ms per launch at P = 20000, 1080 columns)
+template <int KQ>
+__global__ __launch_bounds__(kLdsWaves * 64, 4) void k_kernel_gemm16_lds(
+    const uint4 *__restrict__ QH, const uint4 *__restrict__ KH, const float *__restrict__ RN, int nrow_blocks,
+    int ncp, const uint4 *__restrict__ BH, int64_t lo_off, int NB16, int dR, double scale0, double scale1,
+    float one, float *__restrict__ Y, int64_t ldy) {
+  __shared__ uint4 bsh[2][2 * kNBG * 64];
+  __shared__ uint4 ksh[2][2 * KQ * 64];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int rb0 = ((int)blockIdx.x * kLdsWaves + wave) * kLdsRB;
+  const int nb0 = (int)blockIdx.y * kNBG;
+  const int nbn = min(kNBG, NB16 - nb0);
+  const int diag_i = (lane & 15) - 4 * (lane >> 4);
+  half8 qh[kLdsRB][KQ];
+  float rinit[kLdsRB];
+#pragma unroll
+  for (int r = 0; r < kLdsRB; ++r) {
+    const bool ok = rb0 + r < nrow_blocks;
+#pragma unroll
+    for (int m = 0; m < KQ; ++m)
+      qh[r][m] = as_half8(ok ? QH[((int64_t)(rb0 + r) * KQ + m) * 64 + lane] : uint4{0, 0, 0, 0});
+    rinit[r] = (ok ? RN[(int64_t)(rb0 + r) * 16 + (lane & 15)] : 0.f) + kKgShift;
+  }
+  floatx4 acc[kLdsRB][kNBG];
+#pragma unroll
+  for (int r = 0; r < kLdsRB; ++r)
+#pragma unroll
+    for (int g = 0; g < kNBG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // tile loads: thread t < kNBG 64 takes B high and low element t of the
+  // chunk's kNBG x 64 uint4 (zero past the last column block) and, for
+  // t < 2 KQ 64, distance operand t
+  const int gt = t >> 6;
+  static_assert(kNBG <= kLdsWaves && 2 * 2 <= kLdsWaves, "one tile element per thread");
+  auto load_tile = [&](int cp, uint4 &bh, uint4 &bl, uint4 &kh) {
+    const int64_t bo = ((int64_t)cp * NB16 + nb0) * 64 + t;
+    bh = gt < nbn ? BH[bo] : uint4{0, 0, 0, 0};
+    bl = gt < nbn ? BH[lo_off + bo] : uint4{0, 0, 0, 0};
+    if (t < 2 * KQ * 64) kh = KH[(int64_t)(2 * cp) * KQ * 64 + t];
+  };
+  auto store_tile = [&](int buf, const uint4 &bh, const uint4 &bl, const uint4 &kh) {
+    if (gt < kNBG) {
+      bsh[buf][t] = bh;
+      bsh[buf][kNBG * 64 + t] = bl;
+    }
+    if (t < 2 * KQ * 64) ksh[buf][t] = kh;
+  };
+  uint4 nbh = uint4{0, 0, 0, 0}, nbl = uint4{0, 0, 0, 0}, nkh = uint4{0, 0, 0, 0};
+  if (ncp > 0) {
+    load_tile(0, nbh, nbl, nkh);
+    store_tile(0, nbh, nbl, nkh);
+  }
+  __syncthreads();
+  const bool active = rb0 < nrow_blocks;  // wave-uniform; every wave still stages tiles
+  for (int cp = 0; cp < ncp; ++cp) {
+    const int cur = cp & 1;
+    if (cp + 1 < ncp) load_tile(cp + 1, nbh, nbl, nkh);
+    if (active) {
+      half8 eh[kLdsRB], el[kLdsRB];
+#pragma unroll
+      for (int r = 0; r < kLdsRB; ++r) {
+        float e[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          floatx4 tt = {rinit[r], rinit[r], rinit[r], rinit[r]};
+#pragma unroll
+          for (int m = 0; m < KQ; ++m)
+            tt = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(ksh[cur][(s2 * KQ + m) * 64 + lane]), qh[r][m], tt,
+                                                        0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) e[4 * s2 + i] = __builtin_amdgcn_exp2f(tt[i]);
+          if (2 * cp + s2 == rb0 + r) {  // the self pair has Z_II = K_h(0) = 1 exactly
+#pragma unroll
+            for (int i = 0; i < 4; ++i) e[4 * s2 + i] = diag_i == i ? 32768.f : e[4 * s2 + i];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          const half2v h = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(e[j], e[j + 1]));
+          const float ra = __builtin_fmaf(-(float)h.x, one, e[j]);
+          const float rb2 = __builtin_fmaf(-(float)h.y, one, e[j + 1]);
+          eh[r][j] = h.x;
+          eh[r][j + 1] = h.y;
+          el[r][j] = (_Float16)ra;
+          el[r][j + 1] = (_Float16)rb2;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kNBG; ++g) {
+        const half8 bh = as_half8(bsh[cur][g * 64 + lane]);
+        const half8 bl = as_half8(bsh[cur][kNBG * 64 + g * 64 + lane]);
+#pragma unroll
+        for (int r = 0; r < kLdsRB; ++r) {
+          acc[r][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh[r], bh, acc[r][g], 0, 0, 0);
+          acc[r][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(eh[r], bl, acc[r][g], 0, 0, 0);
+          acc[r][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(el[r], bh, acc[r][g], 0, 0, 0);
+        }
+      }
+    }
+    if (cp + 1 < ncp) store_tile(cur ^ 1, nbh, nbl, nkh);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int r = 0; r < kLdsRB; ++r) {
+    if (rb0 + r >= nrow_blocks) break;
+#pragma unroll
+    for (int g = 0; g < kNBG; ++g) {
+      if (g >= nbn) break;
+      const int col = (nb0 + g) * 16 + (lane & 15);
+      const double sc = col < dR ? scale0 : scale1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = (int64_t)(rb0 + r) * 16 + 4 * (lane >> 4) + i;
+        Y[row * ldy + col] = (float)((double)acc[r][g][i] * sc);
+      }
+    }
+  }
+}
+
 __global__ void k_fill_scaled(const float *__restrict__ src, float a, int64_t n, float *__restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t < n) dst[t] = a * src[t];
@@ -600,19 +734,8 @@ vds_status rom_gemm(vds_rom r, GemmShape g, double flops) {
 void reconstruct_qt(vds_rom r, const float *p) {
   vds_ctx c = r->ctx;
   const int64_t m = 3 * c->prob.P;
-  GemmShape g;
-  g.M = (int)m;
-  g.N = c->prob.nb;
-  g.K = r->R;
-  g.A = r->U;
-  g.lda = m;
-  g.a_mn = true;
-  g.B = p;
-  g.ldb = r->R;
-  g.C = r->qt;
-  g.ldc = m;
-  g.c_colmajor = true;
-  timed(c, VDS_TIMER_PROJ, 4.0 * m * r->R, [&] { launch_gemm(g, r->part, c->stream); });
+  timed(c, VDS_TIMER_PROJ, 4.0 * m * r->R,
+        [&] { launch_pod_reconstruct(r->U, m, r->R, c->prob.nb, p, r->qt, c->stream); });
 }
 
 vds_status freeze(vds_rom r, const float *p) {
@@ -639,7 +762,19 @@ vds_status freeze(vds_rom r, const float *p) {
     const double unscale = 1.0 / ((double)kKgBScale * 32768.0);
     const double s0 = (double)wmax * unscale, s1 = unscale;
     const double flops = 2.0 * (double)P * P * 2 * 3 * R;
-    timed(c, VDS_TIMER_KGEMM, flops, [&] {
+    if (c->ep.qhalf) {
+      const uint4 *qh = reinterpret_cast<const uint4 *>(c->f16.QH), *kh = reinterpret_cast<const uint4 *>(c->f16.KH);
+      const int ncp = (ncc + 1) / 2;
+      dim3 g2((unsigned)((nrb + kLdsWaves * kLdsRB - 1) / (kLdsWaves * kLdsRB)), (unsigned)((L.NB16 + kNBG - 1) / kNBG));
+      timed(c, VDS_TIMER_KGEMM, flops, [&] {
+        if (c->ep.KQ == 1)
+          k_kernel_gemm16_lds<1><<<g2, kLdsWaves * 64, 0, s>>>(qh, kh, c->f16.RN, nrb, ncp, bh, lo_off, L.NB16, 3 * R,
+                                                               s0, s1, 1.f, r->Y, L.ldy);
+        else
+          k_kernel_gemm16_lds<2><<<g2, kLdsWaves * 64, 0, s>>>(qh, kh, c->f16.RN, nrb, ncp, bh, lo_off, L.NB16, 3 * R,
+                                                               s0, s1, 1.f, r->Y, L.ldy);
+      });
+    } else timed(c, VDS_TIMER_KGEMM, flops, [&] {
       switch (c->ep.KK) {
         case 2: k_kernel_gemm16<2><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;
         case 3: k_kernel_gemm16<3><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;

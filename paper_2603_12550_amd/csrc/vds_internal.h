@@ -146,6 +146,8 @@ void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const 
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm,
                         float *f, hipStream_t s);
 void launch_copy(const float *src, float *dst, int64_t n, const int *done_flag_or_null, hipStream_t s);
+// q[k][i] = sum_r U[r][i] p[k][r] for i < m, k < nb (U is m x R column-major; pod.hip).
+void launch_pod_reconstruct(const float *U, int64_t m, int R, int nb, const float *p, float *q, hipStream_t s);
 
 // ---- batched per-particle kernels (local_kernels.hip) ----
 // Block tables: blk16_ens[b] / blk256_ens[b] = ensemble of 16- / 256-particle block b.
