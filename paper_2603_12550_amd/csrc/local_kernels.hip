@@ -203,23 +203,22 @@ __device__ bool picard_converged(const PicardCheck &chk, const float *__restrict
 
 // Centre, pack Q/K operands and the pass-A V operand (weights w; over their
 // maximum, which goes to *wscale, when V is written in FP16 halves).
-__device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
-                          const double *__restrict__ meanp, int nmeanp, float *__restrict__ xc,
-                          float *__restrict__ wv, float *__restrict__ QB, float *__restrict__ KA,
-                          float *__restrict__ VA, float *__restrict__ wscale, F16Operands f16) {
-  __shared__ float mean_sh[16];
-  load_mean(p, meanp, nmeanp, mean_sh);
-  if (p.vhalf && wscale != nullptr && lb == 0 && threadIdx.x == 0) *wscale = mean_sh[15];
-  const int64_t I = group_particle(lb);
-  const int n = group_lane();
-  if (I >= p.Ppad) return;
+// Lane n of particle I's raw coordinate (0 past the particles or D).
+__device__ inline float prep_coord(const EvalParams &p, const float *__restrict__ q, int64_t I, int n) {
+  return (I < p.P && n < p.D) ? q[((int64_t)(n / 3) * p.P + I) * 3 + (n % 3)] : 0.f;
+}
+
+// Operand packing of particle I (lane n) from its centred coordinate x and
+// weight wi; mean_sh[15] is the largest weight.
+__device__ void prep_write(const EvalParams &p, int64_t I, int n, float x, float wi, const float *mean_sh,
+                           float *__restrict__ xc, float *__restrict__ wv, float *__restrict__ QB,
+                           float *__restrict__ KA, float *__restrict__ VA, F16Operands f16) {
   const bool real = I < p.P;
-  const float x = (real && n < p.D) ? q[((int64_t)(n / 3) * p.P + I) * 3 + (n % 3)] - mean_sh[n] : 0.f;
   const float nrm = gsum(x * x);
-  const float wi = real ? load_weight(w, I, p.uniform_w) : 0.f;
   if (n == 0) wv[I] = wi;
   if (n < p.D) xc[I * p.D + n] = x;
-  for (int k = n; k < 4 * p.KK; k += 16) {
+  // the FP32 distance operands are read only by the FP32-distance pair forms
+  for (int k = n; k < (p.qhalf ? 0 : 4 * p.KK); k += 16) {
     float qa = 0.f, ka = 0.f;
     if (real) {
       if (k < p.D) {
@@ -237,24 +236,43 @@ __device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restri
     KA[qk_index(I, k, p.KK)] = ka;
   }
   if (p.qhalf) {
-    _Float16 *qh = reinterpret_cast<_Float16 *>(f16.QH);
-    _Float16 *kh = reinterpret_cast<_Float16 *>(f16.KH);
+    // slots 2 m and 2 m + 1 are adjacent: one 32-bit store each for QH and KH
+    uint32_t *qh = reinterpret_cast<uint32_t *>(f16.QH);
+    uint32_t *kh = reinterpret_cast<uint32_t *>(f16.KH);
     const float y = p.cs * x;
-    for (int sl = n; sl < 32 * p.KQ; sl += 16) {  // the same trip count on every lane
-      const int k = sl / 3;
-      const float yk = gshfl(y, k < 16 ? k : 0);
-      _Float16 qv, kv;
-      dh_slot(p, sl, yk, real ? -p.kappa * nrm : 0.f, qv, kv);
-      qh[dh_index(I, sl, p.KQ)] = qv;
-      kh[dh_index(I, sl, p.KQ)] = kv;
+    const float nt = real ? -p.kappa * nrm : 0.f;
+    for (int sp = n; sp < 16 * p.KQ; sp += 16) {  // the same trip count on every lane
+      const int s0 = 2 * sp, k0 = s0 / 3, k1 = (s0 + 1) / 3;
+      const float y0 = gshfl(y, k0 < 16 ? k0 : 0), y1 = gshfl(y, k1 < 16 ? k1 : 0);
+      _Float16 q0, c0, q1, c1;
+      dh_slot(p, s0, y0, nt, q0, c0);
+      dh_slot(p, s0 + 1, y1, nt, q1, c1);
+      const int64_t di = dh_index(I, s0, p.KQ) >> 1;
+      qh[di] = (uint32_t)__builtin_bit_cast(uint16_t, q0) | ((uint32_t)__builtin_bit_cast(uint16_t, q1) << 16);
+      kh[di] = (uint32_t)__builtin_bit_cast(uint16_t, c0) | ((uint32_t)__builtin_bit_cast(uint16_t, c1) << 16);
     }
-    if (n == 0) f16.RN[I] = real ? -p.kappa * nrm : 0.f;
+    if (n == 0) f16.RN[I] = nt;
   }
   const float wn = p.vhalf ? (real ? wi / mean_sh[15] : 0.f) : wi;
   float v = 0.f;
   if (n < p.D) v = wn * x;
   else if (n == p.D) v = wn;
   store_v(p, VA, I, n, v);
+}
+
+__device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
+                          const double *__restrict__ meanp, int nmeanp, float *__restrict__ xc,
+                          float *__restrict__ wv, float *__restrict__ QB, float *__restrict__ KA,
+                          float *__restrict__ VA, float *__restrict__ wscale, F16Operands f16) {
+  __shared__ float mean_sh[16];
+  load_mean(p, meanp, nmeanp, mean_sh);
+  if (p.vhalf && wscale != nullptr && lb == 0 && threadIdx.x == 0) *wscale = mean_sh[15];
+  const int64_t I = group_particle(lb);
+  const int n = group_lane();
+  if (I >= p.Ppad) return;
+  const float x = I < p.P && n < p.D ? prep_coord(p, q, I, n) - mean_sh[n] : 0.f;
+  const float wi = I < p.P ? load_weight(w, I, p.uniform_w) : 0.f;
+  prep_write(p, I, n, x, wi, mean_sh, xc, wv, QB, KA, VA, f16);
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *__restrict__ q,
@@ -265,33 +283,82 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
                                                     F16Operands f16, PicardCheck chk,
                                                     const float *__restrict__ blockmax, int nblk_chk,
                                                     const int *done) {
-  if (chk.ctrl != nullptr) {
-    // block 0 of this launch may set *done: one read per block keeps the
-    // block's waves together (a block that sees it set returns, as it would
-    // after the test below)
-    __shared__ int skip;
-    if (threadIdx.x == 0) skip = done != nullptr ? *done : 0;
-    __syncthreads();
-    if (skip) return;
-  } else if (done != nullptr && *done) {
+  if (chk.ctrl == nullptr) {
+    if (done != nullptr && *done) return;
+    prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16);
     return;
   }
-  if (chk.ctrl != nullptr) {
-    // test the previous iteration first: once it has converged this one and
-    // every later kernel of the step do nothing
-    float r;
-    const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      chk.ctrl->last_resid = r;
-      chk.ctrl->checked = chk.iter + 1;
-      if (conv) {
-        chk.ctrl->conv_iter = chk.iter;
-        chk.ctrl->done = 1;
-      }
-    }
-    if (conv) return;
+  // A fixed-point iteration after the first: test the previous one first
+  // (once it has converged this kernel and every later one of the step do
+  // nothing).  Every global load the block needs (the done flag, the
+  // combine kernel's block maxima, the centring partials, the coordinate) is
+  // issued before the first barrier, so they share one memory latency.
+  __shared__ int skip, conv;
+  __shared__ float sr[kRedBlock / 64], sx[kRedBlock / 64], rr;
+  __shared__ double part[16][17];
+  __shared__ float mean_sh[16];
+  const int t = threadIdx.x;
+  // block 0 of this launch may set *done: one read per block keeps the
+  // block's waves together (a block that sees it set returns, as it would
+  // after the test below)
+  if (t == 0) skip = *done;
+  float r = 0.f, x = 0.f;
+#pragma unroll 4
+  for (int b = t; b < nblk_chk; b += kRedBlock) {
+    r = fmaxf(r, blockmax[2 * b]);
+    x = fmaxf(x, blockmax[2 * b + 1]);
   }
-  prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16);
+  const int c = t & 15, j = t >> 4;
+  double mv = 0.0;
+  if (c == 15) {
+#pragma unroll 4
+    for (int b = j; b < nmeanp; b += 16) mv = fmax(mv, meanp[(int64_t)b * 16 + 15]);
+  } else if (c < p.D) {
+#pragma unroll 4
+    for (int b = j; b < nmeanp; b += 16) mv += meanp[(int64_t)b * 16 + c];
+  }
+  const int64_t I = group_particle(blockIdx.x);
+  const int n = group_lane();
+  const float xr = I < p.Ppad ? prep_coord(p, q, I, n) : 0.f;
+  const float wi = I < p.P ? load_weight(w, I, p.uniform_w) : 0.f;
+  for (int off = 32; off > 0; off >>= 1) {
+    r = fmaxf(r, __shfl_xor(r, off));
+    x = fmaxf(x, __shfl_xor(x, off));
+  }
+  if ((t & 63) == 0) {
+    sr[t >> 6] = r;
+    sx[t >> 6] = x;
+  }
+  part[c][j] = mv;
+  __syncthreads();
+  if (skip) return;
+  if (t == 0) {
+    for (int i = 1; i < kRedBlock / 64; ++i) {
+      r = fmaxf(r, sr[i]);
+      x = fmaxf(x, sx[i]);
+    }
+    rr = r;
+    conv = r <= chk.rtol * fmaxf(1.f, x) ? 1 : 0;
+  }
+  if (t < 16 && (t < p.D || t == 15)) {  // the same fixed order as load_mean
+    double m = 0.0;
+    for (int i = 0; i < 16; ++i) m = t == 15 ? fmax(m, part[t][i]) : m + part[t][i];
+    mean_sh[t] = (float)m;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && t == 0) {
+    chk.ctrl->last_resid = rr;
+    chk.ctrl->checked = chk.iter + 1;
+    if (conv) {
+      chk.ctrl->conv_iter = chk.iter;
+      chk.ctrl->done = 1;
+    }
+  }
+  if (conv) return;
+  if (p.vhalf && wscale != nullptr && blockIdx.x == 0 && t == 0) *wscale = mean_sh[15];
+  if (I >= p.Ppad) return;
+  const float xc_n = I < p.P && n < p.D ? xr - mean_sh[n] : 0.f;
+  prep_write(p, I, n, xc_n, wi, mean_sh, xc, wv, QB, KA, VA, f16);
 }
 
 // Component n of row I summed over the column splits, in FP64.
