@@ -334,6 +334,33 @@ def measure_paper_tables(pkg, wl, torch):
     return out
 
 
+def measure_predictor(pkg, wl, torch, P, steps):
+    """Implicit steps of the headline workload started from 2 q^n - q^(n-1)
+    (picard_predictor = 1) against the default start from q^n: time per step,
+    fixed-point iterations and the stress difference after the same steps."""
+    cfg = wl.chain4_shear(P=P)
+    q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
+    out = {"workload": f"chain4_shear P={P}, {steps} implicit steps in one call, rtol 1e-6"}
+    taus = {}
+    for name, pred in (("from_q", 0), ("predictor", 1)):
+        ctx = pkg.Context(3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit",
+                          picard_rtol=1e-6, picard_max=50, picard_batch=3, picard_predictor=pred)
+        ctx.set_tuning(3, 2, 8)
+        ctx.step(q0.clone(), nsteps=3)
+        q = q0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = ctx.step(q, nsteps=steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        taus[name] = d["tau"]
+        out[name] = {"ms_per_step": el * 1e3 / steps, "iterations_per_step": d["iters"] / steps,
+                     "pair_evals_per_s": 2.0 * P * P * d["iters"] / el}
+    out["stress_rel_diff"] = float(np.linalg.norm(taus["predictor"] - taus["from_q"]) / np.linalg.norm(taus["from_q"]))
+    out["speedup"] = out["from_q"]["ms_per_step"] / out["predictor"]["ms_per_step"]
+    return out
+
+
 def measure_fene(pkg, wl, torch, steps):
     """6-bead FENE chain (D = 15), P = 50000, explicit steps of the plain scheme."""
     from paper_2603_12550_amd import _vds
@@ -491,6 +518,7 @@ def main():
                          ("batched", lambda: measure_batched(pkg, wl, torch, args.batched_steps)),
                          ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
                                                             args.learned_run_steps, args.learned_epochs, 300)),
+                         ("implicit_predictor", lambda: measure_predictor(pkg, wl, torch, P, 100)),
                          ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20)),
                          ("appendix_a", lambda: measure_appendix_a(pkg, wl, torch)),
                          ("paper_tables", lambda: measure_paper_tables(pkg, wl, torch))):

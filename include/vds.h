@@ -82,7 +82,9 @@ typedef struct vds_problem {
   int32_t picard_max;    /* implicit: iteration cap (>= 1) */
   double picard_rtol;    /* implicit: stop when max|dx| <= rtol * max(1, max|x|) */
   int32_t picard_batch;  /* implicit: iterations queued per step before the host checks (>= 1) */
-  int32_t reserved;
+  int32_t picard_predictor; /* implicit: 0 iterate from q^n; 1 from 2 q^n - q^(n-1) where the
+                             * previous step of the same vds_step call is at hand (same fixed
+                             * point, about one iteration fewer per step) */
 } vds_problem;
 
 /* Diagnostics of a step or an evaluation (host struct). */

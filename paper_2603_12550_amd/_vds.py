@@ -35,7 +35,7 @@ class vds_problem(C.Structure):
                 ("zeta", C.c_double), ("n", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("G", C.c_double * 9), ("b_max", C.c_double), ("scheme", C.c_int32),
                 ("picard_max", C.c_int32), ("picard_rtol", C.c_double), ("picard_batch", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("picard_predictor", C.c_int32)]
 
 
 class vds_diag(C.Structure):
@@ -175,7 +175,8 @@ def _check(status, ctx=None):
 
 
 def make_problem(nb, P, h, dt=1e-3, kT=1.0, zeta=4.0, n=1.0, G=None, potential="hookean", b_max=0.0,
-                 scheme="implicit", picard_max=50, picard_rtol=1e-6, picard_batch=3) -> vds_problem:
+                 scheme="implicit", picard_max=50, picard_rtol=1e-6, picard_batch=3,
+                 picard_predictor=0) -> vds_problem:
     pr = vds_problem()
     pr.nb, pr.P, pr.h, pr.dt, pr.kT, pr.zeta, pr.n = int(nb), int(P), float(h), float(dt), float(kT), float(zeta), float(n)
     G = np.zeros((3, 3)) if G is None else np.asarray(G, dtype=np.float64).reshape(3, 3)
@@ -185,6 +186,7 @@ def make_problem(nb, P, h, dt=1e-3, kT=1.0, zeta=4.0, n=1.0, G=None, potential="
     pr.b_max = float(b_max)
     pr.scheme = VDS_IMPLICIT if scheme == "implicit" else VDS_EXPLICIT
     pr.picard_max, pr.picard_rtol, pr.picard_batch = int(picard_max), float(picard_rtol), int(picard_batch)
+    pr.picard_predictor = int(picard_predictor)
     return pr
 
 

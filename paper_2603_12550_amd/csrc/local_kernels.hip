@@ -587,7 +587,7 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
 __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck chk, const float *__restrict__ blockmax,
                                                         int nblk_chk, const float *__restrict__ xb0,
                                                         const float *__restrict__ xb1, float *__restrict__ q,
-                                                        int64_t n) {
+                                                        float *__restrict__ xpred, int64_t n) {
   // block 0 may set `halted` and `done` during this launch: one read per
   // block keeps the block's waves together
   __shared__ int st[3];
@@ -618,7 +618,11 @@ __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck 
   }
   const float *src = (it & 1) ? xb1 : xb0;
   const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
-  if (i < n) q[i] = src[i];
+  if (i < n) {
+    const float qn = src[i];
+    if (xpred != nullptr) xpred[i] = 2.f * qn - q[i];
+    q[i] = qn;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->steps_done += 1;
     ctrl->last_iters = it + 1;
@@ -796,8 +800,8 @@ void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, 
 }
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s) { k_ctrl_reset<<<1, 64, 0, s>>>(ctrl); }
 void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
-                     const float *xb1, float *q, int64_t n, hipStream_t s) {
-  k_step_end<<<nblocks(n), kRedBlock, 0, s>>>(ctrl, chk, blockmax, nblk_chk, xb0, xb1, q, n);
+                     const float *xb1, float *q, float *xpred, int64_t n, hipStream_t s) {
+  k_step_end<<<nblocks(n), kRedBlock, 0, s>>>(ctrl, chk, blockmax, nblk_chk, xb0, xb1, q, xpred, n);
 }
 void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s) {
   k_picard_check<<<1, kRedBlock, 0, s>>>(chk, blockmax, nblk_chk);

@@ -103,6 +103,7 @@ bool problem_valid(const vds_problem *p, std::string *why) {
     if (p->picard_max < 1) return fail("picard_max must be >= 1");
     if (!(p->picard_rtol > 0.0)) return fail("picard_rtol must be > 0");
     if (p->picard_batch < 1) return fail("picard_batch must be >= 1");
+    if (p->picard_predictor != 0 && p->picard_predictor != 1) return fail("picard_predictor must be 0 or 1");
   }
   return true;
 }
@@ -141,6 +142,7 @@ Layout make_layout(const vds_problem &p) {
   L.hist = take(sizeof(unsigned long long) * 2 * kHistBins);
   L.xb0 = take(sizeof(float) * p.P * D);
   L.xb1 = take(sizeof(float) * p.P * D);
+  L.xpred = take(sizeof(float) * p.P * D);
   L.total = off;
   return L;
 }
@@ -315,6 +317,7 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->hist = reinterpret_cast<unsigned long long *>(c->ws + L.hist);
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
   c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);
+  c->xpred = reinterpret_cast<float *>(c->ws + L.xpred);
   return VDS_OK;
 }
 
@@ -426,14 +429,17 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
     launch_ctrl_reset(c->ctrl, c->stream);
     for (int j = 0; j < chunk; ++j) {
       launch_mean_partials(c->ep, q, w, c->meanp, nullptr, c->ctrl, c->stream);
+      // with the predictor, steps after the first of the queue start from
+      // the extrapolation the previous step end wrote
+      const float *x0 = (p.picard_predictor && j > 0) ? c->xpred : q;
       for (int m = 0; m < batch; ++m) {
         // iteration m's prep tests iteration m - 1
         const PicardCheck chk{c->ctrl, (float)p.picard_rtol, m - 1};
-        const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
+        const float *xin = (m == 0) ? x0 : c->xb[(m - 1) & 1];
         evaluate(c, xin, w, MODE_PICARD, false, q, c->xb[m & 1], nullptr, done, m > 0 ? &chk : nullptr, false);
       }
       launch_step_end(c->ctrl, PicardCheck{c->ctrl, (float)p.picard_rtol, batch - 1}, c->blockmax, c->nblk_comb,
-                      c->xb[0], c->xb[1], q, nq, c->stream);
+                      c->xb[0], c->xb[1], q, p.picard_predictor ? c->xpred : nullptr, nq, c->stream);
     }
     Ctrl h{};
     vds_status st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream),

@@ -9,7 +9,7 @@
 namespace vds {
 
 struct Layout {
-  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, hist, xb0, xb1, total;
+  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, hist, xb0, xb1, xpred, total;
 };
 
 struct TimerAcc {
@@ -37,7 +37,7 @@ struct vds_ctx_s {
   std::vector<hipEvent_t> event_pool;
 
   // workspace views
-  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *xb[2], *blockmax, *wscale;
+  float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *xb[2], *xpred, *blockmax, *wscale;
   vds::F16Operands f16{};
   unsigned long long *hist;  // median-bandwidth histograms [2][kHistBins]
   double *meanp, *redp, *redout;

@@ -135,9 +135,10 @@ void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, 
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 // Closes a queued implicit step whose last queued iteration is chk.iter: tests
 // it unless an earlier test converged, then copies the converged iterate
-// (xb[conv_iter & 1]) into q and counts the step, or halts the queue.
+// (xb[conv_iter & 1]) into q and counts the step, or halts the queue.  With
+// xpred it also writes the next step's starting point 2 q^(n+1) - q^n there.
 void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
-                     const float *xb1, float *q, int64_t n, hipStream_t s);
+                     const float *xb1, float *q, float *xpred, int64_t n, hipStream_t s);
 // Stand-alone test of iteration chk.iter (host-driven iterations).
 void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s);
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s);

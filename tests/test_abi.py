@@ -50,7 +50,7 @@ def _problem(**kw):
 @pytest.mark.parametrize("bad", [dict(nb=0), dict(nb=6), dict(P=0), dict(h=0.0), dict(h=float("nan")),
                                  dict(dt=-1e-3), dict(zeta=0.0), dict(kT=-1.0),
                                  dict(potential="fene", b_max=0.0), dict(picard_max=0),
-                                 dict(picard_rtol=0.0), dict(picard_batch=0)])
+                                 dict(picard_rtol=0.0), dict(picard_batch=0), dict(picard_predictor=2)])
 def test_invalid_problems_are_rejected_before_any_launch(lib, bad):
     from paper_2603_12550_amd import _vds
     pr = _problem(**bad)

@@ -221,6 +221,30 @@ def test_queued_implicit_steps_match_oracle(lib):
     assert 6 <= d["iters"] <= iters
 
 
+def test_implicit_predictor_same_fixed_point_fewer_iterations(lib):
+    # picard_predictor = 1 starts each step after the first of a call from
+    # 2 q^n - q^(n-1): the same implicit Euler solution (within the fixed-point
+    # tolerance, so within the velocity tolerance of the oracle), reached in
+    # fewer iterations
+    cfg = wl.chain4_shear(P=1500, seed=23)
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    qo = wl.f32_as_f64(q32)
+    kw = dict(H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit")
+    q_plain, q_pred = _dev(q32), _dev(q32)
+    _say("implicit predictor chain4 P=1500, 8 steps")
+    d_plain = _ctx(lib, 3, P, cfg["h"], **kw).step(q_plain, nsteps=8)
+    d_pred = _ctx(lib, 3, P, cfg["h"], picard_predictor=1, **kw).step(q_pred, nsteps=8)
+    for _ in range(8):
+        qo, _ = ovds.step_implicit(qo, w, prob, threads=8)
+    assert _rel(q_pred.cpu().numpy(), qo) < 1e-5
+    assert _rel(q_pred.cpu().numpy(), q_plain.cpu().numpy().astype(np.float64)) < 1e-5
+    assert d_pred["iters"] < d_plain["iters"]
+    assert np.linalg.norm(d_pred["tau"] - d_plain["tau"]) / np.linalg.norm(d_plain["tau"]) < 1e-5
+
+
 @pytest.mark.parametrize("batch", [1, 2, 3])
 def test_queued_implicit_steps_do_not_depend_on_batching(lib, batch):
     # 70 steps (more than one queue of 64): with picard_batch below the
