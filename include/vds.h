@@ -184,8 +184,11 @@ vds_status vds_density_at(vds_ctx ctx, const float *q_dev, const float *w_dev,
 vds_status vds_median_bandwidth(vds_ctx ctx, const float *q_dev, double *med_host, double *h_host);
 
 enum { VDS_TIMER_PAIR = 0, VDS_TIMER_GEMM = 1, VDS_TIMER_KGEMM = 2, VDS_TIMER_PROJ = 3, VDS_TIMER_COUNT = 4 };
-/* enable != 0 starts recording an event pair around every launch of the timed
- * kernels and clears the totals; 0 stops. */
+/* enable = N >= 1 starts recording an event pair around every N-th launch of
+ * each timed kernel (1: every launch) and clears the totals; 0 stops.  The
+ * events carry no system-scope fence (timing only).  Launches that return at
+ * once (fixed-point iterations queued past convergence) are counted too when
+ * sampled. */
 vds_status vds_timing_enable(vds_ctx ctx, int32_t enable);
 /* Synchronises and returns the summed kernel time (ms), the launch count and
  * the pair-evaluations (pair kernel) or flops (GEMMs) of timer `which`. */

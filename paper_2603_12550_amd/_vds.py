@@ -228,8 +228,9 @@ class Context:
         _check(_lib.vds_autotune(self.ctx, _ptr(q), _ptr(w)), self.ctx)
         return self.get_tuning()
 
-    def timing_enable(self, on=True):
-        _check(_lib.vds_timing_enable(self.ctx, 1 if on else 0), self.ctx)
+    def timing_enable(self, on=True, stride=1):
+        """Event timing of every `stride`-th launch of each timed kernel."""
+        _check(_lib.vds_timing_enable(self.ctx, int(stride) if on else 0), self.ctx)
 
     def timing_read(self, which=VDS_TIMER_PAIR):
         ms, n, work = C.c_double(), C.c_int64(), C.c_double()

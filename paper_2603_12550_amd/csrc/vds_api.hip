@@ -38,8 +38,11 @@ hipEvent_t get_event(vds_ctx c) {
     c->event_pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (its cache writeback and invalidation
+  // would slow the kernels between the events); elapsed times are read after
+  // a stream synchronisation
   hipEvent_t e = nullptr;
-  (void)hipEventCreate(&e);
+  (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
   return e;
 }
 
@@ -545,13 +548,16 @@ vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float
 
 vds_status vds_timing_enable(vds_ctx c, int32_t enable) {
   if (c == nullptr) return VDS_ERR_ARG;
+  if (enable < 0) return set_err(c, VDS_ERR_ARG, "timing stride < 0");
   drain_timers(c);
   for (auto &t : c->timers) {
     t.ms = 0.0;
     t.launches = 0;
     t.work = 0.0;
+    t.seen = 0;
   }
   c->timing = enable != 0;
+  c->timing_stride = enable > 0 ? enable : 1;
   return VDS_OK;
 }
 

@@ -16,6 +16,7 @@ struct TimerAcc {
   double ms = 0.0;
   int64_t launches = 0;
   double work = 0.0;
+  int64_t seen = 0;  // launches since timing was enabled, sampled or not
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<double> pending_work;
 };
@@ -33,6 +34,7 @@ struct vds_ctx_s {
   size_t ws_bytes = 0;
   std::string err;
   bool timing = false;
+  int timing_stride = 1;  // time every timing_stride-th launch of each timer
   vds::TimerAcc timers[VDS_TIMER_COUNT];
   std::vector<hipEvent_t> event_pool;
 
@@ -57,7 +59,7 @@ hipEvent_t get_event(vds_ctx c);
 // pair when timing is on; `work` is the pair-evaluations or FLOP it performs.
 template <class F>
 void timed(vds_ctx c, int which, double work, F &&fn) {
-  if (!c->timing) {
+  if (!c->timing || c->timers[which].seen++ % c->timing_stride != 0) {
     fn();
     return;
   }
