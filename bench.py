@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix and packed vector), AMD datasheet
+LEARNED_INPUT_NOISE = 10.0  # training input noise, in increment standard deviations
 TIMING_STRIDE = 4          # event-timed pair launches: every 4th (events between kernels cost ~1 % per stride)
 PEAK_HBM_GBS = 8000.0
 
@@ -264,7 +265,7 @@ def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps)
     init = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in wl.mlp_init(9, [3 * R + 1, 128, 128, 3 * R])])
     m.set_params(torch.from_numpy(wl.to_f32(init)).cuda())
     X, T = learned.training_set(m, trajs)
-    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=3)
+    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=3, input_noise=LEARNED_INPUT_NOISE)
     torch.cuda.synchronize()
     T_offline = time.perf_counter() - t0
     rate = 1.0
@@ -294,7 +295,8 @@ def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps)
     return {
         "workload": f"learned reduced step, 4-bead chain P={P}, R={R} (input {3 * R + 1}, width 128, SiLU), "
                     f"{n_runs} training runs x {run_steps} explicit steps at shear rates log-uniform [0.1, 10] "
-                    f"({int(X.shape[0])} pairs), {epochs} epochs of batch 64 at lr 2e-3; rollout {rollout_steps} steps at the held-out rate 1.0, "
+                    f"({int(X.shape[0])} pairs), {epochs} epochs of batch 64 at lr 2e-3, input noise {LEARNED_INPUT_NOISE} "
+                    f"increment standard deviations; rollout {rollout_steps} steps at the held-out rate 1.0, "
                     f"checked every 50 steps (increment residual <= 0.2, energy-law gap <= 0.5)",
         "offline_s": T_offline, "final_loss": float(losses[-1]), "first_loss": float(losses[0]),
         "T_plain_s": T_plain, "T_rollout_s": T_roll, "speedup_vs_plain": T_plain / T_roll,
@@ -405,7 +407,7 @@ def main():
                     help="skip the POD-reduced, batched, learned and FENE measurements")
     ap.add_argument("--extras", type=str, default="", help="comma-separated subset of the extra measurements")
     ap.add_argument("--batched-steps", type=int, default=200)
-    ap.add_argument("--learned-runs", type=int, default=24)
+    ap.add_argument("--learned-runs", type=int, default=48)
     ap.add_argument("--learned-run-steps", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=200)
     args = ap.parse_args()

@@ -76,6 +76,14 @@ vds_status vds_mlp_fit_scaling(vds_mlp m, const float *X_dev, const float *T_dev
 vds_status vds_mlp_make_pairs(vds_mlp m, const float *traj_dev, int32_t nt, float log_rate, float *X_dev,
                               float *T_dev);
 
+/* Input-noise regularisation of vds_mlp_train_epoch (for learned steps, nin =
+ * nout + 1): each gathered input coefficient c < nout gets sigma * y_scale[c]
+ * * xi in raw units, xi standard normal (SplitMix64 counters and the
+ * Box-Muller transform, stream `seed`, restarted by this call), the target
+ * unchanged, so that the network's increment varies little off the training
+ * trajectories.  sigma = 0 (the default) turns it off. */
+vds_status vds_mlp_set_input_noise(vds_mlp m, float sigma, uint64_t seed);
+
 /* One pass over n raw samples in minibatches of `batch` rows: each minibatch
  * gathers rows order_dev[i] (a permutation of 0..n-1 supplied by the caller;
  * NULL = in order), applies the scaling, then loss_grad + adam_step (beta1 0.9,

@@ -132,6 +132,7 @@ _sigs.update({
     "vds_mlp_get_grads": ([_P, _P], C.c_int),
     "vds_mlp_forward": ([_P, _P, C.c_int32, _P, C.c_int32], C.c_int),
     "vds_mlp_predict_steps": ([_P, _P, C.c_float, C.c_int32], C.c_int),
+    "vds_mlp_set_input_noise": ([_P, C.c_float, C.c_uint64], C.c_int),
     "vds_mlp_loss_grad": ([_P, _P, _P, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_mlp_adam_step": ([_P, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
     "vds_mlp_train_epoch": ([_P, _P, _P, C.c_int32, C.c_int32, C.c_float, _P, C.POINTER(C.c_double)], C.c_int),
@@ -485,6 +486,10 @@ class Mlp:
         Y = torch.empty((X.shape[0], self.nout), dtype=torch.float32, device=self.device)
         _mcheck(_lib.vds_mlp_forward(self.m, _ptr(X), int(X.shape[0]), _ptr(Y), 1 if bf16 else 0), self.m)
         return Y
+
+    def set_input_noise(self, sigma, seed=0):
+        """Training input noise of sigma increment standard deviations."""
+        _mcheck(_lib.vds_mlp_set_input_noise(self.m, float(sigma), int(seed)), self.m)
 
     def predict_steps(self, p, log_rate, nsteps):
         """nsteps learned steps on the reduced state p (in place)."""

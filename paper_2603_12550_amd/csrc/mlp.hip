@@ -441,19 +441,45 @@ __global__ __launch_bounds__(kRegThreads) void k_learned_steps_reg(float *__rest
     for (int i = t; i < np_; i += kRegThreads) p[i] = ps[i];
 }
 
+// SplitMix64 (Steele, Lea and Flood 2014): a counter-based stream of 64-bit
+// values; one call per draw.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+// Standard normal draw number `ctr` of stream `seed` by the Box-Muller
+// transform of two SplitMix64 uniforms in (0, 1].
+__device__ inline float normal_draw(uint64_t seed, uint64_t ctr) {
+  const uint64_t a = splitmix64(seed ^ splitmix64(2 * ctr)), b = splitmix64(seed ^ splitmix64(2 * ctr + 1));
+  const double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53, u2 = (double)(b >> 11) * 0x1.0p-53;
+  return (float)(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
 // Minibatch rows i < nb: xin[i] = (X[order[i0 + i]] - xs) / xsc, tin likewise.
+// With noise > 0 (learned steps, nin = nout + 1) input c < nout also gets
+// noise * (ysc[c] / xsc[c]) * xi, xi standard normal from (seed, draw_base +
+// row * nin + c): a perturbation of the state coefficient by `noise` standard
+// deviations of its increment, the target unchanged.
 __global__ void k_gather_scaled(const float *__restrict__ X, const float *__restrict__ T,
                                 const int *__restrict__ order, int i0, int nb, int nin, int nout,
                                 const float *__restrict__ xs, const float *__restrict__ xsc,
                                 const float *__restrict__ ys, const float *__restrict__ ysc, float *__restrict__ xin,
-                                float *__restrict__ tin) {
+                                float *__restrict__ tin, float noise, uint64_t seed, uint64_t draw_base) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t row_len = nin + nout;
   if (t >= (int64_t)nb * row_len) return;
   const int i = (int)(t / row_len), c = (int)(t % row_len);
   const int64_t src = order ? order[i0 + i] : i0 + i;
-  if (c < nin) xin[(int64_t)i * nin + c] = (X[src * nin + c] - xs[c]) / xsc[c];
-  else tin[(int64_t)i * nout + (c - nin)] = (T[src * nout + (c - nin)] - ys[c - nin]) / ysc[c - nin];
+  if (c < nin) {
+    float x = (X[src * nin + c] - xs[c]) / xsc[c];
+    if (noise > 0.f && c < nout)
+      x += noise * (ysc[c] / xsc[c]) * normal_draw(seed, draw_base + (uint64_t)i * nin + c);
+    xin[(int64_t)i * nin + c] = x;
+  } else {
+    tin[(int64_t)i * nout + (c - nin)] = (T[src * nout + (c - nin)] - ys[c - nin]) / ysc[c - nin];
+  }
 }
 
 // Column mean and standard deviation of A[n][m] (FP64 sums); zero spread -> 1.
@@ -504,6 +530,8 @@ struct vds_mlp_s {
   double *loss_out;  // one slot after the per-block partials
   int t = 0;
   bool bf_stale = true;
+  float noise = 0.f;          // training input noise (vds_mlp_set_input_noise)
+  uint64_t noise_seed = 0, noise_draws = 0;
   std::string err;
   // parameter block views
   float *W1() { return params; }
@@ -613,8 +641,9 @@ void refresh_bf16(vds_mlp m) {
 // LDS floats of the fused step kernel: x, two hidden layers, p and the output.
 int64_t fused_lds_floats(vds_mlp m) { return (int64_t)m->nin + 2 * m->w + 2 * (int64_t)m->nout; }
 
-// nsteps learned steps on p (or one increment into dp): the fused kernel when
-// its LDS fits, else the layer-by-layer BF16 kernels step by step.
+// nsteps learned steps on p (or one increment into dp): the kernel with the
+// weights on chip, or the one streaming them, or the layer-by-layer BF16
+// kernels step by step.
 void learned_steps(vds_mlp m, float *p, float *dp, float log_rate, int nsteps);
 
 void forward_bf16(vds_mlp m, const float *X, int n, float *Y) {
@@ -767,6 +796,16 @@ vds_status vds_mlp_forward(vds_mlp m, const float *X, int32_t n, float *Y, int32
   return mhip(m, hipGetLastError(), "forward");
 }
 
+vds_status vds_mlp_set_input_noise(vds_mlp m, float sigma, uint64_t seed) {
+  if (!m) return VDS_ERR_ARG;
+  if (!(sigma >= 0.f) || !std::isfinite(sigma)) return merr(m, VDS_ERR_ARG, "noise must be finite and >= 0");
+  if (sigma > 0.f && m->nin != m->nout + 1) return merr(m, VDS_ERR_ARG, "input noise needs nin = nout + 1");
+  m->noise = sigma;
+  m->noise_seed = seed;
+  m->noise_draws = 0;
+  return VDS_OK;
+}
+
 vds_status vds_mlp_predict_steps(vds_mlp m, float *p, float log_rate, int32_t nsteps) {
   if (!m || !p) return VDS_ERR_ARG;
   if (!m->ws) return merr(m, VDS_ERR_STATE, "no workspace bound");
@@ -811,7 +850,9 @@ vds_status vds_mlp_train_epoch(vds_mlp m, const float *X, const float *T, int32_
   double acc = 0.0;
   for (int bi = 0; bi < nbatch; ++bi) {
     k_gather_scaled<<<nb256((int64_t)batch * (m->nin + m->nout)), 256, 0, m->s>>>(
-        X, T, order, bi * batch, batch, m->nin, m->nout, m->xs, m->xsc, m->ys, m->ysc, m->xin, m->tin);
+        X, T, order, bi * batch, batch, m->nin, m->nout, m->xs, m->xsc, m->ys, m->ysc, m->xin, m->tin, m->noise,
+        m->noise_seed, m->noise_draws);
+    m->noise_draws += (uint64_t)batch * m->nin;
     forward_fp32(m, m->xin, batch);
     backward_fp32(m, m->xin, m->tin, batch);
     vds_mlp_adam_step(m, lr, 0.9f, 0.999f, 1e-8f);

@@ -49,9 +49,13 @@ def training_set(mlp: Mlp, trajectories):
     return torch.cat(Xs).contiguous(), torch.cat(Ts).contiguous()
 
 
-def train(mlp: Mlp, X: torch.Tensor, T: torch.Tensor, epochs: int, batch: int, lr: float, seed: int = 0):
-    """Fits the scaling, then `epochs` passes in seeded random order; returns the losses."""
+def train(mlp: Mlp, X: torch.Tensor, T: torch.Tensor, epochs: int, batch: int, lr: float, seed: int = 0,
+          input_noise: float = 0.0):
+    """Fits the scaling, then `epochs` passes in seeded random order (with input
+    noise of `input_noise` increment standard deviations, vds_mlp_set_input_noise);
+    returns the losses."""
     mlp.fit_scaling(X, T)
+    mlp.set_input_noise(input_noise, seed)
     gen = torch.Generator(device="cpu").manual_seed(seed)
     losses = []
     for _ in range(epochs):

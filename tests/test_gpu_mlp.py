@@ -153,6 +153,42 @@ def test_training_epochs_reduce_loss(lib):
     assert losses[-1] < 0.2 * losses[0]
 
 
+def test_input_noise_is_seeded_and_off_by_default(lib):
+    # vds_mlp_set_input_noise: sigma = 0 is the plain epoch (bit for bit), the
+    # same seed gives the same epoch, another seed another one; with the
+    # learning rate 0 the epoch's loss grows with the noise
+    rng = np.random.default_rng(8)
+    nout = 12
+    X = rng.standard_normal((256, nout + 1))
+    T = 0.1 * rng.standard_normal((256, nout))
+    init = _dev(_flat(wl.mlp_init(3, [nout + 1, 16, 16, nout])))
+
+    def epoch(sigma, seed, lr=3e-3, set_noise=True):
+        m = lib.Mlp(nout + 1, 16, nout, 64)
+        m.set_params(init)
+        m.fit_scaling(_dev(X), _dev(T))
+        if set_noise:
+            m.set_input_noise(sigma, seed)
+        loss = m.train_epoch(_dev(X), _dev(T), 64, lr)
+        return loss, m.get_params().cpu().numpy()
+
+    l_plain, p_plain = epoch(0.0, 0, set_noise=False)
+    l0, p0 = epoch(0.0, 5)
+    assert l0 == l_plain and np.array_equal(p0, p_plain)
+    la, pa = epoch(2.0, 7)
+    lb, pb = epoch(2.0, 7)
+    lc, pc = epoch(2.0, 8)
+    assert la == lb and np.array_equal(pa, pb)
+    assert not np.array_equal(pa, pc)
+    assert epoch(2.0, 7, lr=0.0)[0] > epoch(0.0, 7, lr=0.0)[0]
+    m = lib.Mlp(nout + 1, 16, nout, 64)
+    with pytest.raises(lib.VDSError):
+        m.set_input_noise(-1.0)
+    m2 = lib.Mlp(nout + 2, 16, nout, 64)
+    with pytest.raises(lib.VDSError):
+        m2.set_input_noise(1.0)
+
+
 def _pipeline(lib, P=400, R=20, rates=(0.5, 1.0, 2.0), nsteps=300, width=64, epochs=150):
     import torch
     from paper_2603_12550_amd import learned

@@ -112,9 +112,11 @@ def test_pod_basis_on_vds_snapshots_vs_oracle_svd(lib):
     assert abs((E * E).sum() - lam_o[R:].sum()) < 1e-5 * lam_o.sum()
 
 
-def test_project_and_reconstruct(lib):
-    rng = np.random.default_rng(2)
-    P, nb, R = 700, 3, 25
+@pytest.mark.parametrize("P,nb,R", [(700, 3, 25), (10, 1, 1), (333, 5, 8), (2000, 3, 180), (20000, 3, 180)])
+def test_project_and_reconstruct(lib, P, nb, R):
+    # the skinny kernels: R not a multiple of their unrolling, row chunks of
+    # the projection that are short or empty (P = 10: 30 rows in 16 chunks)
+    rng = np.random.default_rng(2 + P)
     U, _ = np.linalg.qr(rng.standard_normal((3 * P, R)))
     U32 = wl.to_f32(U.T)
     q32 = wl.to_f32(wl.gaussian_bonds(3, nb, P, 1 / 3))
