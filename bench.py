@@ -65,6 +65,13 @@ def kernel_source_hash() -> str:
 
 
 PAIR_KERNEL = {0: "k_pair_mfma", 1: "k_pair_valu", 2: "k_pair_mfma16", 3: "k_pair_mfma16"}
+PAIR_ARITHMETIC = {
+    0: "pair products on FP32 MFMA, FP32 exponentials",
+    1: "pair products as FP32 vector FMAs, FP32 exponentials",
+    2: "distances on FP32 MFMA, kernel-weighted sums on FP16 MFMA with split factors, FP32 accumulation",
+    3: "both pair products on FP16 MFMA with every factor split into high and low halves, FP32 accumulation "
+       "and exponentials",
+}
 # v_exp_f32 issues at a quarter of the FP32 lane rate: 8 lanes per cycle per SIMD
 EXP_PER_S = 256 * 4 * 8 * 2.4e9
 PEAK_FP16_TFLOPS = 2500.0
@@ -496,11 +503,13 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_detail": PAIR_ARITHMETIC[tune["impl"]] + "; FP64 split sums and observables",
         "data": "synthetic: 4-bead chain bonds drawn N(0, I/3), seed 2",
         "config": {"workload": f"chain4_shear: 4-bead Hookean chain, P={P}, D=9, h=0.4, shear rate 1, "
                                f"implicit Euler dt=1e-3, fixed-point rtol 1e-6",
                    "P": P, "D": D, "pair_tuning": tune,
-                   "fixed_point_iterations": iters},
+                   "fixed_point_iterations_total": iters,
+                   "fixed_point_iterations_per_step": iters / max(1, args.steps)},
         "roofline": {"bound": "mfma" if tune["impl"] == 0 else "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
