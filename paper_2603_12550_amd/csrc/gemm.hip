@@ -100,8 +100,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, int splits, c
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)M * N) return;
   const int i = (int)(t / N), j = (int)(t % N);
-  double s = 0.0;
-  for (int sp = 0; sp < splits; ++sp) s += (double)part[(int64_t)sp * M * N + t];
+  const double s = ordered_sum<double>(part + t, splits, (int64_t)M * N);
   float *dst = c_colmajor ? &C[(int64_t)j * ldc + i] : &C[(int64_t)i * ldc + j];
   const float v = (float)((double)alpha * s);
   *dst = accumulate ? *dst + v : v;

@@ -134,11 +134,9 @@ __device__ void load_mean(const EvalParams &p, const double *meanp, int nmeanp, 
   __shared__ double part[16][17];
   const int c = threadIdx.x & 15, j = threadIdx.x >> 4;  // blockDim.x == 256
   double v = 0.0;
-  if (c == 15) {
-    for (int b = j; b < nmeanp; b += 16) v = fmax(v, meanp[(int64_t)b * 16 + 15]);
-  } else if (c < p.D) {
-    for (int b = j; b < nmeanp; b += 16) v += meanp[(int64_t)b * 16 + c];
-  }
+  const int nj = strided_count(j, nmeanp, 16);
+  if (c == 15) v = strided_max(meanp + (int64_t)j * 16 + 15, nj, 256, 0.0);
+  else if (c < p.D) v = ordered_sum<double>(meanp + (int64_t)j * 16 + c, nj, 256);
   part[c][j] = v;
   __syncthreads();
   if (threadIdx.x < 16 && (threadIdx.x < p.D || threadIdx.x == 15)) {
@@ -174,11 +172,9 @@ __device__ bool picard_converged(const PicardCheck &chk, const float *__restrict
   __shared__ float sr[kRedBlock / 64], sx[kRedBlock / 64];
   __shared__ int conv;
   __shared__ float rr;
-  float r = 0.f, x = 0.f;
-  for (int b = threadIdx.x; b < nblk; b += kRedBlock) {
-    r = fmaxf(r, blockmax[2 * b]);
-    x = fmaxf(x, blockmax[2 * b + 1]);
-  }
+  const int nt = strided_count(threadIdx.x, nblk, kRedBlock);
+  float r = strided_max(blockmax + 2 * threadIdx.x, nt, 2 * kRedBlock, 0.f);
+  float x = strided_max(blockmax + 2 * threadIdx.x + 1, nt, 2 * kRedBlock, 0.f);
   for (int off = 32; off > 0; off >>= 1) {
     r = fmaxf(r, __shfl_xor(r, off));
     x = fmaxf(x, __shfl_xor(x, off));
@@ -302,21 +298,14 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
   // block's waves together (a block that sees it set returns, as it would
   // after the test below)
   if (t == 0) skip = *done;
-  float r = 0.f, x = 0.f;
-#pragma unroll 4
-  for (int b = t; b < nblk_chk; b += kRedBlock) {
-    r = fmaxf(r, blockmax[2 * b]);
-    x = fmaxf(x, blockmax[2 * b + 1]);
-  }
+  const int nt = strided_count(t, nblk_chk, kRedBlock);
+  float r = strided_max(blockmax + 2 * t, nt, 2 * kRedBlock, 0.f);
+  float x = strided_max(blockmax + 2 * t + 1, nt, 2 * kRedBlock, 0.f);
   const int c = t & 15, j = t >> 4;
   double mv = 0.0;
-  if (c == 15) {
-#pragma unroll 4
-    for (int b = j; b < nmeanp; b += 16) mv = fmax(mv, meanp[(int64_t)b * 16 + 15]);
-  } else if (c < p.D) {
-#pragma unroll 4
-    for (int b = j; b < nmeanp; b += 16) mv += meanp[(int64_t)b * 16 + c];
-  }
+  const int nj = strided_count(j, nmeanp, 16);
+  if (c == 15) mv = strided_max(meanp + (int64_t)j * 16 + 15, nj, 256, 0.0);
+  else if (c < p.D) mv = ordered_sum<double>(meanp + (int64_t)j * 16 + c, nj, 256);
   const int64_t I = group_particle(blockIdx.x);
   const int n = group_lane();
   const float xr = I < p.Ppad ? prep_coord(p, q, I, n) : 0.f;
@@ -361,12 +350,10 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
   prep_write(p, I, n, xc_n, wi, mean_sh, xc, wv, QB, KA, VA, f16);
 }
 
-// Component n of row I summed over the column splits, in FP64.
+// Component n of row I summed over the column splits in split order, in FP64.
 __device__ inline double sum_splits(const EvalParams &p, const float *__restrict__ partial, int splits, int64_t I,
                                     int n) {
-  double o = 0.0;
-  for (int s = 0; s < splits; ++s) o += (double)partial[((int64_t)s * p.Ppad + I) * 16 + n];
-  return o;
+  return ordered_sum<double>(partial + I * 16 + n, splits, p.Ppad * 16);
 }
 
 // Pass-A finalisation: S_I = w_I + sum_{J != I} w_J e_IJ,
@@ -596,12 +583,21 @@ __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck 
     st[1] = ctrl->done;
     st[2] = ctrl->conv_iter;
   }
+  // the copy's loads for the tested iteration (the usual outcome) go out
+  // before the test, so that their latency overlaps it
+  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  float qn = 0.f, qo = 0.f;
+  if (i < n) {
+    qn = ((chk.iter & 1) ? xb1 : xb0)[i];
+    if (xpred != nullptr) qo = q[i];
+  }
   __syncthreads();
   if (st[0]) return;
   int it;
   if (st[1]) {
     it = st[2];  // converged at an earlier test of this step
     if (it < 0) return;
+    if (i < n && ((it ^ chk.iter) & 1)) qn = ((it & 1) ? xb1 : xb0)[i];
   } else {
     float r;
     const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
@@ -616,11 +612,8 @@ __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck 
     if (!conv) return;
     it = chk.iter;
   }
-  const float *src = (it & 1) ? xb1 : xb0;
-  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
   if (i < n) {
-    const float qn = src[i];
-    if (xpred != nullptr) xpred[i] = 2.f * qn - q[i];
+    if (xpred != nullptr) xpred[i] = 2.f * qn - qo;
     q[i] = qn;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -699,9 +692,7 @@ __global__ __launch_bounds__(kRedBlock) void k_density_out(const float *__restri
                                                            float *__restrict__ f) {
   const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
   if (I >= ny) return;
-  float s = 0.f;
-  for (int sp = 0; sp < splits; ++sp) s += partial[((int64_t)sp * stride_rows + I) * 16 + D];
-  f[I] = s * norm;
+  f[I] = ordered_sum<float>(partial + I * 16 + D, splits, stride_rows * 16) * norm;
 }
 
 // ---- batched ensembles: the same bodies, per ensemble ----

@@ -104,8 +104,7 @@ __global__ void k_rom_scalars(const float *__restrict__ part, int splits, int64_
     invS[I] = 0.f;
     return;
   }
-  double o = 0.0;
-  for (int s = 0; s < splits; ++s) o += (double)part[((int64_t)s * Ppad + I) * 16 + D];
+  const double o = ordered_sum<double>(part + I * 16 + D, splits, Ppad * 16);
   const double Si = (double)S[I];
   T[I] = (float)(o + (double)wv[I] / Si);
   invS[I] = (float)(1.0 / Si);

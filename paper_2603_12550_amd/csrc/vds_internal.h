@@ -86,6 +86,44 @@ struct EnsDesc {
   int blk256;       // first 256-particle block of the ensemble
 };
 
+// sum_{k < n} src[k stride], added in the order of k into Acc.  The loads of
+// eight terms are issued together, so a sum over column splits or block
+// partials waits for one memory latency per eight terms rather than one per
+// term (a plain loop waits for each load before its add).  Terms past n are
+// read as zero, which leaves every sum unchanged.
+template <typename Acc, typename T>
+__device__ inline Acc ordered_sum(const T *__restrict__ src, int n, int64_t stride) {
+  Acc o = Acc(0);
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = k0 + j < n ? src[(int64_t)(k0 + j) * stride] : T(0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o += (Acc)v[j];
+  }
+  return o;
+}
+
+// fmax(init, src[k stride]) over k < n (NaN terms ignored, as fmax does),
+// the loads issued eight at a time.
+template <typename T>
+__device__ inline T strided_max(const T *__restrict__ src, int n, int64_t stride, T init) {
+  T m = init;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = k0 + j < n ? src[(int64_t)(k0 + j) * stride] : init;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m = fmax(m, v[j]);
+  }
+  return m;
+}
+
+// Terms of a strided loop b = first, first + step, ... < end.
+__host__ __device__ inline int strided_count(int first, int end, int step) {
+  return first < end ? (end - first + step - 1) / step : 0;
+}
+
 // Modes of the combine kernel.
 enum CombineMode { MODE_TERMS = 0, MODE_VELOCITY = 1, MODE_EXPLICIT = 2, MODE_PICARD = 3, MODE_OBS_ONLY = 4 };
 
