@@ -211,7 +211,8 @@ class Context:
         _check(_lib.vds_bind_workspace(self.ctx, _ptr(self.ws), nbytes), self.ctx)
 
     def __del__(self):
-        if getattr(self, "ctx", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "ctx", None) and _lib is not None:
             _lib.vds_destroy(self.ctx)
             self.ctx = None
 
@@ -339,7 +340,8 @@ class Rom:
         self.rom = h
 
     def __del__(self):
-        if getattr(self, "rom", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "rom", None) and _lib is not None:
             _lib.vds_rom_destroy(self.rom)
             self.rom = None
 
@@ -410,7 +412,8 @@ class Batch:
         self.offsets = [int(_lib.vds_batch_state_offset(self.b, e)) for e in range(self.nens + 1)]
 
     def __del__(self):
-        if getattr(self, "b", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "b", None) and _lib is not None:
             _lib.vds_batch_destroy(self.b)
             self.b = None
 
@@ -465,7 +468,8 @@ class Mlp:
         self.nparams = int(_lib.vds_mlp_param_count(self.m))
 
     def __del__(self):
-        if getattr(self, "m", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "m", None) and _lib is not None:
             _lib.vds_mlp_destroy(self.m)
             self.m = None
 

@@ -259,10 +259,12 @@ __device__ void prep_write(const EvalParams &p, int64_t I, int n, float x, float
 __device__ void prep_body(const EvalParams &p, int64_t lb, const float *__restrict__ q, const float *__restrict__ w,
                           const double *__restrict__ meanp, int nmeanp, float *__restrict__ xc,
                           float *__restrict__ wv, float *__restrict__ QB, float *__restrict__ KA,
-                          float *__restrict__ VA, float *__restrict__ wscale, F16Operands f16) {
+                          float *__restrict__ VA, float *__restrict__ wscale, F16Operands f16,
+                          float *__restrict__ cmean = nullptr) {
   __shared__ float mean_sh[16];
   load_mean(p, meanp, nmeanp, mean_sh);
   if (p.vhalf && wscale != nullptr && lb == 0 && threadIdx.x == 0) *wscale = mean_sh[15];
+  if (cmean != nullptr && lb == 0 && threadIdx.x < 16) cmean[threadIdx.x] = mean_sh[threadIdx.x];
   const int64_t I = group_particle(lb);
   const int n = group_lane();
   if (I >= p.Ppad) return;
@@ -278,10 +280,10 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
                                                     float *__restrict__ VA, float *__restrict__ wscale,
                                                     F16Operands f16, PicardCheck chk,
                                                     const float *__restrict__ blockmax, int nblk_chk,
-                                                    const int *done) {
+                                                    const int *done, float *__restrict__ cmean) {
   if (chk.ctrl == nullptr) {
     if (done != nullptr && *done) return;
-    prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16);
+    prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16, cmean);
     return;
   }
   // A fixed-point iteration after the first: test the previous one first
@@ -345,6 +347,7 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
   }
   if (conv) return;
   if (p.vhalf && wscale != nullptr && blockIdx.x == 0 && t == 0) *wscale = mean_sh[15];
+  if (cmean != nullptr && blockIdx.x == 0 && t < 16) cmean[t] = mean_sh[t];
   if (I >= p.Ppad) return;
   const float xc_n = I < p.P && n < p.D ? xr - mean_sh[n] : 0.f;
   prep_write(p, I, n, xc_n, wi, mean_sh, xc, wv, QB, KA, VA, f16);
@@ -396,12 +399,14 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const fl
 // g = kT b + grad Psi, u = -(1/zeta)(A (x) I) g, flow G q, and by mode the
 // terms, the velocity, an explicit update or a fixed-point update (whose flow
 // term is taken at the step's start state qs).  With `obs` it also
-// accumulates F_h, dissipation, work and stress in FP64.
+// accumulates F_h, dissipation, work and stress in FP64.  With pack.VA set
+// (fixed-point mode) it packs the new iterate's pair operands as the prep
+// kernel would: the same lanes hold the same coordinates there.
 __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs, const float *__restrict__ partial,
-                             int splits, const float *__restrict__ xc, const float *__restrict__ t1,
-                             const float *__restrict__ S, const float *__restrict__ wv, const float *qin,
+                             int splits, const float *xc, const float *__restrict__ t1,
+                             const float *__restrict__ S, const float *wv, const float *qin,
                              const float *__restrict__ qs, float *out, float *out2, double *__restrict__ redp,
-                             float *__restrict__ blockmax) {
+                             float *__restrict__ blockmax, const PackOps &pack) {
   __shared__ double sm[12][kRedBlock];
   const int64_t I = group_particle(lb);
   const int n = group_lane();
@@ -412,7 +417,7 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
   double red[12];
 #pragma unroll
   for (int s = 0; s < 12; ++s) red[s] = 0.0;
-  float resid = 0.f, xmax = 0.f;
+  float resid = 0.f, xmax = 0.f, xnew = 0.f;
 
   const double o = comp ? sum_splits(p, partial, splits, I, n) : 0.0;
   const float t2v = (float)(-(double)p.inv_h2 * o);
@@ -462,7 +467,15 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
         out[idx] = xn;
         resid = fabsf(xn - qv);
         xmax = fabsf(xn);
+        xnew = xn;
       }
+    }
+    if (mode == MODE_PICARD && pack.VA != nullptr) {
+      // the prep kernel's work for the new iterate: wv already holds the
+      // step's weights (zero past the particles)
+      const float x = comp ? xnew - pack.cmean[n] : 0.f;
+      const float wi = real ? wv[I] : 0.f;
+      prep_write(p, I, n, x, wi, pack.cmean, pack.xc, pack.wv, pack.QB, pack.KA, pack.VA, pack.f16);
     }
     if (obs) {
       // stress column beta needs grad Psi of this bond's component beta
@@ -510,13 +523,14 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
 
 __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, int obs,
                                                        const float *__restrict__ partial, int splits,
-                                                       const float *__restrict__ xc, const float *__restrict__ t1,
-                                                       const float *__restrict__ S, const float *__restrict__ wv,
+                                                       const float *xc, const float *__restrict__ t1,
+                                                       const float *__restrict__ S, const float *wv,
                                                        const float *qin, const float *__restrict__ qs,
                                                        float *out, float *out2, double *__restrict__ redp,
-                                                       float *__restrict__ blockmax, const int *__restrict__ done) {
+                                                       float *__restrict__ blockmax, const int *__restrict__ done,
+                                                       PackOps pack) {
   if (done != nullptr && *done) return;
-  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qs, out, out2, redp, blockmax);
+  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qs, out, out2, redp, blockmax, pack);
 }
 
 // Sum over blocks of the FP64 block partials, slot by slot: wave s takes slot s,
@@ -539,14 +553,18 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double *__restrict_
   if (lane == 0) out[s] = acc;
 }
 
-// Stand-alone convergence test (host-driven iterations).
+// Stand-alone convergence test: between the fixed-point iterations of a
+// queued step (after a combine that packed the next iterate) and in the
+// host-driven iterations.
 __global__ __launch_bounds__(kRedBlock) void k_picard_check(PicardCheck chk, const float *__restrict__ blockmax,
                                                             int nblk_chk) {
   Ctrl *ctrl = chk.ctrl;
-  if (ctrl->done) return;
+  // the flag and the block maxima are loaded together (one block: nothing
+  // else writes the flag during this launch)
+  const int done = ctrl->done;
   float r;
   const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
-  if (threadIdx.x != 0) return;
+  if (done || threadIdx.x != 0) return;
   ctrl->last_resid = r;
   ctrl->checked = chk.iter + 1;
   if (conv) {
@@ -740,7 +758,7 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_explicit(BatchView b, const
   const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
   const int64_t o = d.pad_off;
   combine_body(d.p, blockIdx.x - d.blk16, MODE_EXPLICIT, 0, partial + o * 16, 1, xc + o * b.D, t1 + o * b.D, S + o,
-               wv + o, q + d.q_off, nullptr, q + d.q_off, nullptr, nullptr, nullptr);
+               wv + o, q + d.q_off, nullptr, q + d.q_off, nullptr, nullptr, nullptr, PackOps{});
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_batch_stress(BatchView b, const float *__restrict__ q,
@@ -770,11 +788,11 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 }
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
                  float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16, const int *done,
-                 hipStream_t s, const PicardCheck *chk, const float *blockmax, int nblk_chk) {
+                 hipStream_t s, const PicardCheck *chk, const float *blockmax, int nblk_chk, float *cmean) {
   const F16Operands ops = f16 != nullptr ? *f16 : F16Operands{nullptr, nullptr, nullptr};
   const PicardCheck c = chk != nullptr ? *chk : PicardCheck{nullptr, 0.f, 0};
   k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, c,
-                                                    blockmax, nblk_chk, done);
+                                                    blockmax, nblk_chk, done, cmean);
 }
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {
@@ -782,9 +800,11 @@ void launch_finalize_a(const EvalParams &p, const float *partial, int splits, co
 }
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
-                    float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s) {
+                    float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s,
+                    const PackOps *pack) {
+  const PackOps pk = pack != nullptr ? *pack : PackOps{};
   k_combine<<<nblocks(p.P * 16), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, q0,
-                                                    out, out2, redp, blockmax, done);
+                                                    out, out2, redp, blockmax, done, pk);
 }
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s) {
   k_reduce_final<<<1, 1024, 0, s>>>(redp, nblk, nslots, out, done);

@@ -139,6 +139,7 @@ Layout make_layout(const vds_problem &p) {
   L.ctrl = take(sizeof(Ctrl));
   L.blockmax = take(sizeof(float) * 2 * nblk);
   L.wscale = take(sizeof(float) * 4);
+  L.cmean = take(sizeof(float) * 16);
   L.QH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
   L.KH = take(sizeof(uint16_t) * Ppad * 32 * f16_slices(D));
   L.RN = take(sizeof(float) * Ppad);
@@ -316,6 +317,7 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->ctrl = reinterpret_cast<Ctrl *>(c->ws + L.ctrl);
   c->blockmax = reinterpret_cast<float *>(c->ws + L.blockmax);
   c->wscale = reinterpret_cast<float *>(c->ws + L.wscale);
+  c->cmean = reinterpret_cast<float *>(c->ws + L.cmean);
   c->f16 = F16Operands{c->ws + L.QH, c->ws + L.KH, reinterpret_cast<float *>(c->ws + L.RN)};
   c->hist = reinterpret_cast<unsigned long long *>(c->ws + L.hist);
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
@@ -436,10 +438,22 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
       // the extrapolation the previous step end wrote
       const float *x0 = (p.picard_predictor && j > 0) ? c->xpred : q;
       for (int m = 0; m < batch; ++m) {
-        // iteration m's prep tests iteration m - 1
-        const PicardCheck chk{c->ctrl, (float)p.picard_rtol, m - 1};
         const float *xin = (m == 0) ? x0 : c->xb[(m - 1) & 1];
-        evaluate(c, xin, w, MODE_PICARD, false, q, c->xb[m & 1], nullptr, done, m > 0 ? &chk : nullptr, false);
+        if (m == 0) {
+          launch_prep(c->ep, x0, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done,
+                      c->stream, nullptr, nullptr, 0, c->cmean);
+        } else {
+          // the previous combine packed this iterate's operands; one block
+          // tests the previous iteration
+          launch_picard_check(PicardCheck{c->ctrl, (float)p.picard_rtol, m - 1}, c->blockmax, c->nblk_comb,
+                              c->stream);
+        }
+        pair_pass(c, c->VA, c->wscale, done);
+        launch_finalize_a(c->ep, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
+        eval_pass_b(c, done);
+        const PackOps pk{c->xc, c->wv, c->QB, c->KA, c->VA, c->f16, c->cmean};
+        launch_combine(c->ep, MODE_PICARD, false, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, xin, q,
+                       c->xb[m & 1], nullptr, c->redp, c->blockmax, done, c->stream, m + 1 < batch ? &pk : nullptr);
       }
       launch_step_end(c->ctrl, PicardCheck{c->ctrl, (float)p.picard_rtol, batch - 1}, c->blockmax, c->nblk_comb,
                       c->xb[0], c->xb[1], q, p.picard_predictor ? c->xpred : nullptr, nq, c->stream);

@@ -9,7 +9,8 @@
 namespace vds {
 
 struct Layout {
-  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, QH, KH, RN, hist, xb0, xb1, xpred, total;
+  size_t QB, KA, VA, VB, part, xc, t1, S, wv, meanp, redp, redout, ctrl, blockmax, wscale, cmean, QH, KH, RN, hist, xb0,
+      xb1, xpred, total;
 };
 
 struct TimerAcc {
@@ -40,6 +41,7 @@ struct vds_ctx_s {
 
   // workspace views
   float *QB, *KA, *VA, *VB, *part, *xc, *t1, *S, *wv, *xb[2], *xpred, *blockmax, *wscale;
+  float *cmean;  // a step's centre and weight maximum (see vds::PackOps)
   vds::F16Operands f16{};
   unsigned long long *hist;  // median-bandwidth histograms [2][kHistBins]
   double *meanp, *redp, *redout;

@@ -124,6 +124,16 @@ __host__ __device__ inline int strided_count(int first, int end, int step) {
   return first < end ? (end - first + step - 1) / step : 0;
 }
 
+// Operands the combine kernel packs for the next fixed-point iterate, as the
+// prep kernel would (VA == nullptr: no packing).  cmean holds the step's
+// centre in slots 0..D-1 and the weight maximum in slot 15, as the prep
+// kernel of the step's first iteration wrote them.
+struct PackOps {
+  float *xc, *wv, *QB, *KA, *VA;
+  F16Operands f16;
+  const float *cmean;
+};
+
 // Modes of the combine kernel.
 enum CombineMode { MODE_TERMS = 0, MODE_VELOCITY = 1, MODE_EXPLICIT = 2, MODE_PICARD = 3, MODE_OBS_ONLY = 4 };
 
@@ -157,18 +167,22 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 // weights divided by their maximum, which goes to *wscale; with p.qhalf the
 // FP16 distance operands and row norms too (f16 may be null otherwise).
 // With `chk`, the launch first tests iteration chk->iter (block maxima of
-// nblk_chk combine blocks) and does nothing once it has converged.
+// nblk_chk combine blocks) and does nothing once it has converged.  cmean
+// (may be null) receives the centre and weight maximum (see PackOps).
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp,
                  float *xc, float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16,
                  const int *done, hipStream_t s, const PicardCheck *chk = nullptr, const float *blockmax = nullptr,
-                 int nblk_chk = 0);
+                 int nblk_chk = 0, float *cmean = nullptr);
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 // In MODE_PICARD, q0 is the state at the start of the step (the flow term is
 // taken there) and each block leaves its maxima of |dx| and |x| in blockmax.
+// With `pack` (MODE_PICARD), it also writes the next iterate's pair operands
+// from `out`, centred at pack->cmean (the prep kernel's work for that iterate).
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
-                    float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s);
+                    float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s,
+                    const PackOps *pack = nullptr);
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s);
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 // Closes a queued implicit step whose last queued iteration is chk.iter: tests
@@ -177,7 +191,8 @@ void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 // xpred it also writes the next step's starting point 2 q^(n+1) - q^n there.
 void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
                      const float *xb1, float *q, float *xpred, int64_t n, hipStream_t s);
-// Stand-alone test of iteration chk.iter (host-driven iterations).
+// Stand-alone test of iteration chk.iter, one block (queued steps after a
+// packing combine; host-driven iterations).
 void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s);
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s);
 void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,
