@@ -320,6 +320,29 @@ def test_explicit_steps_match_oracle_fene(lib, tuning):
 
 
 @pytest.mark.parametrize("tuning", IMPLS)
+def test_queued_implicit_steps_fene_chain6_match_oracle(lib, tuning):
+    # D = 15: two FP16 distance slices, written by the prep kernel for a
+    # step's first iteration and by the combine kernel for the later ones
+    cfg = wl.fene_chain6(P=700)
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w = ovds.uniform_weights(P)
+    q32 = wl.to_f32(cfg["q0"])
+    qo = wl.f32_as_f64(q32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 5, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme="implicit", potential="fene",
+               b_max=cfg["b_max"], picard_batch=4)
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    _say(f"queued implicit steps FENE chain6 P=700 tuning {tuning}")
+    d = ctx.step(qg, nsteps=3)
+    for _ in range(3):
+        qo, _ = ovds.step_implicit(qo, w, prob)
+    assert 1 <= d["last_iters"] <= 10
+    assert _rel(qg.cpu().numpy(), qo) < 1e-5
+
+
+@pytest.mark.parametrize("tuning", IMPLS)
 def test_implicit_step_full_size_solves_the_implicit_equation(lib, tuning):
     # chain4 at P = 20000: one implicit step on the GPU; on sampled rows the
     # oracle checks (q+ - q*)/dt = u(q+) with q* = q + dt G q (Appendix A)
