@@ -251,32 +251,10 @@ def measure_batched(pkg, wl, torch, steps):
     }
 
 
-def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps):
-    """Learned reduced step on the 4-bead chain (R = 180, input 541, width 128):
-    training pairs from projected explicit runs at log-uniform shear rates, then
-    a checked rollout at a held-out rate against the plain scheme and against the
-    POD-Galerkin reduced model (the method without the network)."""
+def _learned_rollout_vs_plain(torch, ctx, m, U, q0, rate, rollout_steps):
+    """Plain-scheme run and checked learned rollout from q0 over rollout_steps
+    steps: (T_plain, tau_ref, T_rollout, rollout stats)."""
     import math
-    from paper_2603_12550_amd import learned
-    R, h = 180, 0.4
-    rates = wl.mlp_shear_rates(n_runs)
-    q0 = torch.from_numpy(wl.to_f32(wl.gaussian_bonds(2, 3, P, 1 / 3))).cuda()
-    ctxs = [pkg.Context(3, P, h, G=wl.shear_gradient(r), dt=1e-3, scheme="explicit") for r in rates]
-    t0 = time.perf_counter()
-    states = []
-    for ctx in ctxs:
-        states += learned.run_states(ctx, q0, run_steps, 10)
-    U, eig = ctxs[0].pod_basis(learned.snapshot_matrix(states), R)
-    trajs = [(learned.reduced_trajectory(ctx, U, q0, run_steps), math.log(r)) for ctx, r in zip(ctxs, rates)]
-    m = pkg.Mlp(3 * R + 1, 128, 3 * R, 256)
-    init = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in wl.mlp_init(9, [3 * R + 1, 128, 128, 3 * R])])
-    m.set_params(torch.from_numpy(wl.to_f32(init)).cuda())
-    X, T = learned.training_set(m, trajs)
-    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=3, input_noise=LEARNED_INPUT_NOISE)
-    torch.cuda.synchronize()
-    T_offline = time.perf_counter() - t0
-    rate = 1.0
-    ctx = pkg.Context(3, P, h, G=wl.shear_gradient(rate), dt=1e-3, scheme="explicit")
     q = q0.clone()
     ctx.step(q.clone(), nsteps=2)
     torch.cuda.synchronize()
@@ -290,7 +268,46 @@ def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps)
     t2 = time.perf_counter()
     st = m.rollout(ctx, U, p, math.log(rate), nsteps=rollout_steps, check_every=50, resid_tol=0.2, energy_tol=0.5)
     torch.cuda.synchronize()
-    T_roll = time.perf_counter() - t2
+    return T_plain, tau_ref, time.perf_counter() - t2, st
+
+
+def _train_learned(pkg, wl, torch, mk, q0, nb, R, rates, n_snap_runs, run_steps, epochs):
+    """POD basis from the snapshots (every 10 steps) of the first n_snap_runs
+    runs, training pairs from the projected trajectories of every run, and the
+    trained network; returns (U, m, pairs, losses)."""
+    import math
+    from paper_2603_12550_amd import learned
+    states = []
+    for r in rates[:n_snap_runs]:
+        states += learned.run_states(mk(r), q0, run_steps, 10)
+    U, _ = mk(rates[0]).pod_basis(learned.snapshot_matrix(states), R)
+    del states
+    trajs = [(learned.reduced_trajectory(mk(r), U, q0, run_steps), math.log(r)) for r in rates]
+    nin, nout = nb * R + 1, nb * R
+    m = pkg.Mlp(nin, 128, nout, 256)
+    init = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in wl.mlp_init(9, [nin, 128, 128, nout])])
+    m.set_params(torch.from_numpy(wl.to_f32(init)).cuda())
+    X, T = learned.training_set(m, trajs)
+    del trajs
+    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=3, input_noise=LEARNED_INPUT_NOISE)
+    return U, m, int(X.shape[0]), losses
+
+
+def measure_learned(pkg, wl, torch, P, n_runs, n_snap_runs, run_steps, epochs, rollout_steps):
+    """Learned reduced step on the 4-bead chain (R = 180, input 541, width 128):
+    explicit runs at log-uniform shear rates in [0.1, 10], then a checked rollout
+    at a held-out rate against the plain scheme and against the POD-Galerkin
+    reduced model (the method without the network)."""
+    R, h, rate = 180, 0.4, 1.0
+    rates = wl.mlp_shear_rates(n_runs)
+    q0 = torch.from_numpy(wl.to_f32(wl.gaussian_bonds(2, 3, P, 1 / 3))).cuda()
+    mk = lambda r: pkg.Context(3, P, h, G=wl.shear_gradient(r), dt=1e-3, scheme="explicit")
+    t0 = time.perf_counter()
+    U, m, pairs, losses = _train_learned(pkg, wl, torch, mk, q0, 3, R, rates, n_snap_runs, run_steps, epochs)
+    torch.cuda.synchronize()
+    T_offline = time.perf_counter() - t0
+    ctx = mk(rate)
+    T_plain, tau_ref, T_roll, st = _learned_rollout_vs_plain(torch, ctx, m, U, q0, rate, rollout_steps)
     rom = pkg.Rom(ctx, U)
     pg = ctx.pod_project(U, q0)
     torch.cuda.synchronize()
@@ -302,15 +319,49 @@ def measure_learned(pkg, wl, torch, P, n_runs, run_steps, epochs, rollout_steps)
     return {
         "workload": f"learned reduced step, 4-bead chain P={P}, R={R} (input {3 * R + 1}, width 128, SiLU), "
                     f"{n_runs} training runs x {run_steps} explicit steps at shear rates log-uniform [0.1, 10] "
-                    f"({int(X.shape[0])} pairs), {epochs} epochs of batch 64 at lr 2e-3, input noise {LEARNED_INPUT_NOISE} "
-                    f"increment standard deviations; rollout {rollout_steps} steps at the held-out rate 1.0, "
-                    f"checked every 50 steps (increment residual <= 0.2, energy-law gap <= 0.5)",
+                    f"({pairs} pairs; basis from the snapshots of the first {n_snap_runs} runs), {epochs} epochs of "
+                    f"batch 64 at lr 2e-3, input noise {LEARNED_INPUT_NOISE} increment standard deviations; rollout "
+                    f"{rollout_steps} steps at the held-out rate {rate}, checked every 50 steps (increment residual "
+                    f"<= 0.2, energy-law gap <= 0.5)",
         "offline_s": T_offline, "final_loss": float(losses[-1]), "first_loss": float(losses[0]),
         "T_plain_s": T_plain, "T_rollout_s": T_roll, "speedup_vs_plain": T_plain / T_roll,
         "stress_rel_err_vs_plain": err(st["tau"]), "checks": st["checks"], "fallbacks": st["fallbacks"],
         "max_resid": st["max_resid"], "max_energy_gap": st["max_energy_gap"],
         "without_network_pod_galerkin": {"T_s": T_gal, "stress_rel_err_vs_plain": err(tau_gal),
                                          "speedup_vs_plain": T_plain / T_gal},
+    }
+
+
+def measure_learned_fene(pkg, wl, torch, n_runs, R, run_steps, epochs, rollout_steps):
+    """The learned reduced step re-instantiated on the 6-bead FENE chain (D = 15,
+    P = 50000): its own basis (R per bond), network and training runs at
+    log-uniform shear rates in [0.3, 3], and a checked rollout at the held-out
+    rate 1 against the plain scheme.  The POD-Galerkin model has no FENE form
+    (its reduced spring term is exact only for linear springs), so the plain
+    scheme is the method without the network here."""
+    import math
+    cfg = wl.fene_chain6()
+    P, rate = cfg["P"], 1.0
+    rates = wl.mlp_shear_rates(n_runs, log10_range=(math.log10(0.3), math.log10(3.0)))
+    q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
+    mk = lambda r: pkg.Context(5, P, cfg["h"], G=wl.shear_gradient(r), dt=cfg["dt"], scheme="explicit",
+                               potential="fene", b_max=cfg["b_max"])
+    t0 = time.perf_counter()
+    U, m, pairs, losses = _train_learned(pkg, wl, torch, mk, q0, 5, R, rates, n_runs, run_steps, epochs)
+    torch.cuda.synchronize()
+    T_offline = time.perf_counter() - t0
+    T_plain, tau_ref, T_roll, st = _learned_rollout_vs_plain(torch, mk(rate), m, U, q0, rate, rollout_steps)
+    err = float(np.linalg.norm(st["tau"] - tau_ref) / np.linalg.norm(tau_ref))
+    return {
+        "workload": f"learned reduced step, 6-bead FENE chain P={P}, D=15, b_max={cfg['b_max']}, R={R} per bond "
+                    f"(input {5 * R + 1}, width 128, SiLU), {n_runs} training runs x {run_steps} explicit steps at "
+                    f"shear rates log-uniform [0.3, 3] ({pairs} pairs), {epochs} epochs of batch 64 at lr 2e-3, input "
+                    f"noise {LEARNED_INPUT_NOISE}; rollout {rollout_steps} steps at the held-out rate {rate}, checked "
+                    f"every 50 steps (increment residual <= 0.2, energy-law gap <= 0.5)",
+        "offline_s": T_offline, "final_loss": float(losses[-1]), "first_loss": float(losses[0]),
+        "T_plain_s": T_plain, "T_rollout_s": T_roll, "speedup_vs_plain": T_plain / T_roll,
+        "stress_rel_err_vs_plain": err, "checks": st["checks"], "fallbacks": st["fallbacks"],
+        "max_resid": st["max_resid"], "max_energy_gap": st["max_energy_gap"],
     }
 
 
@@ -414,9 +465,11 @@ def main():
                     help="skip the POD-reduced, batched, learned and FENE measurements")
     ap.add_argument("--extras", type=str, default="", help="comma-separated subset of the extra measurements")
     ap.add_argument("--batched-steps", type=int, default=200)
-    ap.add_argument("--learned-runs", type=int, default=48)
+    ap.add_argument("--learned-runs", type=int, default=334, help="training runs (300 steps each: 1e5 pairs)")
+    ap.add_argument("--learned-snapshot-runs", type=int, default=48, help="runs whose snapshots make the basis")
     ap.add_argument("--learned-run-steps", type=int, default=300)
-    ap.add_argument("--learned-epochs", type=int, default=200)
+    ap.add_argument("--learned-epochs", type=int, default=60)
+    ap.add_argument("--fene-learned-runs", type=int, default=32)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -535,7 +588,10 @@ def main():
         for name, fn in (("pod_reduced", lambda: measure_pod_rom(pkg, wl, torch, P)),
                          ("batched", lambda: measure_batched(pkg, wl, torch, args.batched_steps)),
                          ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
-                                                            args.learned_run_steps, args.learned_epochs, 300)),
+                                                            args.learned_snapshot_runs, args.learned_run_steps,
+                                                            args.learned_epochs, 300)),
+                         ("learned_fene", lambda: measure_learned_fene(pkg, wl, torch, args.fene_learned_runs, 108,
+                                                                       300, 200, 300)),
                          ("implicit_predictor", lambda: measure_predictor(pkg, wl, torch, P, 100)),
                          ("fene_chain6", lambda: measure_fene(pkg, wl, torch, 20)),
                          ("appendix_a", lambda: measure_appendix_a(pkg, wl, torch)),

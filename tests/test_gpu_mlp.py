@@ -236,3 +236,44 @@ def test_learned_rollout_tracks_plain_scheme_and_falls_back(lib):
     p = ctx.pod_project(U, q0)
     st10 = m.rollout(ctx, U, p, math.log(r), nsteps=100, check_every=50, resid_tol=0.5, energy_tol=0.5)
     assert st10["fallbacks"] == st10["checks"] == 2
+
+
+def test_learned_rollout_fene_chain6(lib):
+    # the same pipeline on the 6-bead FENE chain (five bonds: its own basis and
+    # network); the POD-Galerkin model has no FENE form, the rollout checks
+    # itself against the plain scheme
+    import torch
+    from paper_2603_12550_amd import learned
+    P, R, nsteps = 400, 20, 300
+    cfg = wl.fene_chain6(P=P)
+
+    def mk(r):
+        return lib.Context(5, P, cfg["h"], G=wl.shear_gradient(r), dt=cfg["dt"], scheme="explicit",
+                           potential="fene", b_max=cfg["b_max"])
+
+    _say("learned-step pipeline, FENE chain6 P=400 R=20")
+    q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
+    rates = (0.5, 1.0, 2.0)
+    states = []
+    for r in rates:
+        states += learned.run_states(mk(r), q0, nsteps, 10)
+    U, _ = mk(1.0).pod_basis(learned.snapshot_matrix(states), R)
+    trajs = [(learned.reduced_trajectory(mk(r), U, q0, nsteps), math.log(r)) for r in rates]
+    m = lib.Mlp(5 * R + 1, 64, 5 * R, 256)
+    m.set_params(_dev(_flat(wl.mlp_init(8, [5 * R + 1, 64, 64, 5 * R]))))
+    X, T = learned.training_set(m, trajs)
+    losses = learned.train(m, X, T, epochs=150, batch=64, lr=2e-3, seed=2)
+    assert losses[-1] < 0.1 * losses[0]
+    ctx = mk(1.0)
+    q = q0.clone()
+    ctx.step(q, nsteps=nsteps)
+    tau_ref = ctx.stress(q)
+    st = m.rollout(ctx, U, ctx.pod_project(U, q0), 0.0, nsteps=nsteps, check_every=50, resid_tol=0.5,
+                   energy_tol=0.5)
+    _say("rollout", st)
+    assert st["checks"] == 6
+    assert np.linalg.norm(st["tau"] - tau_ref) / np.linalg.norm(tau_ref) < 1e-2
+    st0 = m.rollout(ctx, U, ctx.pod_project(U, q0), 0.0, nsteps=nsteps, check_every=50, resid_tol=0.0,
+                    energy_tol=0.5)
+    assert st0["fallbacks"] == st0["checks"] == 6
+    assert np.linalg.norm(st0["tau"] - tau_ref) / np.linalg.norm(tau_ref) < 1e-2

@@ -184,10 +184,11 @@ def density_grid(D: int, values=(-2.0, 0.0, 2.0)) -> np.ndarray:
     return np.stack([a.reshape(-1) for a in axes], axis=1)
 
 
-def mlp_shear_rates(n_runs: int, seed: int = 5) -> np.ndarray:
-    """Shear rates of the learned-model training runs, log-uniform in [0.1, 10]."""
+def mlp_shear_rates(n_runs: int, seed: int = 5, log10_range=(-1.0, 1.0)) -> np.ndarray:
+    """Shear rates of the learned-model training runs, log-uniform in
+    [10^lo, 10^hi] (default [0.1, 10])."""
     rng = np.random.default_rng(seed)
-    return 10.0 ** rng.uniform(-1.0, 1.0, size=n_runs)
+    return 10.0 ** rng.uniform(log10_range[0], log10_range[1], size=n_runs)
 
 
 def mlp_init(seed: int, sizes) -> list:
