@@ -142,7 +142,13 @@ vds_status vds_pair_sums(vds_ctx ctx, const float *q_dev, const float *w_dev,
 
 /* Particle velocity v = dq/dt of eq. model_DymRepPar into v_dev[nb][P][3].
  * `diag` (host, may be NULL) receives the stress and, at no extra kernel
- * cost, F_h, dissipation and work at q. */
+ * cost, F_h, dissipation and work at q.
+ * FENE domain: with FENE springs, every call that evaluates the spring force
+ * (vds_velocity, vds_step, vds_energy) returns VDS_ERR_ARG when a bond of an
+ * evaluated state has |q_j|^2 >= b_max or is not finite.  The kernels flag
+ * such bonds on the device and the call synchronises to read the flag.  The
+ * outputs are then meaningless, and vds_step leaves q_dev at the steps taken
+ * so far. */
 vds_status vds_velocity(vds_ctx ctx, const float *q_dev, const float *w_dev, float *v_dev, vds_diag *diag);
 
 /* Advances q_dev in place by `nsteps` steps of the problem's scheme

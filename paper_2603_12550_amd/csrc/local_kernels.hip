@@ -406,7 +406,7 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
                              int splits, const float *xc, const float *__restrict__ t1,
                              const float *__restrict__ S, const float *wv, const float *qin,
                              const float *__restrict__ qs, float *out, float *out2, double *__restrict__ redp,
-                             float *__restrict__ blockmax, const PackOps &pack) {
+                             float *__restrict__ blockmax, const PackOps &pack, int *fene_out) {
   __shared__ double sm[12][kRedBlock];
   const int64_t I = group_particle(lb);
   const int n = group_lane();
@@ -437,6 +437,8 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
     float fac = H, psi = 0.f;
     if (p.potential == VDS_FENE) {
       const float sb = 1.f - r2 / p.b_max;
+      // outside the domain (or not finite): every such lane stores the same flag
+      if (fene_out != nullptr && comp && !(sb > 0.f)) *fene_out = 1;
       fac = H / sb;
       psi = comp && al == 0 ? -0.5f * H * p.b_max * logf(sb) : 0.f;
     } else {
@@ -528,9 +530,10 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, i
                                                        const float *qin, const float *__restrict__ qs,
                                                        float *out, float *out2, double *__restrict__ redp,
                                                        float *__restrict__ blockmax, const int *__restrict__ done,
-                                                       PackOps pack) {
+                                                       PackOps pack, int *fene_out) {
   if (done != nullptr && *done) return;
-  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qs, out, out2, redp, blockmax, pack);
+  combine_body(p, blockIdx.x, mode, obs, partial, splits, xc, t1, S, wv, qin, qs, out, out2, redp, blockmax, pack,
+               fene_out);
 }
 
 // Sum over blocks of the FP64 block partials, slot by slot: wave s takes slot s,
@@ -583,6 +586,7 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
   ctrl->steps_done = 0;
   ctrl->last_iters = 0;
   ctrl->total_iters = 0;
+  ctrl->fene_out = 0;
 }
 
 // End of a queued implicit step (see launch_step_end).  Only block 0 writes
@@ -758,7 +762,7 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_explicit(BatchView b, const
   const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
   const int64_t o = d.pad_off;
   combine_body(d.p, blockIdx.x - d.blk16, MODE_EXPLICIT, 0, partial + o * 16, 1, xc + o * b.D, t1 + o * b.D, S + o,
-               wv + o, q + d.q_off, nullptr, q + d.q_off, nullptr, nullptr, nullptr, PackOps{});
+               wv + o, q + d.q_off, nullptr, q + d.q_off, nullptr, nullptr, nullptr, PackOps{}, nullptr);
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_batch_stress(BatchView b, const float *__restrict__ q,
@@ -801,10 +805,10 @@ void launch_finalize_a(const EvalParams &p, const float *partial, int splits, co
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
                     float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s,
-                    const PackOps *pack) {
+                    const PackOps *pack, int *fene_out) {
   const PackOps pk = pack != nullptr ? *pack : PackOps{};
   k_combine<<<nblocks(p.P * 16), kRedBlock, 0, s>>>(p, mode, obs ? 1 : 0, partial, splits, xc, t1, S, wv, qin, q0,
-                                                    out, out2, redp, blockmax, done, pk);
+                                                    out, out2, redp, blockmax, done, pk, fene_out);
 }
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s) {
   k_reduce_final<<<1, 1024, 0, s>>>(redp, nblk, nslots, out, done);

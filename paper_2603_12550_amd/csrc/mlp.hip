@@ -944,30 +944,37 @@ vds_status vds_mlp_rollout_run(vds_mlp m, vds_ctx ctx, const float *U, int32_t R
     if (st != VDS_OK) return st;
     learned_steps(m, p, nullptr, log_rate, n);
     st = observe(p, &d1);
+    // a reconstructed FENE bond outside the spring's domain fails the window
+    const bool outside = st == VDS_ERR_ARG && pr.potential == VDS_FENE;
+    if (outside) st = VDS_OK;
     if (st != VDS_OK) return st;
-    // full-step residual at the window's end state
-    learned_steps(m, p, dp_net, log_rate, 1);
-    st = vds_pod_project(ctx, U, R, v, dp_vds, mws, mapw);
-    if (st != VDS_OK) return st;
-    st = mhip(m, hipMemcpyAsync(a.data(), dp_net, 4 * np_, hipMemcpyDeviceToHost, m->s), "copy");
-    if (st == VDS_OK) st = mhip(m, hipMemcpyAsync(b.data(), dp_vds, 4 * np_, hipMemcpyDeviceToHost, m->s), "copy");
-    if (st == VDS_OK) st = mhip(m, hipStreamSynchronize(m->s), "synchronise");
-    if (st != VDS_OK) return st;
-    double num = 0.0, den = 0.0;
-    for (int i = 0; i < np_; ++i) {
-      const double ref = dt * (double)b[i];
-      num += ((double)a[i] - ref) * ((double)a[i] - ref);
-      den += ref * ref;
+    double resid = HUGE_VAL, egap = HUGE_VAL;
+    if (!outside) {
+      // full-step residual at the window's end state
+      learned_steps(m, p, dp_net, log_rate, 1);
+      st = vds_pod_project(ctx, U, R, v, dp_vds, mws, mapw);
+      if (st != VDS_OK) return st;
+      st = mhip(m, hipMemcpyAsync(a.data(), dp_net, 4 * np_, hipMemcpyDeviceToHost, m->s), "copy");
+      if (st == VDS_OK) st = mhip(m, hipMemcpyAsync(b.data(), dp_vds, 4 * np_, hipMemcpyDeviceToHost, m->s), "copy");
+      if (st == VDS_OK) st = mhip(m, hipStreamSynchronize(m->s), "synchronise");
+      if (st != VDS_OK) return st;
+      double num = 0.0, den = 0.0;
+      for (int i = 0; i < np_; ++i) {
+        const double ref = dt * (double)b[i];
+        num += ((double)a[i] - ref) * ((double)a[i] - ref);
+        den += ref * ref;
+      }
+      resid = std::sqrt(num / std::max(den, 1e-300));
+      const double rate0 = d0.work - d0.dissipation, rate1 = d1.work - d1.dissipation;
+      const double gap = std::fabs(d1.F - d0.F - 0.5 * dt * n * (rate0 + rate1));
+      const double scale =
+          0.5 * dt * n * (std::fabs(d0.work) + d0.dissipation + std::fabs(d1.work) + d1.dissipation);
+      egap = gap / std::max(scale, 1e-300);
+      S.max_resid = std::max(S.max_resid, resid);
+      S.max_energy_gap = std::max(S.max_energy_gap, egap);
     }
-    const double resid = std::sqrt(num / std::max(den, 1e-300));
-    const double rate0 = d0.work - d0.dissipation, rate1 = d1.work - d1.dissipation;
-    const double gap = std::fabs(d1.F - d0.F - 0.5 * dt * n * (rate0 + rate1));
-    const double scale = 0.5 * dt * n * (std::fabs(d0.work) + d0.dissipation + std::fabs(d1.work) + d1.dissipation);
-    const double egap = gap / std::max(scale, 1e-300);
     S.checks += 1;
-    S.max_resid = std::max(S.max_resid, resid);
-    S.max_energy_gap = std::max(S.max_energy_gap, egap);
-    if (!(resid <= resid_tol) || !(egap <= energy_tol)) {
+    if (outside || !(resid <= resid_tol) || !(egap <= energy_tol)) {
       // redo the window with the plain scheme from its start
       st = vds_pod_reconstruct(ctx, U, R, p_acc, qt, mws, mapw);
       if (st == VDS_OK) st = vds_step(ctx, qt, nullptr, n, nullptr);

@@ -48,6 +48,10 @@ hipEvent_t get_event(vds_ctx c) {
 
 int64_t ncol_chunks(const vds_ctx c) { return (c->prob.P + 15) / 16; }
 
+// Where the combine kernel flags FENE bonds outside the spring's domain (NULL
+// for Hookean springs).
+int *fene_flag(vds_ctx c) { return c->prob.potential == VDS_FENE ? &c->ctrl->fene_out : nullptr; }
+
 // One pair pass over all particle rows with the V operand `V`.
 // `wscale` is the weight maximum the FP16-split V operand was divided by
 // (pass A), or NULL (pass B: its weights w_J / S_J are at most one already).
@@ -206,8 +210,21 @@ void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, con
   eval_pass_a(c, q, w, done, centre, chk);
   eval_pass_b(c, done);
   launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, q0, out, out2, c->redp,
-                 c->blockmax, done, c->stream);
+                 c->blockmax, done, c->stream, nullptr, fene_flag(c));
   if (obs) launch_reduce_final(c->redp, c->nblk_comb, 12, c->redout, done, c->stream);
+}
+
+// Reads and clears the FENE domain flag (FENE problems only; synchronises).
+vds_status fene_domain_check(vds_ctx c) {
+  if (c->prob.potential != VDS_FENE) return VDS_OK;
+  int out = 0;
+  vds_status st = hip_check(c, hipMemcpyAsync(&out, fene_flag(c), sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                            "copy flag");
+  if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+  if (st != VDS_OK) return st;
+  if (out == 0) return VDS_OK;
+  launch_ctrl_reset(c->ctrl, c->stream);
+  return set_err(c, VDS_ERR_ARG, "a FENE bond reached |q|^2 >= b_max (outside the spring's domain) or is not finite");
 }
 
 vds_status fetch_obs(vds_ctx c, vds_diag *d) {
@@ -352,8 +369,10 @@ vds_status vds_velocity(vds_ctx c, const float *q, const float *w, float *v, vds
   vds_status st = ready(c);
   if (st != VDS_OK) return st;
   if (!q || !v) return set_err(c, VDS_ERR_ARG, "null array");
+  if (c->prob.potential == VDS_FENE) launch_ctrl_reset(c->ctrl, c->stream);
   evaluate(c, q, w, MODE_VELOCITY, d != nullptr, nullptr, v, nullptr, nullptr);
   st = hip_check(c, hipGetLastError(), "launch");
+  if (st == VDS_OK) st = fene_domain_check(c);
   if (st != VDS_OK || d == nullptr) return st;
   std::memset(d, 0, sizeof(*d));
   return fetch_obs(c, d);
@@ -396,6 +415,8 @@ vds_status finish_step(vds_ctx c, float *q, const float *w, int m0, StepCounts &
                               "copy ctrl");
     if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
     if (st != VDS_OK) return st;
+    if (h.fene_out)
+      return set_err(c, VDS_ERR_ARG, "a FENE bond reached |q|^2 >= b_max (outside the spring's domain) or is not finite");
     if (h.done) {
       converged = true;
       break;
@@ -453,7 +474,8 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
         eval_pass_b(c, done);
         const PackOps pk{c->xc, c->wv, c->QB, c->KA, c->VA, c->f16, c->cmean};
         launch_combine(c->ep, MODE_PICARD, false, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, xin, q,
-                       c->xb[m & 1], nullptr, c->redp, c->blockmax, done, c->stream, m + 1 < batch ? &pk : nullptr);
+                       c->xb[m & 1], nullptr, c->redp, c->blockmax, done, c->stream, m + 1 < batch ? &pk : nullptr,
+                       fene_flag(c));
       }
       launch_step_end(c->ctrl, PicardCheck{c->ctrl, (float)p.picard_rtol, batch - 1}, c->blockmax, c->nblk_comb,
                       c->xb[0], c->xb[1], q, p.picard_predictor ? c->xpred : nullptr, nq, c->stream);
@@ -463,6 +485,8 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
                               "copy ctrl");
     if (st == VDS_OK) st = hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
     if (st != VDS_OK) return st;
+    if (h.fene_out)
+      return set_err(c, VDS_ERR_ARG, "a FENE bond reached |q|^2 >= b_max (outside the spring's domain) or is not finite");
     n.total_iters += (int)h.total_iters;
     if (h.steps_done > 0) n.last_iters = h.last_iters;
     n.last_resid = h.last_resid;  // of the last iteration checked
@@ -490,7 +514,10 @@ vds_status vds_step(vds_ctx c, float *q, const float *w, int32_t nsteps, vds_dia
   const vds_problem &p = c->prob;
   StepCounts n;
   if (p.scheme == VDS_EXPLICIT) {
+    if (p.potential == VDS_FENE && nsteps > 0) launch_ctrl_reset(c->ctrl, c->stream);
     for (int s = 0; s < nsteps; ++s) evaluate(c, q, w, MODE_EXPLICIT, false, nullptr, q, nullptr, nullptr);
+    if (nsteps > 0) st = fene_domain_check(c);
+    if (st != VDS_OK) return st;
   } else if (nsteps > 0) {
     int taken = 0;
     st = implicit_steps(c, q, w, nsteps, n, taken);
@@ -527,7 +554,10 @@ vds_status vds_energy(vds_ctx c, const float *q, const float *w, double *F, doub
   vds_status st = ready(c);
   if (st != VDS_OK) return st;
   if (!q) return set_err(c, VDS_ERR_ARG, "null state");
+  if (c->prob.potential == VDS_FENE) launch_ctrl_reset(c->ctrl, c->stream);
   evaluate(c, q, w, MODE_OBS_ONLY, true, nullptr, nullptr, nullptr, nullptr);
+  st = fene_domain_check(c);
+  if (st != VDS_OK) return st;
   vds_diag d{};
   st = fetch_obs(c, &d);
   if (st != VDS_OK) return st;

@@ -34,6 +34,7 @@ struct Ctrl {
   int steps_done;         // queued steps written back since the last reset
   int last_iters;         // iterations of the last step written back
   long long total_iters;  // iterations of the steps written back since the last reset
+  int fene_out;           // a combine kernel saw a FENE bond with |q|^2 >= b_max (or not finite)
 };
 
 // Convergence test of one fixed-point iteration, taken from the combine
@@ -179,10 +180,12 @@ void launch_finalize_a(const EvalParams &p, const float *partial, int splits, co
 // taken there) and each block leaves its maxima of |dx| and |x| in blockmax.
 // With `pack` (MODE_PICARD), it also writes the next iterate's pair operands
 // from `out`, centred at pack->cmean (the prep kernel's work for that iterate).
+// With fene_out (FENE springs), a bond of qin outside the spring's domain sets
+// *fene_out to 1.
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
                     float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s,
-                    const PackOps *pack = nullptr);
+                    const PackOps *pack = nullptr, int *fene_out = nullptr);
 void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, const int *done, hipStream_t s);
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 // Closes a queued implicit step whose last queued iteration is chk.iter: tests

@@ -139,6 +139,31 @@ def test_velocity_chain4_full_size_sampled_rows(lib, tuning):
     assert err < 1e-5, err
 
 
+def test_fene_state_outside_the_domain_is_rejected(lib):
+    # one bond with |q|^2 = 53 >= b_max = 50: every call that evaluates the
+    # spring force reports it, and the next valid call works again
+    import torch
+    cfg = wl.fene_chain6(P=300)
+    P = cfg["P"]
+    good = wl.to_f32(cfg["q0"])
+    bad = good.copy()
+    bad[2, 17] = [6.0, 4.0, 1.0]
+    kw = dict(G=cfg["G"], dt=cfg["dt"], potential="fene", b_max=cfg["b_max"])
+    for scheme in ("explicit", "implicit"):
+        ctx = _ctx(lib, 5, P, cfg["h"], scheme=scheme, **kw)
+        _say(f"FENE domain check, {scheme}")
+        ctx.velocity(_dev(good))
+        with pytest.raises(lib.VDSError, match="FENE"):
+            ctx.velocity(_dev(bad))
+        with pytest.raises(lib.VDSError, match="FENE"):
+            ctx.step(_dev(bad))
+        with pytest.raises(lib.VDSError, match="FENE"):
+            ctx.energy(_dev(bad))
+        q = _dev(good)
+        ctx.step(q, nsteps=2)
+        assert bool(torch.isfinite(q).all().item())
+
+
 @pytest.mark.parametrize("tuning", IMPLS)
 def test_velocity_fene_chain6_sampled_rows(lib, tuning):
     cfg = wl.fene_chain6(P=6000)
