@@ -280,9 +280,20 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
                                                     float *__restrict__ VA, float *__restrict__ wscale,
                                                     F16Operands f16, PicardCheck chk,
                                                     const float *__restrict__ blockmax, int nblk_chk,
-                                                    const int *done, float *__restrict__ cmean) {
+                                                    const int *done, float *__restrict__ cmean, Ctrl *begin) {
   if (chk.ctrl == nullptr) {
-    if (done != nullptr && *done) return;
+    if (begin != nullptr) {
+      // opens a queued implicit step (no other block of this launch reads
+      // the fields that block 0 clears)
+      if (begin->halted) return;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        begin->done = 0;
+        begin->conv_iter = -1;
+        begin->checked = 0;
+      }
+    } else if (done != nullptr && *done) {
+      return;
+    }
     prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16, cmean);
     return;
   }
@@ -589,14 +600,15 @@ __global__ void k_ctrl_reset(Ctrl *ctrl) {
   ctrl->fene_out = 0;
 }
 
-// End of a queued implicit step (see launch_step_end).  Only block 0 writes
-// *ctrl.  If another block sees its `halted` or `done` of this launch, the
-// step did not converge (conv_iter is still -1 then) and it returns as block
-// 0 does.
-__global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck chk, const float *__restrict__ blockmax,
-                                                        int nblk_chk, const float *__restrict__ xb0,
-                                                        const float *__restrict__ xb1, float *__restrict__ q,
-                                                        float *__restrict__ xpred, int64_t n) {
+// End of a queued implicit step (see launch_step_end), one thread per
+// particle.  Only block 0 writes *ctrl.  If another block sees its `halted` or
+// `done` of this launch, the step did not converge (conv_iter is still -1
+// then) and it returns as block 0 does.
+__global__ __launch_bounds__(kRedBlock) void k_step_end(EvalParams p, Ctrl *ctrl, PicardCheck chk,
+                                                        const float *__restrict__ blockmax, int nblk_chk,
+                                                        const float *__restrict__ xb0, const float *__restrict__ xb1,
+                                                        float *__restrict__ q, float *__restrict__ xpred,
+                                                        const float *__restrict__ w, double *__restrict__ meanp) {
   // block 0 may set `halted` and `done` during this launch: one read per
   // block keeps the block's waves together
   __shared__ int st[3];
@@ -607,11 +619,19 @@ __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck 
   }
   // the copy's loads for the tested iteration (the usual outcome) go out
   // before the test, so that their latency overlaps it
-  const int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
-  float qn = 0.f, qo = 0.f;
-  if (i < n) {
-    qn = ((chk.iter & 1) ? xb1 : xb0)[i];
-    if (xpred != nullptr) qo = q[i];
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  const bool real = I < p.P;
+  float qn[kMaxD], qo[kMaxD];
+  auto at = [&](int a) { return ((int64_t)(a / 3) * p.P + I) * 3 + a % 3; };
+  const float *src = (chk.iter & 1) ? xb1 : xb0;
+#pragma unroll
+  for (int a = 0; a < kMaxD; ++a) {
+    qn[a] = 0.f;
+    qo[a] = 0.f;
+    if (real && a < p.D) {
+      qn[a] = src[at(a)];
+      if (xpred != nullptr) qo[a] = q[at(a)];
+    }
   }
   __syncthreads();
   if (st[0]) return;
@@ -619,7 +639,12 @@ __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck 
   if (st[1]) {
     it = st[2];  // converged at an earlier test of this step
     if (it < 0) return;
-    if (i < n && ((it ^ chk.iter) & 1)) qn = ((it & 1) ? xb1 : xb0)[i];
+    if ((it ^ chk.iter) & 1) {
+      const float *alt = (it & 1) ? xb1 : xb0;
+#pragma unroll
+      for (int a = 0; a < kMaxD; ++a)
+        if (real && a < p.D) qn[a] = alt[at(a)];
+    }
   } else {
     float r;
     const bool conv = picard_converged(chk, blockmax, nblk_chk, &r);
@@ -634,10 +659,16 @@ __global__ __launch_bounds__(kRedBlock) void k_step_end(Ctrl *ctrl, PicardCheck 
     if (!conv) return;
     it = chk.iter;
   }
-  if (i < n) {
-    if (xpred != nullptr) xpred[i] = 2.f * qn - qo;
-    q[i] = qn;
+#pragma unroll
+  for (int a = 0; a < kMaxD; ++a) {
+    if (real && a < p.D) {
+      if (xpred != nullptr) xpred[at(a)] = 2.f * qn[a] - qo[a];
+      q[at(a)] = qn[a];
+    }
   }
+  // the next step's centring partials from the new state, as k_mean_partials
+  // computes them (each thread reads back what it wrote)
+  if (meanp != nullptr) mean_partials_body(p, blockIdx.x, q, w, meanp);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->steps_done += 1;
     ctrl->last_iters = it + 1;
@@ -792,11 +823,12 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 }
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
                  float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16, const int *done,
-                 hipStream_t s, const PicardCheck *chk, const float *blockmax, int nblk_chk, float *cmean) {
+                 hipStream_t s, const PicardCheck *chk, const float *blockmax, int nblk_chk, float *cmean,
+                 Ctrl *begin) {
   const F16Operands ops = f16 != nullptr ? *f16 : F16Operands{nullptr, nullptr, nullptr};
   const PicardCheck c = chk != nullptr ? *chk : PicardCheck{nullptr, 0.f, 0};
   k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, c,
-                                                    blockmax, nblk_chk, done, cmean);
+                                                    blockmax, nblk_chk, done, cmean, begin);
 }
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {
@@ -814,9 +846,10 @@ void launch_reduce_final(const double *redp, int nblk, int nslots, double *out, 
   k_reduce_final<<<1, 1024, 0, s>>>(redp, nblk, nslots, out, done);
 }
 void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s) { k_ctrl_reset<<<1, 64, 0, s>>>(ctrl); }
-void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
-                     const float *xb1, float *q, float *xpred, int64_t n, hipStream_t s) {
-  k_step_end<<<nblocks(n), kRedBlock, 0, s>>>(ctrl, chk, blockmax, nblk_chk, xb0, xb1, q, xpred, n);
+void launch_step_end(const EvalParams &p, Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk,
+                     const float *xb0, const float *xb1, float *q, float *xpred, const float *w, double *meanp,
+                     hipStream_t s) {
+  k_step_end<<<nblocks(p.P), kRedBlock, 0, s>>>(p, ctrl, chk, blockmax, nblk_chk, xb0, xb1, q, xpred, w, meanp);
 }
 void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s) {
   k_picard_check<<<1, kRedBlock, 0, s>>>(chk, blockmax, nblk_chk);

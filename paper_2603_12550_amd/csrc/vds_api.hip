@@ -446,7 +446,6 @@ vds_status finish_step(vds_ctx c, float *q, const float *w, int m0, StepCounts &
 // the rest.  The host synchronises once per kQueueSteps steps.
 vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepCounts &n, int &steps_taken) {
   const vds_problem &p = c->prob;
-  const int64_t nq = (int64_t)p.P * c->ep.D;
   const int batch = std::min(p.picard_batch, p.picard_max);
   const int *done = &c->ctrl->done;
   steps_taken = 0;
@@ -454,15 +453,18 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
     const int chunk = std::min(nsteps - steps_taken, kQueueSteps);
     launch_ctrl_reset(c->ctrl, c->stream);
     for (int j = 0; j < chunk; ++j) {
-      launch_mean_partials(c->ep, q, w, c->meanp, nullptr, c->ctrl, c->stream);
+      // the first step of the queue computes its centring partials; the step
+      // end of every other step left them behind, and its prep kernel opens
+      // the step in the control block
+      if (j == 0) launch_mean_partials(c->ep, q, w, c->meanp, nullptr, c->ctrl, c->stream);
       // with the predictor, steps after the first of the queue start from
       // the extrapolation the previous step end wrote
       const float *x0 = (p.picard_predictor && j > 0) ? c->xpred : q;
       for (int m = 0; m < batch; ++m) {
         const float *xin = (m == 0) ? x0 : c->xb[(m - 1) & 1];
         if (m == 0) {
-          launch_prep(c->ep, x0, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done,
-                      c->stream, nullptr, nullptr, 0, c->cmean);
+          launch_prep(c->ep, x0, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16,
+                      j == 0 ? done : nullptr, c->stream, nullptr, nullptr, 0, c->cmean, j > 0 ? c->ctrl : nullptr);
         } else {
           // the previous combine packed this iterate's operands; one block
           // tests the previous iteration
@@ -477,8 +479,9 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
                        c->xb[m & 1], nullptr, c->redp, c->blockmax, done, c->stream, m + 1 < batch ? &pk : nullptr,
                        fene_flag(c));
       }
-      launch_step_end(c->ctrl, PicardCheck{c->ctrl, (float)p.picard_rtol, batch - 1}, c->blockmax, c->nblk_comb,
-                      c->xb[0], c->xb[1], q, p.picard_predictor ? c->xpred : nullptr, nq, c->stream);
+      launch_step_end(c->ep, c->ctrl, PicardCheck{c->ctrl, (float)p.picard_rtol, batch - 1}, c->blockmax,
+                      c->nblk_comb, c->xb[0], c->xb[1], q, p.picard_predictor ? c->xpred : nullptr, w,
+                      j + 1 < chunk ? c->meanp : nullptr, c->stream);
     }
     Ctrl h{};
     vds_status st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream),

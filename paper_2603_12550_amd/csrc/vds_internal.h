@@ -169,11 +169,13 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 // FP16 distance operands and row norms too (f16 may be null otherwise).
 // With `chk`, the launch first tests iteration chk->iter (block maxima of
 // nblk_chk combine blocks) and does nothing once it has converged.  cmean
-// (may be null) receives the centre and weight maximum (see PackOps).
+// (may be null) receives the centre and weight maximum (see PackOps).  With
+// `begin` (and no chk), the launch opens a queued implicit step as
+// launch_mean_partials does.
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp,
                  float *xc, float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16,
                  const int *done, hipStream_t s, const PicardCheck *chk = nullptr, const float *blockmax = nullptr,
-                 int nblk_chk = 0, float *cmean = nullptr);
+                 int nblk_chk = 0, float *cmean = nullptr, Ctrl *begin = nullptr);
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 // In MODE_PICARD, q0 is the state at the start of the step (the flow term is
@@ -192,8 +194,11 @@ void launch_ctrl_reset(Ctrl *ctrl, hipStream_t s);
 // it unless an earlier test converged, then copies the converged iterate
 // (xb[conv_iter & 1]) into q and counts the step, or halts the queue.  With
 // xpred it also writes the next step's starting point 2 q^(n+1) - q^n there.
-void launch_step_end(Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk, const float *xb0,
-                     const float *xb1, float *q, float *xpred, int64_t n, hipStream_t s);
+// With meanp it also leaves the centring partials of the new q there, as
+// launch_mean_partials would.
+void launch_step_end(const EvalParams &p, Ctrl *ctrl, const PicardCheck &chk, const float *blockmax, int nblk_chk,
+                     const float *xb0, const float *xb1, float *q, float *xpred, const float *w, double *meanp,
+                     hipStream_t s);
 // Stand-alone test of iteration chk.iter, one block (queued steps after a
 // packing combine; host-driven iterations).
 void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s);
