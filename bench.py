@@ -488,7 +488,7 @@ def main():
     ap.add_argument("--learned-snapshot-runs", type=int, default=48, help="runs whose snapshots make the basis")
     ap.add_argument("--learned-run-steps", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=60)
-    ap.add_argument("--fene-learned-runs", type=int, default=32)
+    ap.add_argument("--fene-learned-runs", type=int, default=48)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

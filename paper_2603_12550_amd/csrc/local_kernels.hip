@@ -411,8 +411,9 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const fl
 // terms, the velocity, an explicit update or a fixed-point update (whose flow
 // term is taken at the step's start state qs).  With `obs` it also
 // accumulates F_h, dissipation, work and stress in FP64.  With pack.VA set
-// (fixed-point mode) it packs the new iterate's pair operands as the prep
-// kernel would: the same lanes hold the same coordinates there.
+// (fixed-point or explicit mode) it packs the new iterate's or state's pair
+// operands as the prep kernel would: the same lanes hold the same coordinates
+// there.
 __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs, const float *__restrict__ partial,
                              int splits, const float *xc, const float *__restrict__ t1,
                              const float *__restrict__ S, const float *wv, const float *qin,
@@ -474,7 +475,8 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
       if (mode == MODE_VELOCITY) {
         out[idx] = flow + u;
       } else if (mode == MODE_EXPLICIT) {
-        out[idx] = qv + p.dt * (flow + u);
+        xnew = qv + p.dt * (flow + u);
+        out[idx] = xnew;
       } else if (mode == MODE_PICARD) {
         const float xn = qstart + p.dt * (flow0 + u);
         out[idx] = xn;
@@ -483,9 +485,9 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
         xnew = xn;
       }
     }
-    if (mode == MODE_PICARD && pack.VA != nullptr) {
-      // the prep kernel's work for the new iterate: wv already holds the
-      // step's weights (zero past the particles)
+    if ((mode == MODE_PICARD || mode == MODE_EXPLICIT) && pack.VA != nullptr) {
+      // the prep kernel's work for the new iterate or state: wv already holds
+      // the weights (zero past the particles)
       const float x = comp ? xnew - pack.cmean[n] : 0.f;
       const float wi = real ? wv[I] : 0.f;
       prep_write(p, I, n, x, wi, pack.cmean, pack.xc, pack.wv, pack.QB, pack.KA, pack.VA, pack.f16);

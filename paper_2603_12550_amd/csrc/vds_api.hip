@@ -385,6 +385,27 @@ namespace {
 // Implicit steps queued on the stream between two host synchronisations.
 constexpr int kQueueSteps = 64;
 
+// Explicit steps: every kQueueSteps steps the centring partials and the pair
+// operands come from the prep kernels; in between, each step's combine kernel
+// packs the next step's operands centred where the last prep centred (the
+// sums are differences, so a centre near the particles serves).
+void explicit_steps(vds_ctx c, float *q, const float *w, int nsteps) {
+  const PackOps pk{c->xc, c->wv, c->QB, c->KA, c->VA, c->f16, c->cmean};
+  for (int s = 0; s < nsteps; ++s) {
+    if (s % kQueueSteps == 0) {
+      launch_mean_partials(c->ep, q, w, c->meanp, nullptr, nullptr, c->stream);
+      launch_prep(c->ep, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr,
+                  c->stream, nullptr, nullptr, 0, c->cmean);
+    }
+    pair_pass(c, c->VA, c->wscale, nullptr);
+    launch_finalize_a(c->ep, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
+    eval_pass_b(c, nullptr);
+    const bool pack = s + 1 < nsteps && (s + 1) % kQueueSteps != 0;
+    launch_combine(c->ep, MODE_EXPLICIT, false, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, nullptr,
+                   q, nullptr, c->redp, c->blockmax, nullptr, c->stream, pack ? &pk : nullptr, fene_flag(c));
+  }
+}
+
 struct StepCounts {
   int total_iters = 0, last_iters = 0;
   float last_resid = 0.f;
@@ -518,7 +539,7 @@ vds_status vds_step(vds_ctx c, float *q, const float *w, int32_t nsteps, vds_dia
   StepCounts n;
   if (p.scheme == VDS_EXPLICIT) {
     if (p.potential == VDS_FENE && nsteps > 0) launch_ctrl_reset(c->ctrl, c->stream);
-    for (int s = 0; s < nsteps; ++s) evaluate(c, q, w, MODE_EXPLICIT, false, nullptr, q, nullptr, nullptr);
+    explicit_steps(c, q, w, nsteps);
     if (nsteps > 0) st = fene_domain_check(c);
     if (st != VDS_OK) return st;
   } else if (nsteps > 0) {

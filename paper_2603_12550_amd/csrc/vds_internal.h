@@ -180,8 +180,9 @@ void launch_finalize_a(const EvalParams &p, const float *partial, int splits, co
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 // In MODE_PICARD, q0 is the state at the start of the step (the flow term is
 // taken there) and each block leaves its maxima of |dx| and |x| in blockmax.
-// With `pack` (MODE_PICARD), it also writes the next iterate's pair operands
-// from `out`, centred at pack->cmean (the prep kernel's work for that iterate).
+// With `pack` (MODE_PICARD or MODE_EXPLICIT), it also writes the pair operands
+// of the new iterate or state from `out`, centred at pack->cmean (the prep
+// kernel's work for it).
 // With fene_out (FENE springs), a bond of qin outside the spring's domain sets
 // *fene_out to 1.
 void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
