@@ -159,9 +159,13 @@ vds_status vds_velocity(vds_ctx ctx, const float *q_dev, const float *w_dev, flo
  * iterations queued past convergence return at once, and the host
  * synchronises once per 64 steps, plus once per picard_batch further
  * iterations for a step that needs more than picard_batch.  The iterates, and
- * so the result, do not depend on picard_batch.  On VDS_ERR_NOT_CONVERGED
- * q_dev holds the last iterate of the failing step.  `diag` (host, may be NULL) gets iteration counts, the last
- * residual and the stress after the last step. */
+ * so the result, do not depend on picard_batch.  Explicit steps do not
+ * synchronise (FENE springs: once per call, see vds_velocity); their pair
+ * operands are centred at the state of every 64th step (the sums are
+ * differences: only rounding depends on the centre).  On
+ * VDS_ERR_NOT_CONVERGED q_dev holds the last iterate of the failing step.
+ * `diag` (host, may be NULL) gets iteration counts, the last residual and the
+ * stress after the last step. */
 vds_status vds_step(vds_ctx ctx, float *q_dev, const float *w_dev, int32_t nsteps, vds_diag *diag);
 
 /* Stress tau (Section 2.1; discrete form of Appendix A), FP64 accumulation,
@@ -178,8 +182,6 @@ vds_status vds_energy(vds_ctx ctx, const float *q_dev, const float *w_dev,
 vds_status vds_density_at(vds_ctx ctx, const float *q_dev, const float *w_dev,
                           const float *y_dev, int64_t ny, float *f_dev);
 
-/* ---- per-kernel timing (HIP events on the context's stream) ------------- */
-
 /* Median-heuristic bandwidth (eq. model_bandwidth): med = the median of
  * |q_J - q_K| (configuration-space distance) over all P^2 ordered pairs, J = K
  * included (for an even count, the mean of the two middle values), and
@@ -188,6 +190,8 @@ vds_status vds_density_at(vds_ctx ctx, const float *q_dev, const float *w_dev,
  * NULL) receive the FP64 results.  Needs 2 <= P <= 2^24.  Synchronises (three passes over
  * the pairs).  The context's h is not changed: create a context with the result. */
 vds_status vds_median_bandwidth(vds_ctx ctx, const float *q_dev, double *med_host, double *h_host);
+
+/* ---- per-kernel timing (HIP events on the context's stream) ------------- */
 
 enum { VDS_TIMER_PAIR = 0, VDS_TIMER_GEMM = 1, VDS_TIMER_KGEMM = 2, VDS_TIMER_PROJ = 3, VDS_TIMER_COUNT = 4 };
 /* enable = N >= 1 starts recording an event pair around every N-th launch of
