@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 (matrix and packed vector), AMD datasheet
 LEARNED_INPUT_NOISE = 10.0  # training input noise, in increment standard deviations
-TIMING_STRIDE = 4          # event-timed pair launches: every 4th (events between kernels cost ~1 % per stride)
+TIMING_STRIDE = 5          # event-timed pair launches: every 5th, odd so that passes A and B are both sampled
 PEAK_HBM_GBS = 8000.0
 
 
