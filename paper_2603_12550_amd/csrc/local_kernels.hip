@@ -278,90 +278,21 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
                                                     int nmeanp, float *__restrict__ xc, float *__restrict__ wv,
                                                     float *__restrict__ QB, float *__restrict__ KA,
                                                     float *__restrict__ VA, float *__restrict__ wscale,
-                                                    F16Operands f16, PicardCheck chk,
-                                                    const float *__restrict__ blockmax, int nblk_chk,
-                                                    const int *done, float *__restrict__ cmean, Ctrl *begin) {
-  if (chk.ctrl == nullptr) {
-    if (begin != nullptr) {
-      // opens a queued implicit step (no other block of this launch reads
-      // the fields that block 0 clears)
-      if (begin->halted) return;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        begin->done = 0;
-        begin->conv_iter = -1;
-        begin->checked = 0;
-      }
-    } else if (done != nullptr && *done) {
-      return;
+                                                    F16Operands f16, const int *done, float *__restrict__ cmean,
+                                                    Ctrl *begin) {
+  if (begin != nullptr) {
+    // opens a queued implicit step (no other block of this launch reads the
+    // fields that block 0 clears)
+    if (begin->halted) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      begin->done = 0;
+      begin->conv_iter = -1;
+      begin->checked = 0;
     }
-    prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16, cmean);
+  } else if (done != nullptr && *done) {
     return;
   }
-  // A fixed-point iteration after the first: test the previous one first
-  // (once it has converged this kernel and every later one of the step do
-  // nothing).  Every global load the block needs (the done flag, the
-  // combine kernel's block maxima, the centring partials, the coordinate) is
-  // issued before the first barrier, so they share one memory latency.
-  __shared__ int skip, conv;
-  __shared__ float sr[kRedBlock / 64], sx[kRedBlock / 64], rr;
-  __shared__ double part[16][17];
-  __shared__ float mean_sh[16];
-  const int t = threadIdx.x;
-  // block 0 of this launch may set *done: one read per block keeps the
-  // block's waves together (a block that sees it set returns, as it would
-  // after the test below)
-  if (t == 0) skip = *done;
-  const int nt = strided_count(t, nblk_chk, kRedBlock);
-  float r = strided_max(blockmax + 2 * t, nt, 2 * kRedBlock, 0.f);
-  float x = strided_max(blockmax + 2 * t + 1, nt, 2 * kRedBlock, 0.f);
-  const int c = t & 15, j = t >> 4;
-  double mv = 0.0;
-  const int nj = strided_count(j, nmeanp, 16);
-  if (c == 15) mv = strided_max(meanp + (int64_t)j * 16 + 15, nj, 256, 0.0);
-  else if (c < p.D) mv = ordered_sum<double>(meanp + (int64_t)j * 16 + c, nj, 256);
-  const int64_t I = group_particle(blockIdx.x);
-  const int n = group_lane();
-  const float xr = I < p.Ppad ? prep_coord(p, q, I, n) : 0.f;
-  const float wi = I < p.P ? load_weight(w, I, p.uniform_w) : 0.f;
-  for (int off = 32; off > 0; off >>= 1) {
-    r = fmaxf(r, __shfl_xor(r, off));
-    x = fmaxf(x, __shfl_xor(x, off));
-  }
-  if ((t & 63) == 0) {
-    sr[t >> 6] = r;
-    sx[t >> 6] = x;
-  }
-  part[c][j] = mv;
-  __syncthreads();
-  if (skip) return;
-  if (t == 0) {
-    for (int i = 1; i < kRedBlock / 64; ++i) {
-      r = fmaxf(r, sr[i]);
-      x = fmaxf(x, sx[i]);
-    }
-    rr = r;
-    conv = r <= chk.rtol * fmaxf(1.f, x) ? 1 : 0;
-  }
-  if (t < 16 && (t < p.D || t == 15)) {  // the same fixed order as load_mean
-    double m = 0.0;
-    for (int i = 0; i < 16; ++i) m = t == 15 ? fmax(m, part[t][i]) : m + part[t][i];
-    mean_sh[t] = (float)m;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && t == 0) {
-    chk.ctrl->last_resid = rr;
-    chk.ctrl->checked = chk.iter + 1;
-    if (conv) {
-      chk.ctrl->conv_iter = chk.iter;
-      chk.ctrl->done = 1;
-    }
-  }
-  if (conv) return;
-  if (p.vhalf && wscale != nullptr && blockIdx.x == 0 && t == 0) *wscale = mean_sh[15];
-  if (cmean != nullptr && blockIdx.x == 0 && t < 16) cmean[t] = mean_sh[t];
-  if (I >= p.Ppad) return;
-  const float xc_n = I < p.P && n < p.D ? xr - mean_sh[n] : 0.f;
-  prep_write(p, I, n, xc_n, wi, mean_sh, xc, wv, QB, KA, VA, f16);
+  prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16, cmean);
 }
 
 // Component n of row I summed over the column splits in split order, in FP64.
@@ -825,12 +756,10 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 }
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp, float *xc,
                  float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16, const int *done,
-                 hipStream_t s, const PicardCheck *chk, const float *blockmax, int nblk_chk, float *cmean,
-                 Ctrl *begin) {
+                 hipStream_t s, float *cmean, Ctrl *begin) {
   const F16Operands ops = f16 != nullptr ? *f16 : F16Operands{nullptr, nullptr, nullptr};
-  const PicardCheck c = chk != nullptr ? *chk : PicardCheck{nullptr, 0.f, 0};
-  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, c,
-                                                    blockmax, nblk_chk, done, cmean, begin);
+  k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, done,
+                                                    cmean, begin);
 }
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {

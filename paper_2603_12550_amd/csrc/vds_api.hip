@@ -72,11 +72,10 @@ void apply_tuning(vds_ctx c, const vds_tuning &t) {
   c->ep.qhalf = t.impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
 }
 
-void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre, const PicardCheck *chk) {
+void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre) {
   const EvalParams &e = c->ep;
   if (centre) launch_mean_partials(e, q, w, c->meanp, done, nullptr, c->stream);
-  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done, c->stream,
-              chk, c->blockmax, c->nblk_comb);
+  launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done, c->stream);
   pair_pass(c, c->VA, c->wscale, done);
   launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
 }
@@ -203,11 +202,10 @@ void drain_timers(vds_ctx c) {
 // centring partials already in the workspace are used (the fixed-point
 // iterations of a step all centre at the step's start state: the sums are
 // differences, so any centre near the particles gives the same result).
-// `chk` (fixed-point mode) makes the prep kernel test the previous iteration.
 void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, const float *q0, float *out,
-              float *out2, const int *done, const PicardCheck *chk = nullptr, bool centre = true) {
+              float *out2, const int *done, bool centre = true) {
   const EvalParams &e = c->ep;
-  eval_pass_a(c, q, w, done, centre, chk);
+  eval_pass_a(c, q, w, done, centre);
   eval_pass_b(c, done);
   launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, q0, out, out2, c->redp,
                  c->blockmax, done, c->stream, nullptr, fene_flag(c));
@@ -395,7 +393,7 @@ void explicit_steps(vds_ctx c, float *q, const float *w, int nsteps) {
     if (s % kQueueSteps == 0) {
       launch_mean_partials(c->ep, q, w, c->meanp, nullptr, nullptr, c->stream);
       launch_prep(c->ep, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr,
-                  c->stream, nullptr, nullptr, 0, c->cmean);
+                  c->stream, c->cmean);
     }
     pair_pass(c, c->VA, c->wscale, nullptr);
     launch_finalize_a(c->ep, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
@@ -429,7 +427,7 @@ vds_status finish_step(vds_ctx c, float *q, const float *w, int m0, StepCounts &
     const int batch = std::min(p.picard_batch, p.picard_max - m);
     for (int b = 0; b < batch; ++b, ++m) {
       const float *xin = (m == 0) ? q : c->xb[(m - 1) & 1];
-      evaluate(c, xin, w, MODE_PICARD, false, q, c->xb[m & 1], nullptr, done, nullptr, false);
+      evaluate(c, xin, w, MODE_PICARD, false, q, c->xb[m & 1], nullptr, done, false);
       launch_picard_check(PicardCheck{c->ctrl, (float)p.picard_rtol, m}, c->blockmax, c->nblk_comb, c->stream);
     }
     vds_status st = hip_check(c, hipMemcpyAsync(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream),
@@ -485,7 +483,7 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
         const float *xin = (m == 0) ? x0 : c->xb[(m - 1) & 1];
         if (m == 0) {
           launch_prep(c->ep, x0, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16,
-                      j == 0 ? done : nullptr, c->stream, nullptr, nullptr, 0, c->cmean, j > 0 ? c->ctrl : nullptr);
+                      j == 0 ? done : nullptr, c->stream, c->cmean, j > 0 ? c->ctrl : nullptr);
         } else {
           // the previous combine packed this iterate's operands; one block
           // tests the previous iteration

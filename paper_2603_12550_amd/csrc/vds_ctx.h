@@ -75,8 +75,7 @@ void timed(vds_ctx c, int which, double work, F &&fn) {
 // Centring, operand packing and pass A at the state q (weights w or uniform):
 // leaves S, term1 and the pass-B operand in the workspace.  Without `centre`
 // the centring partials already in the workspace are reused.
-void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre = true,
-                 const PicardCheck *chk = nullptr);
+void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre = true);
 // Pass B with the operand eval_pass_a left; partial sums stay in c->part.
 void eval_pass_b(vds_ctx c, const int *done);
 

@@ -167,15 +167,12 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 // With p.vhalf, VA is written as FP16 halves (see pair_kernels.hip) with the
 // weights divided by their maximum, which goes to *wscale; with p.qhalf the
 // FP16 distance operands and row norms too (f16 may be null otherwise).
-// With `chk`, the launch first tests iteration chk->iter (block maxima of
-// nblk_chk combine blocks) and does nothing once it has converged.  cmean
-// (may be null) receives the centre and weight maximum (see PackOps).  With
-// `begin` (and no chk), the launch opens a queued implicit step as
-// launch_mean_partials does.
+// cmean (may be null) receives the centre and weight maximum (see PackOps).
+// With `begin`, the launch opens a queued implicit step as
+// launch_mean_partials does (and ignores `done`).
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp,
                  float *xc, float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16,
-                 const int *done, hipStream_t s, const PicardCheck *chk = nullptr, const float *blockmax = nullptr,
-                 int nblk_chk = 0, float *cmean = nullptr, Ctrl *begin = nullptr);
+                 const int *done, hipStream_t s, float *cmean = nullptr, Ctrl *begin = nullptr);
 void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 // In MODE_PICARD, q0 is the state at the start of the step (the flow term is
