@@ -325,6 +325,29 @@ def test_implicit_dumbbell_trajectory_and_stress(lib, tuning):
 
 
 @pytest.mark.parametrize("tuning", IMPLS)
+def test_explicit_steps_across_recentring_match_oracle(lib, tuning):
+    # 150 explicit steps in one call: the prep kernels centre and pack at
+    # steps 0, 64 and 128, the combine kernels pack in between; a strong shear
+    # moves the state away from where it was centred
+    cfg = wl.chain4_shear(P=400, seed=13)
+    prob = ovds.problem_from(cfg)
+    prob.G = 5.0 * prob.G
+    P = cfg["P"]
+    w32 = wl.to_f32(wl.random_weights(9, P))
+    q32 = wl.to_f32(cfg["q0"])
+    qo, wo = wl.f32_as_f64(q32), wl.f32_as_f64(w32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=prob.G, dt=cfg["dt"], scheme="explicit")
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
+    _say(f"150 explicit steps chain4 P=400 tuning {tuning}")
+    ctx.step(qg, w=_dev(w32), nsteps=150)
+    for _ in range(150):
+        qo = ovds.step_explicit(qo, wo, prob)
+    assert _rel(qg.cpu().numpy(), qo) < 1e-5
+
+
+@pytest.mark.parametrize("tuning", IMPLS)
 def test_explicit_steps_match_oracle_fene(lib, tuning):
     cfg = wl.fene_chain6(P=700)
     prob = ovds.problem_from(cfg)
