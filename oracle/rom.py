@@ -106,20 +106,34 @@ def reduced_rhs(p: np.ndarray, XH: np.ndarray, XB: np.ndarray, prob: vds.Problem
 
 
 def rom_run(U: np.ndarray, q0: np.ndarray, w: np.ndarray, prob: vds.Problem, steps: int,
-            freeze_every: int, callback=None):
+            freeze_every: int, callback=None, midpoint: bool = False):
     """Reduced explicit Euler from p(0) = U^T q(0) with the freeze schedule
-    above.  `callback(step, p)` sees every reduced state.  Returns p(steps)."""
+    above.  `callback(step, p)` sees every reduced state.  Returns p(steps).
+
+    With `midpoint` (an addition, not in the paper) the operators of a window
+    of n steps are rebuilt at the state predicted for its midpoint: n // 2
+    steps from the window's start with the start's operators (none when
+    n = 1), then the window is taken from its start with the new operators."""
     if prob.potential != "hookean":
         raise ValueError("the reduced spring term is exact only for Hookean springs")
     nb, P, d = q0.shape
     p = pod.project(U, q0)
     XH = hydro(U, prob.G, P, d)
+
+    def operators_at(pp):
+        XB1, XB2 = brownian(U, pod.reconstruct(U, pp, P, d), w, prob.h)
+        return XB1 + XB2
+
     XB = None
     for s in range(steps):
         if s % freeze_every == 0:
-            qt = pod.reconstruct(U, p, P, d)
-            XB1, XB2 = brownian(U, qt, w, prob.h)
-            XB = XB1 + XB2
+            XB = operators_at(p)
+            half = min(freeze_every, steps - s) // 2
+            if midpoint and half > 0:
+                pm = p
+                for _ in range(half):
+                    pm = pm + prob.dt * reduced_rhs(pm, XH, XB, prob)
+                XB = operators_at(pm)
         p = p + prob.dt * reduced_rhs(p, XH, XB, prob)
         if callback is not None:
             callback(s + 1, p)

@@ -196,3 +196,24 @@ def test_training_reduces_loss():
         _, g = mlp.backward(layers, X, Y)
         layers, m, v = mlp.adam_step(layers, g, m, v, t, lr=3e-3)
     assert mlp.loss(layers, X, Y) < 0.2 * L0
+
+
+def test_midpoint_freeze_is_second_order_in_the_window():
+    # differences between runs with windows M and M/2 (the time step fixed):
+    # they halve with M for operators frozen at the window's start (first
+    # order) and quarter for operators at the predicted midpoint (second order)
+    q, prob = _small_case(P=14)
+    P = q.shape[1]
+    U, _ = np.linalg.qr(np.random.default_rng(21).standard_normal((3 * P, 10)))
+    w = vds.uniform_weights(P)
+    steps = 128
+    runs = {(mid, M): rom.rom_run(U, q, w, prob, steps, freeze_every=M, midpoint=mid)
+            for mid in (False, True) for M in (8, 16, 32, 64)}
+    scale = np.linalg.norm(runs[(False, 8)])
+    for mid, lo, hi in ((False, 1.8, 2.3), (True, 3.6, 4.6)):
+        d = [np.linalg.norm(runs[(mid, M)] - runs[(mid, M // 2)]) / scale for M in (16, 32, 64)]
+        assert lo < d[1] / d[0] < hi and lo < d[2] / d[1] < hi, (mid, d)
+    # a window of one step has no midpoint to predict: the two schedules agree
+    a = rom.rom_run(U, q, w, prob, 10, freeze_every=1)
+    b = rom.rom_run(U, q, w, prob, 10, freeze_every=1, midpoint=True)
+    assert np.array_equal(a, b)
