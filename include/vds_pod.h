@@ -80,6 +80,16 @@ vds_status vds_rom_operators(vds_rom rom, const float *p_dev, float *XH_dev, flo
  * evaluated from p and the M_ab (no reconstruction).  Synchronises. */
 vds_status vds_rom_run(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every, double *tau_host);
 
+/* As vds_rom_run, with the operators of each window (n steps) rebuilt at the
+ * state predicted for its midpoint (not in the paper): after the freeze at the
+ * window's start, n / 2 steps from there give q~ for a second freeze, and the
+ * window then runs from its start with those operators (a window of one step
+ * has no midpoint and keeps the start's).  The freeze error of a window falls
+ * from first to second order in its length, at two freezes and 1.5 n steps
+ * per window.  Synchronises. */
+vds_status vds_rom_run_midpoint(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every,
+                                double *tau_host);
+
 /* Stress of q~ = U p from p_dev and the M_ab: tau_ab = (n/P) sum_j H_j p_j^T M_ab p_j. */
 vds_status vds_rom_stress(vds_rom rom, const float *p_dev, double *tau_host);
 

@@ -87,6 +87,7 @@ _sigs.update({
     "vds_rom_destroy": ([_P], None),
     "vds_rom_operators": ([_P, _P, _P, _P, _P], C.c_int),
     "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "vds_rom_run_midpoint": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_stress": ([_P, _P, C.POINTER(C.c_double)], C.c_int),
 })
 
@@ -351,9 +352,12 @@ class Rom:
         _check(_lib.vds_rom_operators(self.rom, _ptr(p), _ptr(XH), _ptr(XB1), _ptr(XB2)), self.ctx.ctx)
         return XH, XB1, XB2
 
-    def run(self, p, nsteps, freeze_every):
+    def run(self, p, nsteps, freeze_every, midpoint=False):
+        """Reduced explicit Euler steps; with `midpoint` the operators of each
+        window come from its predicted midpoint (vds_rom_run_midpoint)."""
         tau = (C.c_double * 9)()
-        _check(_lib.vds_rom_run(self.rom, _ptr(p), int(nsteps), int(freeze_every), tau), self.ctx.ctx)
+        fn = _lib.vds_rom_run_midpoint if midpoint else _lib.vds_rom_run
+        _check(fn(self.rom, _ptr(p), int(nsteps), int(freeze_every), tau), self.ctx.ctx)
         return np.array(tau[:]).reshape(3, 3)
 
     def stress(self, p):

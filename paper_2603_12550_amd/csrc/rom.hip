@@ -26,7 +26,7 @@ constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the ke
 constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
 
 struct RomLayout {
-  size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, total;
+  size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, total;
   int NB16;
   int64_t ldy;
 };
@@ -61,6 +61,7 @@ RomLayout rom_layout(const vds_problem &p, int R) {
                                 sizeof(float) * (size_t)m * p.nb});
   L.part = take(part);
   L.red = take(sizeof(double) * 16);
+  L.psave = take(sizeof(float) * (size_t)p.nb * R);
   L.total = off;
   return L;
 }
@@ -717,7 +718,7 @@ struct vds_rom_s {
   int R = 0;
   RomLayout L{};
   char *ws = nullptr;
-  float *Ude, *Mbig, *XH, *I1, *XB1, *XB2, *XB, *Bsw, *Y, *qt, *T, *invS, *part;
+  float *Ude, *Mbig, *XH, *I1, *XB1, *XB2, *XB, *Bsw, *Y, *qt, *T, *invS, *part, *psave;
   double *red;
 };
 
@@ -893,6 +894,7 @@ vds_status vds_rom_create(vds_ctx c, const float *U, int32_t R, void *ws, size_t
   r->invS = f(L.invS);
   r->part = f(L.part);
   r->red = reinterpret_cast<double *>(r->ws + L.red);
+  r->psave = f(L.psave);
   const int64_t P = c->prob.P;
   hipStream_t s = c->stream;
   k_deinterleave<<<nblk256(3 * (int64_t)R * P), 256, 0, s>>>(U, P, R, r->Ude);
@@ -1076,30 +1078,66 @@ vds_status vds_rom_run_exact(vds_rom r, float *p, int32_t nsteps, int32_t freeze
   return hip_check(c, hipStreamSynchronize(s), "synchronise");
 }
 
-vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
-  if (r == nullptr) return VDS_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// n reduced explicit Euler steps of p with the current operators (one launch).
+void rom_steps(vds_rom r, float *p, int n) {
   vds_ctx c = r->ctx;
-  if (!p || nsteps < 0 || freeze_every < 1) return set_err(c, VDS_ERR_ARG, "bad arguments");
+  const int nb = c->prob.nb, R = r->R;
+  if (R <= 32)
+    launch_steps_reg<16>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
+  else if (R <= 64)
+    launch_steps_reg<32>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
+  else if (R <= 128)
+    launch_steps_reg<64>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
+  else if (R <= 192)
+    launch_steps_reg<96>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
+  else
+    k_rom_steps<<<1, 1024, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
+}
+
+// The windows of vds_rom_run / vds_rom_run_midpoint.
+vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, bool midpoint, double *tau) {
+  vds_ctx c = r->ctx;
+  const size_t pbytes = sizeof(float) * (size_t)c->prob.nb * r->R;
   for (int s0 = 0; s0 < nsteps; s0 += freeze_every) {
+    const int n = std::min(freeze_every, nsteps - s0), half = n / 2;
     vds_status st = freeze(r, p);
     if (st != VDS_OK) return st;
-    const int n = std::min(freeze_every, nsteps - s0);
-    const int nb = c->prob.nb, R = r->R;
-    if (R <= 32)
-      launch_steps_reg<16>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
-    else if (R <= 64)
-      launch_steps_reg<32>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
-    else if (R <= 128)
-      launch_steps_reg<64>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
-    else if (R <= 192)
-      launch_steps_reg<96>(nb, r->XH, r->XB, p, R, n, c->ep, c->stream);
-    else
-      k_rom_steps<<<1, 1024, 0, c->stream>>>(r->XH, r->XB, p, nb, R, n, c->ep);
+    if (midpoint && half > 0) {
+      // operators at the state half a window on, predicted with the start's
+      st = hip_check(c, hipMemcpyAsync(r->psave, p, pbytes, hipMemcpyDeviceToDevice, c->stream), "copy");
+      if (st != VDS_OK) return st;
+      rom_steps(r, p, half);
+      st = freeze(r, p);
+      if (st == VDS_OK)
+        st = hip_check(c, hipMemcpyAsync(p, r->psave, pbytes, hipMemcpyDeviceToDevice, c->stream), "copy");
+      if (st != VDS_OK) return st;
+    }
+    rom_steps(r, p, n);
   }
   vds_status st = hip_check(c, hipGetLastError(), "reduced steps");
   if (st != VDS_OK) return st;
   if (tau) return vds_rom_stress(r, p, tau);
   return hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
+}
+
+}  // namespace
+
+extern "C" {
+
+vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  if (!p || nsteps < 0 || freeze_every < 1) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
+  return rom_windows(r, p, nsteps, freeze_every, false, tau);
+}
+
+vds_status vds_rom_run_midpoint(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  if (!p || nsteps < 0 || freeze_every < 1) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
+  return rom_windows(r, p, nsteps, freeze_every, true, tau);
 }
 
 }  // extern "C"

@@ -186,6 +186,30 @@ def test_rom_run_small_vs_oracle(lib, tuning, R):
     assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
+@pytest.mark.parametrize("R", [12, 140, 250])
+@pytest.mark.parametrize("steps,every", [(30, 10), (23, 9)])
+def test_rom_run_midpoint_small_vs_oracle(lib, R, steps, every):
+    # operators at each window's predicted midpoint (vds_rom_run_midpoint)
+    # against the oracle's schedule; 23 steps in windows of 9 end with a
+    # window of 5 (a midpoint 2 steps in)
+    P = 300
+    U32, Uf, p32, prob = _small_rom_case(P, R, seed=7)
+    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    _say(f"reduced run with midpoint freezes P=300 R={R} {steps}/{every}")
+    rom = lib.Rom(ctx, _dev(U32))
+    p = _dev(p32)
+    tau = rom.run(p, nsteps=steps, freeze_every=every, midpoint=True)
+    q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    w = ovds.uniform_weights(P)
+    p_o = orom.rom_run(Uf, q0, w, prob, steps, every, midpoint=True)
+    assert _rel(_np(p), p_o) < 1e-4
+    tau_o = orom.reduced_stress(Uf, p_o, w, prob, P)
+    assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
+    # and it is not the start-freeze schedule
+    p_s = orom.rom_run(Uf, q0, w, prob, steps, every)
+    assert _rel(p_o, p_s) > 10 * _rel(_np(p), p_o)
+
+
 @pytest.mark.parametrize("tuning", TUNINGS)
 def test_full_rank_rom_equals_full_explicit_scheme(lib, tuning):
     # R = P d with an orthogonal U and a freeze every step: the reduced model is the
