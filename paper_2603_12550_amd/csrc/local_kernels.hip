@@ -1,6 +1,7 @@
 // O(P D) kernels around the pair passes: centring and operand packing, the
-// two finalisations (term1 and the pass-B weights; term2, drift and update),
-// the implicit-iteration control, and FP64 reductions of stress, energy,
+// two finalisations (term1 and the pass-B weights; term2, drift and update,
+// with the packing of the next state's operands), the implicit-iteration
+// control, the FENE domain flag, and FP64 reductions of stress, energy,
 // dissipation and work.  All reductions are two-stage (per-block partials in
 // a fixed tree, then a fixed-order sum), so results are bitwise reproducible.
 #include "vds_internal.h"

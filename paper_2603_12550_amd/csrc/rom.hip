@@ -4,7 +4,8 @@
 // S = Z w and T = Z (w/S), form Y = Z [w U_a | (w/S) U_a]_a with the kernel
 // matrix generated tile by tile on MFMA (never stored), then contract with the
 // mode blocks into X^B1 and X^B2.  Between freezes a single workgroup takes the
-// explicit Euler steps of the reduced equation.
+// explicit Euler steps of the reduced equation.  Midpoint freezes add a second
+// freeze per window, at the state half a window on.
 #include <algorithm>
 #include <cmath>
 #include <new>

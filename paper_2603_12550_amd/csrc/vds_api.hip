@@ -1,5 +1,6 @@
 // C ABI of the particle scheme: context, workspace binding, evaluation
-// sequences, the implicit iteration loop, observables and kernel timing.
+// sequences, the queued explicit and implicit steps, the FENE domain check,
+// observables and kernel timing.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
