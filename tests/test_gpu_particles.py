@@ -223,8 +223,9 @@ def test_implicit_steps_match_oracle_trajectory(lib, tuning):
 
 def test_queued_implicit_steps_match_oracle(lib):
     # several implicit steps in one call run queued on the device (the
-    # convergence test in the combine kernel, the write-back in a step-end
-    # kernel); the trajectory still follows the oracle step by step
+    # convergence test in a one-block kernel between iterations, the
+    # write-back in a step-end kernel); the trajectory still follows the
+    # oracle step by step
     cfg = wl.chain4_shear(P=1500, seed=21)
     prob = ovds.problem_from(cfg)
     P = cfg["P"]
@@ -244,6 +245,28 @@ def test_queued_implicit_steps_match_oracle(lib):
     # the device stops at rtol 1e-6, the oracle at 1e-13: the device never
     # takes more iterations
     assert 6 <= d["iters"] <= iters
+
+
+@pytest.mark.parametrize("predictor", [0, 1])
+def test_queued_implicit_steps_across_queues_match_oracle(lib, predictor):
+    # 140 steps in one call cross two queue boundaries (64 steps each): the
+    # first step of a queue centres with its own mean kernel, the others with
+    # the partials the previous step end left; random weights
+    cfg = wl.chain4_shear(P=200, seed=23)
+    prob = ovds.problem_from(cfg)
+    P = cfg["P"]
+    w32 = wl.to_f32(wl.random_weights(11, P))
+    q32 = wl.to_f32(cfg["q0"])
+    qo, wo = wl.f32_as_f64(q32), wl.f32_as_f64(w32)
+    qg = _dev(q32)
+    ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit",
+               picard_predictor=predictor)
+    _say(f"140 queued implicit steps chain4 P=200 predictor {predictor}")
+    d = ctx.step(qg, w=_dev(w32), nsteps=140)
+    for _ in range(140):
+        qo, _ = ovds.step_implicit(qo, wo, prob)
+    assert d["steps"] == 140
+    assert _rel(qg.cpu().numpy(), qo) < 1e-5
 
 
 def test_implicit_predictor_same_fixed_point_fewer_iterations(lib):
