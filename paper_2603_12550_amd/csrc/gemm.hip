@@ -11,13 +11,17 @@ namespace vds {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;   // output tile edge per workgroup
-constexpr int GK = 16;   // k-depth staged per LDS round
+constexpr int GK = 32;   // k-depth staged per LDS round
+constexpr int GE = GT * GK / 256;  // slab elements per thread and operand
 
 // One workgroup: a 64x64 output tile over the k range of split blockIdx.z.
 // Wave w owns the 32x32 quadrant (w / 2, w % 2) as 2x2 blocks of 16x16.
 // A_MN: A element (i, k) of batch b at A[b*sA + k*lda + i] (else at i*lda + k).
 // B_MN: B element (j, k) at B[b*sB + k*ldb + j] (else at j*ldb + k).
 // scale: optional per-k factor (batch stride sS) applied to B.
+// The next 64 x 32 slabs of A and B are loaded into registers while the
+// matrix cores work on the current ones in LDS; the products are summed in k
+// order, 4 at a time.
 template <bool A_MN, bool B_MN>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int64_t K, int nbatch, const float *__restrict__ A,
                                               int64_t lda, int64_t sA, const float *__restrict__ B, int64_t ldb,
@@ -36,35 +40,46 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int64_t K, int nbatc
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // slab element e of this thread sits at row r0 + dr e, k offset k0 + dk e:
+  // rows fastest in the MN layouts, k fastest otherwise, so that a wave's
+  // loads are contiguous
+  const int ar0 = A_MN ? (tid & 63) : (tid >> 5), ak0 = A_MN ? (tid >> 6) : (tid & 31);
+  const int br0 = B_MN ? (tid & 63) : (tid >> 5), bk0 = B_MN ? (tid >> 6) : (tid & 31);
+  constexpr int adr = A_MN ? 0 : 8, adk = A_MN ? 4 : 0, bdr = B_MN ? 0 : 8, bdk = B_MN ? 4 : 0;
+  // element strides in memory: between a thread's elements, and per slab
+  const int64_t a_step = A_MN ? 4 * lda : 8 * lda, a_slab = A_MN ? (int64_t)GK * lda : GK;
+  const int64_t b_step = B_MN ? 4 * ldb : 8 * ldb, b_slab = B_MN ? (int64_t)GK * ldb : GK;
 
   for (int bt = 0; bt < nbatch; ++bt) {
-    const float *Ab = A + bt * sA;
-    const float *Bb = B + bt * sB;
     const float *Sb = scale ? scale + bt * sS : nullptr;
-    for (int64_t k0 = kb; k0 < ke; k0 += GK) {
-      // stage a 64 x 16 slab of A and of B (4 elements per thread each)
+    // element 0 of this thread in the slab at k = kb
+    const float *pa = A + bt * sA + (A_MN ? (kb + ak0) * lda + (i0 + ar0) : (int64_t)(i0 + ar0) * lda + kb + ak0);
+    const float *pb = B + bt * sB + (B_MN ? (kb + bk0) * ldb + (j0 + br0) : (int64_t)(j0 + br0) * ldb + kb + bk0);
+    float ra[GE], rb[GE];
+    auto load = [&](int64_t k0) {
+      const float *qa = pa, *qb = pb;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int idx = tid + 256 * e;  // 0..1023
-        int r, kk;
-        if (A_MN) { r = idx & 63; kk = idx >> 6; } else { r = idx >> 4; kk = idx & 15; }
-        const int64_t k = k0 + kk;
-        const int i = i0 + r;
-        float v = 0.f;
-        if (i < M && k < ke) v = A_MN ? Ab[k * lda + i] : Ab[(int64_t)i * lda + k];
-        sAt[r][kk] = v;
-        int rb, kb2;
-        if (B_MN) { rb = idx & 63; kb2 = idx >> 6; } else { rb = idx >> 4; kb2 = idx & 15; }
-        const int64_t kB = k0 + kb2;
-        const int j = j0 + rb;
-        float u = 0.f;
-        if (j < N && kB < ke) {
-          u = B_MN ? Bb[kB * ldb + j] : Bb[(int64_t)j * ldb + kB];
-          if (Sb) u *= Sb[kB];
-        }
-        sBt[rb][kb2] = u;
+      for (int e = 0; e < GE; ++e) {
+        const bool va = i0 + ar0 + adr * e < M && k0 + ak0 + adk * e < ke;
+        ra[e] = va ? *qa : 0.f;
+        qa += a_step;
+        const int64_t kB = k0 + bk0 + bdk * e;
+        const bool vb = j0 + br0 + bdr * e < N && kB < ke;
+        rb[e] = vb ? *qb * (Sb ? Sb[kB] : 1.f) : 0.f;
+        qb += b_step;
+      }
+      pa += a_slab;
+      pb += b_slab;
+    };
+    if (kb < ke) load(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+      for (int e = 0; e < GE; ++e) {
+        sAt[ar0 + adr * e][ak0 + adk * e] = ra[e];
+        sBt[br0 + bdr * e][bk0 + bdk * e] = rb[e];
       }
       __syncthreads();
+      if (k0 + GK < ke) load(k0 + GK);
 #pragma unroll
       for (int ks = 0; ks < GK; ks += 4) {
         float av[2], bv[2];
@@ -111,7 +126,9 @@ size_t gemm_part_bytes(const GemmShape &g) {
 }
 
 void launch_gemm(const GemmShape &g, float *part, hipStream_t s) {
-  const int64_t kps = round_up((g.K + g.splits - 1) / g.splits, GK);
+  // split ranges start at multiples of 16 (the products are summed in groups
+  // of 4 from each split's start)
+  const int64_t kps = round_up((g.K + g.splits - 1) / g.splits, 16);
   dim3 grid((unsigned)((g.M + GT - 1) / GT), (unsigned)((g.N + GT - 1) / GT), (unsigned)g.splits);
   if (!g.a_mn && !g.b_mn)
     k_gemm<false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, part);
