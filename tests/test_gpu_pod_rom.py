@@ -210,6 +210,30 @@ def test_rom_run_midpoint_small_vs_oracle(lib, R, steps, every):
     assert _rel(p_o, p_s) > 10 * _rel(_np(p), p_o)
 
 
+def test_rom_run_midpoint_edge_cases(lib):
+    # windows of one step have no midpoint (the start-freeze run, bit for
+    # bit); a window longer than the run is one window; zero steps change
+    # nothing; a zero interval is rejected
+    P, R = 300, 12
+    U32, Uf, p32, prob = _small_rom_case(P, R, seed=8)
+    ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    rom = lib.Rom(ctx, _dev(U32))
+    a, b = _dev(p32), _dev(p32)
+    rom.run(a, nsteps=12, freeze_every=1)
+    rom.run(b, nsteps=12, freeze_every=1, midpoint=True)
+    assert bool((a == b).all().item())
+    c = _dev(p32)
+    rom.run(c, nsteps=12, freeze_every=40, midpoint=True)
+    q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    p_o = orom.rom_run(Uf, q0, ovds.uniform_weights(P), prob, 12, 40, midpoint=True)
+    assert _rel(_np(c), p_o) < 1e-4
+    d = _dev(p32)
+    rom.run(d, nsteps=0, freeze_every=5, midpoint=True)
+    assert bool((d == _dev(p32)).all().item())
+    with pytest.raises(lib.VDSError):
+        rom.run(d, nsteps=4, freeze_every=0, midpoint=True)
+
+
 @pytest.mark.parametrize("tuning", TUNINGS)
 def test_full_rank_rom_equals_full_explicit_scheme(lib, tuning):
     # R = P d with an orthogonal U and a freeze every step: the reduced model is the
