@@ -512,3 +512,25 @@ def test_median_bandwidth_rejects_one_particle(lib):
     with pytest.raises(lib.VDSError) as ei:
         ctx.median_bandwidth(_dev(np.zeros((1, 1, 3))))
     assert ei.value.status == lib._vds.VDS_ERR_ARG
+
+
+def test_pair_timer_samples_every_stride_th_launch(lib):
+    # the bench's roofline comes from these timers: 12 explicit steps are 24
+    # pair launches; stride 1 times all of them, stride 5 launches 0, 5, ...,
+    # 20; the work counts the P^2 pair-evaluations of each timed launch
+    from paper_2603_12550_amd import _vds
+    cfg = wl.chain4_shear(P=2000, seed=3)
+    P = cfg["P"]
+    ctx = _ctx(lib, 3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="explicit")
+    q = _dev(cfg["q0"])
+    for stride, timed in ((1, 24), (5, 5)):
+        ctx.timing_enable(True, stride=stride)
+        ctx.step(q, nsteps=12)
+        t = ctx.timing_read(_vds.VDS_TIMER_PAIR)
+        assert t["launches"] == timed
+        assert t["work"] == pytest.approx(timed * float(P) * P)
+        assert t["ms"] > 0
+    ctx.timing_enable(False)
+    ctx.step(q, nsteps=2)
+    t = ctx.timing_read(_vds.VDS_TIMER_PAIR)
+    assert t["launches"] == 0
