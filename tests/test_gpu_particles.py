@@ -534,3 +534,29 @@ def test_pair_timer_samples_every_stride_th_launch(lib):
     ctx.step(q, nsteps=2)
     t = ctx.timing_read(_vds.VDS_TIMER_PAIR)
     assert t["launches"] == 0
+
+
+@pytest.mark.parametrize("scheme", ["explicit", "implicit"])
+def test_step_counts_at_the_boundary(lib, scheme):
+    # zero steps change nothing (and evaluate nothing: even a FENE state
+    # outside the domain passes), a negative count is rejected, one step
+    # matches the oracle
+    cfg = wl.fene_chain6(P=200)
+    P = cfg["P"]
+    prob = ovds.problem_from(cfg)
+    ctx = _ctx(lib, 5, P, cfg["h"], G=cfg["G"], dt=cfg["dt"], scheme=scheme, potential="fene",
+               b_max=cfg["b_max"])
+    bad = wl.to_f32(cfg["q0"]).copy()
+    bad[1, 3] = [7.0, 1.0, 1.0]
+    qb = _dev(bad)
+    ctx.step(qb, nsteps=0)
+    assert np.array_equal(qb.cpu().numpy(), bad)
+    with pytest.raises(lib.VDSError):
+        ctx.step(qb, nsteps=-1)
+    q32 = wl.to_f32(cfg["q0"])
+    qg = _dev(q32)
+    ctx.step(qg, nsteps=1)
+    qo = wl.f32_as_f64(q32)
+    qo = ovds.step_explicit(qo, ovds.uniform_weights(P), prob) if scheme == "explicit" else \
+        ovds.step_implicit(qo, ovds.uniform_weights(P), prob)[0]
+    assert _rel(qg.cpu().numpy(), qo) < 1e-5
