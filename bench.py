@@ -505,7 +505,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the particle rows would shard by block with an all-gather of S between passes).",
               file=sys.stderr)
         sys.exit(2)
