@@ -26,7 +26,9 @@ template <bool A_MN, bool B_MN>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int64_t K, int nbatch, const float *__restrict__ A,
                                               int64_t lda, int64_t sA, const float *__restrict__ B, int64_t ldb,
                                               int64_t sB, const float *__restrict__ scale, int64_t sS,
-                                              int64_t k_per_split, float *__restrict__ part) {
+                                              int64_t k_per_split, int symmetric, float *__restrict__ part) {
+  // a symmetric product computes the tiles on and above the diagonal
+  if (symmetric && blockIdx.x > blockIdx.y) return;
   __shared__ float sAt[GT][GK + 1];
   __shared__ float sBt[GT][GK + 1];
   const int tid = threadIdx.x;
@@ -109,13 +111,17 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int64_t K, int nbatc
       }
 }
 
-// C = alpha * sum_splits part (+ C if accumulate), fixed summation order.
+// C = alpha * sum_splits part (+ C if accumulate), fixed summation order.  A
+// symmetric product takes the entries of tiles below the diagonal from their
+// mirror images.
 __global__ __launch_bounds__(256) void k_gemm_reduce(int M, int N, int splits, const float *__restrict__ part, float alpha,
-                                                     float *__restrict__ C, int64_t ldc, int c_colmajor, int accumulate) {
+                                                     float *__restrict__ C, int64_t ldc, int c_colmajor, int accumulate,
+                                                     int symmetric) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)M * N) return;
   const int i = (int)(t / N), j = (int)(t % N);
-  const double s = ordered_sum<double>(part + t, splits, (int64_t)M * N);
+  const int64_t src = (symmetric && i / GT > j / GT) ? (int64_t)j * N + i : t;
+  const double s = ordered_sum<double>(part + src, splits, (int64_t)M * N);
   float *dst = c_colmajor ? &C[(int64_t)j * ldc + i] : &C[(int64_t)i * ldc + j];
   const float v = (float)((double)alpha * s);
   *dst = accumulate ? *dst + v : v;
@@ -131,16 +137,17 @@ void launch_gemm(const GemmShape &g, float *part, hipStream_t s) {
   const int64_t kps = round_up((g.K + g.splits - 1) / g.splits, 16);
   dim3 grid((unsigned)((g.M + GT - 1) / GT), (unsigned)((g.N + GT - 1) / GT), (unsigned)g.splits);
   if (!g.a_mn && !g.b_mn)
-    k_gemm<false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, part);
+    k_gemm<false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, g.symmetric ? 1 : 0, part);
   else if (g.a_mn && !g.b_mn)
-    k_gemm<true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, part);
+    k_gemm<true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, g.symmetric ? 1 : 0, part);
   else if (!g.a_mn && g.b_mn)
-    k_gemm<false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, part);
+    k_gemm<false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, g.symmetric ? 1 : 0, part);
   else
-    k_gemm<true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, part);
+    k_gemm<true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, g.nbatch, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.scale, g.sS, kps, g.symmetric ? 1 : 0, part);
   const int64_t n = (int64_t)g.M * g.N;
   k_gemm_reduce<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g.M, g.N, g.splits, part, g.alpha, g.C, g.ldc,
-                                                            g.c_colmajor ? 1 : 0, g.accumulate ? 1 : 0);
+                                                            g.c_colmajor ? 1 : 0, g.accumulate ? 1 : 0,
+                                                            g.symmetric ? 1 : 0);
 }
 
 // ---- small dense FP64 kernels (one workgroup) ----

@@ -145,7 +145,7 @@ PodLayout pod_layout(int64_t m, int32_t n, int32_t R) {
   L.GU64 = take(sizeof(double) * R * R);
   L.Linv = take(sizeof(float) * R * R);
   L.work64 = take(sizeof(double) * R * R);
-  const int sg = gemm_splits(n, n, m), su = gemm_splits(R, R, m);
+  const int sg = gemm_splits(n, n, m, 1024, true), su = gemm_splits(R, R, m);
   const size_t part = std::max({sizeof(float) * (size_t)sg * n * n, sizeof(float) * (size_t)su * R * R,
                                 sizeof(float) * (size_t)m * R});
   L.part = take(part);
@@ -175,8 +175,10 @@ vds_status gram_into(vds_ctx c, const float *X, int64_t m, int n, float *gram, f
   g.ldb = m;
   g.C = gram;
   g.ldc = n;
-  g.splits = gemm_splits(n, n, m);
-  timed(c, VDS_TIMER_GEMM, 2.0 * n * (double)n * m, [&] { launch_gemm(g, part, c->stream); });
+  g.symmetric = true;
+  g.splits = gemm_splits(n, n, m, 1024, true);
+  // the symmetric product's own work: n (n + 1) / 2 entries of 2 m FLOP
+  timed(c, VDS_TIMER_GEMM, (double)n * (n + 1) * (double)m, [&] { launch_gemm(g, part, c->stream); });
   return hip_check(c, hipGetLastError(), "gram");
 }
 

@@ -30,6 +30,9 @@ struct GemmShape {
   bool c_colmajor = false;
   bool accumulate = false;
   int splits = 1;
+  // C = A A^T (A and B the same matrix, M = N): only tiles on and above the
+  // diagonal are computed, the others are mirrored in the reduction
+  bool symmetric = false;
 };
 
 size_t gemm_part_bytes(const GemmShape &g);
@@ -39,8 +42,10 @@ void launch_tri_inverse(const double *L, int n, double *work, float *Linv, hipSt
 void launch_f32_to_f64(const float *a, double *b, int64_t n, hipStream_t s);
 
 // Split count giving roughly `target` workgroups for an M x N output.
-inline int gemm_splits(int M, int N, int64_t K, int target = 1024) {
-  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+inline int gemm_splits(int M, int N, int64_t K, int target = 1024, bool symmetric = false) {
+  const int64_t tm = (M + 63) / 64, tn = (N + 63) / 64;
+  // a symmetric product runs only the tiles on and above the diagonal
+  const int64_t tiles = symmetric ? tm * (tm + 1) / 2 : tm * tn;
   int64_t s = (target + tiles - 1) / tiles;
   const int64_t kmax = (K + 255) / 256;  // keep >= 256 k per split
   if (s > kmax) s = kmax;
