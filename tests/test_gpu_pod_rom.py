@@ -60,6 +60,21 @@ def test_pod_gram_matches_exact_products(lib):
     assert _rel(G, X64 @ X64.T) < 1e-6
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (17, 1), (300, 900), (7001, 193), (60000, 300)])
+def test_pod_gram_one_triangle_mirrored(lib, m, n):
+    """The Gram launch computes the tiles on and above the diagonal and mirrors
+    the rest: exactly symmetric, and within FP32 accumulation of the
+    FP64 product, over single-tile, ragged and many-split shapes."""
+    rng = np.random.default_rng(m + n)
+    X = wl.to_f32(rng.standard_normal((n, m)))
+    ctx = lib.Context(1, 10, 0.5, poison=True)
+    G = _np(ctx.pod_gram(_dev(X)))
+    assert np.isfinite(G).all()
+    assert np.array_equal(G, G.T)
+    X64 = X.astype(np.float64)
+    assert _rel(G, X64 @ X64.T) < 1e-6
+
+
 def test_pod_basis_recovers_known_factors(lib):
     rng = np.random.default_rng(1)
     m, n, R = 3000, 40, 8
