@@ -106,16 +106,22 @@ def reduced_rhs(p: np.ndarray, XH: np.ndarray, XB: np.ndarray, prob: vds.Problem
 
 
 def rom_run(U: np.ndarray, q0: np.ndarray, w: np.ndarray, prob: vds.Problem, steps: int,
-            freeze_every: int, callback=None, midpoint: bool = False):
+            freeze_every: int, callback=None, midpoint=False):
     """Reduced explicit Euler from p(0) = U^T q(0) with the freeze schedule
     above.  `callback(step, p)` sees every reduced state.  Returns p(steps).
 
     With `midpoint` (an addition, not in the paper) the operators of a window
     of n steps are rebuilt at the state predicted for its midpoint: n // 2
     steps from the window's start with the start's operators (none when
-    n = 1), then the window is taken from its start with the new operators."""
+    n = 1), then the window is taken from its start with the new operators.
+    With `midpoint="extrapolated"` (also an addition) every window after the
+    first takes its operators at the midpoint state extrapolated on the line
+    through the previous window's start state and its own, i.e.
+    p + (n // 2) / n_prev (p - p_prev) for a previous window of n_prev steps;
+    the first window predicts as with `midpoint`."""
     if prob.potential != "hookean":
         raise ValueError("the reduced spring term is exact only for Hookean springs")
+    extrapolated = midpoint == "extrapolated"
     nb, P, d = q0.shape
     p = pod.project(U, q0)
     XH = hydro(U, prob.G, P, d)
@@ -125,15 +131,22 @@ def rom_run(U: np.ndarray, q0: np.ndarray, w: np.ndarray, prob: vds.Problem, ste
         return XB1 + XB2
 
     XB = None
+    p_prev, n_prev = None, 0
     for s in range(steps):
         if s % freeze_every == 0:
-            XB = operators_at(p)
-            half = min(freeze_every, steps - s) // 2
-            if midpoint and half > 0:
-                pm = p
-                for _ in range(half):
-                    pm = pm + prob.dt * reduced_rhs(pm, XH, XB, prob)
-                XB = operators_at(pm)
+            n = min(freeze_every, steps - s)
+            half = n // 2
+            if extrapolated and n_prev > 0 and half > 0:
+                XB = operators_at(p + (half / n_prev) * (p - p_prev))
+            else:
+                XB = operators_at(p)
+                if midpoint and half > 0:
+                    pm = p
+                    for _ in range(half):
+                        pm = pm + prob.dt * reduced_rhs(pm, XH, XB, prob)
+                    XB = operators_at(pm)
+            if extrapolated:
+                p_prev, n_prev = p, n
         p = p + prob.dt * reduced_rhs(p, XH, XB, prob)
         if callback is not None:
             callback(s + 1, p)

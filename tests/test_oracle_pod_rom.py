@@ -201,19 +201,26 @@ def test_training_reduces_loss():
 def test_midpoint_freeze_is_second_order_in_the_window():
     # differences between runs with windows M and M/2 (the time step fixed):
     # they halve with M for operators frozen at the window's start (first
-    # order) and quarter for operators at the predicted midpoint (second order)
+    # order) and quarter for operators at the predicted midpoint, whether the
+    # midpoint state is predicted by reduced steps or extrapolated from the
+    # last two window starts (second order; a wrong extrapolation coefficient
+    # or sign leaves the prediction first order, and the ratio near 2)
     q, prob = _small_case(P=14)
     P = q.shape[1]
     U, _ = np.linalg.qr(np.random.default_rng(21).standard_normal((3 * P, 10)))
     w = vds.uniform_weights(P)
     steps = 128
     runs = {(mid, M): rom.rom_run(U, q, w, prob, steps, freeze_every=M, midpoint=mid)
-            for mid in (False, True) for M in (8, 16, 32, 64)}
+            for mid in (False, True, "extrapolated") for M in (8, 16, 32, 64)}
     scale = np.linalg.norm(runs[(False, 8)])
-    for mid, lo, hi in ((False, 1.8, 2.3), (True, 3.6, 4.6)):
+    for mid, lo, hi in ((False, 1.8, 2.3), (True, 3.6, 4.6), ("extrapolated", 3.3, 4.6)):
         d = [np.linalg.norm(runs[(mid, M)] - runs[(mid, M // 2)]) / scale for M in (16, 32, 64)]
         assert lo < d[1] / d[0] < hi and lo < d[2] / d[1] < hi, (mid, d)
-    # a window of one step has no midpoint to predict: the two schedules agree
+    # a window of one step has no midpoint to predict: the schedules agree
     a = rom.rom_run(U, q, w, prob, 10, freeze_every=1)
-    b = rom.rom_run(U, q, w, prob, 10, freeze_every=1, midpoint=True)
-    assert np.array_equal(a, b)
+    for mid in (True, "extrapolated"):
+        assert np.array_equal(a, rom.rom_run(U, q, w, prob, 10, freeze_every=1, midpoint=mid))
+    # within the first window there is no earlier start to extrapolate from:
+    # both midpoint forms predict by reduced steps
+    a = rom.rom_run(U, q, w, prob, 12, freeze_every=16, midpoint=True)
+    assert np.array_equal(a, rom.rom_run(U, q, w, prob, 12, freeze_every=16, midpoint="extrapolated"))
