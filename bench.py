@@ -195,18 +195,20 @@ def measure_pod_rom(pkg, wl, torch, P):
             "T_s": T_f, "T_over_T_ref": T_f / T_ref,
             "err_mor_t_end": float((ctx.pod_reconstruct(U, pf) - q).norm() / q.norm()),
             "stress_rel_err_vs_plain": float(np.linalg.norm(tau_f - tau_ref) / np.linalg.norm(tau_ref))}
-    midpoint_sweep = {}
-    for fe in (300, 200, 150, 100):
-        pf = ctx.pod_project(U, q0)
-        torch.cuda.synchronize()
-        t4 = time.perf_counter()
-        tau_f = rom.run(pf, cfg["rom_steps"], fe, midpoint=True)
-        torch.cuda.synchronize()
-        T_f = time.perf_counter() - t4
-        midpoint_sweep[f"freeze_every_{fe}"] = {
-            "T_s": T_f, "T_over_T_ref": T_f / T_ref,
-            "err_mor_t_end": float((ctx.pod_reconstruct(U, pf) - q).norm() / q.norm()),
-            "stress_rel_err_vs_plain": float(np.linalg.norm(tau_f - tau_ref) / np.linalg.norm(tau_ref))}
+    midpoint_sweep, extrapolated_sweep = {}, {}
+    for mode, sweep, fes in ((True, midpoint_sweep, (300, 200, 150, 100)),
+                             ("extrapolated", extrapolated_sweep, (300, 200, 150, 100, 50))):
+        for fe in fes:
+            pf = ctx.pod_project(U, q0)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            tau_f = rom.run(pf, cfg["rom_steps"], fe, midpoint=mode)
+            torch.cuda.synchronize()
+            T_f = time.perf_counter() - t4
+            sweep[f"freeze_every_{fe}"] = {
+                "T_s": T_f, "T_over_T_ref": T_f / T_ref,
+                "err_mor_t_end": float((ctx.pod_reconstruct(U, pf) - q).norm() / q.norm()),
+                "stress_rel_err_vs_plain": float(np.linalg.norm(tau_f - tau_ref) / np.linalg.norm(tau_ref))}
     qp = ctx.pod_reconstruct(U, ctx.pod_project(U, q))
     projection_floor = {"state": float((qp - q).norm() / q.norm()),
                         "stress": float(np.linalg.norm(ctx.stress(qp) - tau_ref) / np.linalg.norm(tau_ref))}
@@ -230,6 +232,7 @@ def measure_pod_rom(pkg, wl, torch, P):
         "kernel_gemm_tflops": kg[2] / (kg[0] * 1e-3) / 1e12 if kg[0] else None,
         "freeze_sweep": freeze_sweep,
         "midpoint_freeze_sweep": midpoint_sweep,
+        "extrapolated_midpoint_freeze_sweep": extrapolated_sweep,
         "projection_floor_t_end": projection_floor,
     }
 

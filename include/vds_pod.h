@@ -90,6 +90,19 @@ vds_status vds_rom_run(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze
 vds_status vds_rom_run_midpoint(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every,
                                 double *tau_host);
 
+/* As vds_rom_run_midpoint (not in the paper either), with one freeze per
+ * window after the first: a window of n steps whose predecessor had n_prev
+ * steps and started at p_prev takes its operators at
+ * p + (n / 2) / n_prev (p - p_prev), the midpoint state extrapolated on the
+ * line through the two window starts.  The first window, and any window of
+ * one step, behaves as in vds_rom_run_midpoint.  The extrapolated state is
+ * second order in the window length, as the predicted one is, so the freeze
+ * error stays second order at half the freezes and n steps per window.
+ * Uses the reduced model's own workspace (two nb x R buffers).  Arguments and
+ * errors as vds_rom_run.  Synchronises. */
+vds_status vds_rom_run_extrapolated(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every,
+                                    double *tau_host);
+
 /* Stress of q~ = U p from p_dev and the M_ab: tau_ab = (n/P) sum_j H_j p_j^T M_ab p_j. */
 vds_status vds_rom_stress(vds_rom rom, const float *p_dev, double *tau_host);
 

@@ -88,6 +88,7 @@ _sigs.update({
     "vds_rom_operators": ([_P, _P, _P, _P, _P], C.c_int),
     "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_run_midpoint": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "vds_rom_run_extrapolated": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_stress": ([_P, _P, C.POINTER(C.c_double)], C.c_int),
 })
 
@@ -354,9 +355,14 @@ class Rom:
 
     def run(self, p, nsteps, freeze_every, midpoint=False):
         """Reduced explicit Euler steps; with `midpoint` the operators of each
-        window come from its predicted midpoint (vds_rom_run_midpoint)."""
+        window come from its predicted midpoint (vds_rom_run_midpoint), with
+        `midpoint="extrapolated"` from the midpoint extrapolated from the last
+        two window starts (vds_rom_run_extrapolated)."""
         tau = (C.c_double * 9)()
-        fn = _lib.vds_rom_run_midpoint if midpoint else _lib.vds_rom_run
+        if midpoint == "extrapolated":
+            fn = _lib.vds_rom_run_extrapolated
+        else:
+            fn = _lib.vds_rom_run_midpoint if midpoint else _lib.vds_rom_run
         _check(fn(self.rom, _ptr(p), int(nsteps), int(freeze_every), tau), self.ctx.ctx)
         return np.array(tau[:]).reshape(3, 3)
 

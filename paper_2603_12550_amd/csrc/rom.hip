@@ -27,7 +27,7 @@ constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the ke
 constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
 
 struct RomLayout {
-  size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, total;
+  size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, pprev, total;
   int NB16;
   int64_t ldy;
 };
@@ -63,6 +63,7 @@ RomLayout rom_layout(const vds_problem &p, int R) {
   L.part = take(part);
   L.red = take(sizeof(double) * 16);
   L.psave = take(sizeof(float) * (size_t)p.nb * R);
+  L.pprev = take(sizeof(float) * (size_t)p.nb * R);
   L.total = off;
   return L;
 }
@@ -483,6 +484,13 @@ __global__ void k_add(const float *__restrict__ a, const float *__restrict__ b, 
   if (t < n) c[t] = a[t] + b[t];
 }
 
+// p <- p + a (p - prev), in place: the linear extrapolation of the reduced
+// state from an earlier one
+__global__ void k_extrapolate(float *__restrict__ p, const float *__restrict__ prev, float a, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) p[t] = fmaf(a, p[t] - prev[t], p[t]);
+}
+
 // Explicit Euler on the reduced state p[k][s] (eq. model_DymReduced):
 // dp_k/dt = X^H p_k - (kT/zeta) sum_j A_kj X^B p_j - (1/zeta) sum_j A_kj H_j p_j.
 // One workgroup; p in LDS; each wavefront takes whole rows of X^H / X^B.
@@ -719,7 +727,7 @@ struct vds_rom_s {
   int R = 0;
   RomLayout L{};
   char *ws = nullptr;
-  float *Ude, *Mbig, *XH, *I1, *XB1, *XB2, *XB, *Bsw, *Y, *qt, *T, *invS, *part, *psave;
+  float *Ude, *Mbig, *XH, *I1, *XB1, *XB2, *XB, *Bsw, *Y, *qt, *T, *invS, *part, *psave, *pprev;
   double *red;
 };
 
@@ -896,6 +904,7 @@ vds_status vds_rom_create(vds_ctx c, const float *U, int32_t R, void *ws, size_t
   r->part = f(L.part);
   r->red = reinterpret_cast<double *>(r->ws + L.red);
   r->psave = f(L.psave);
+  r->pprev = f(L.pprev);
   const int64_t P = c->prob.P;
   hipStream_t s = c->stream;
   k_deinterleave<<<nblk256(3 * (int64_t)R * P), 256, 0, s>>>(U, P, R, r->Ude);
@@ -1100,22 +1109,52 @@ void rom_steps(vds_rom r, float *p, int n) {
 }
 
 // The windows of vds_rom_run / vds_rom_run_midpoint.
-vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, bool midpoint, double *tau) {
+// Operators frozen per window of freeze_every reduced steps.  FREEZE_START:
+// at the window's start state.  FREEZE_MIDPOINT: at the state half a window
+// on, predicted by reduced steps with the start's operators (two operator
+// builds per window).  FREEZE_EXTRAPOLATED: at the midpoint state extrapolated
+// linearly from this and the previous window's start states (one build per
+// window; the first window predicts as FREEZE_MIDPOINT does).  Both midpoint
+// forms predict the midpoint state to O(L^2) in the window length L, so the
+// frozen operators are O(L^2) from those at the true midpoint.
+enum FreezeAt { FREEZE_START = 0, FREEZE_MIDPOINT = 1, FREEZE_EXTRAPOLATED = 2 };
+
+vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, FreezeAt at, double *tau) {
   vds_ctx c = r->ctx;
-  const size_t pbytes = sizeof(float) * (size_t)c->prob.nb * r->R;
+  const int64_t np = (int64_t)c->prob.nb * r->R;
+  const size_t pbytes = sizeof(float) * (size_t)np;
+  auto copy = [&](float *dst, const float *src) {
+    return hip_check(c, hipMemcpyAsync(dst, src, pbytes, hipMemcpyDeviceToDevice, c->stream), "copy");
+  };
+  int nprev = 0;  // length of the previous window (0: none yet)
   for (int s0 = 0; s0 < nsteps; s0 += freeze_every) {
     const int n = std::min(freeze_every, nsteps - s0), half = n / 2;
-    vds_status st = freeze(r, p);
-    if (st != VDS_OK) return st;
-    if (midpoint && half > 0) {
-      // operators at the state half a window on, predicted with the start's
-      st = hip_check(c, hipMemcpyAsync(r->psave, p, pbytes, hipMemcpyDeviceToDevice, c->stream), "copy");
+    vds_status st = VDS_OK;
+    if (at == FREEZE_EXTRAPOLATED && nprev > 0 && half > 0) {
+      // the midpoint state from the last two window starts; back to the start
+      st = copy(r->psave, p);
       if (st != VDS_OK) return st;
-      rom_steps(r, p, half);
+      k_extrapolate<<<(unsigned)((np + 255) / 256), 256, 0, c->stream>>>(p, r->pprev, (float)half / (float)nprev, np);
       st = freeze(r, p);
-      if (st == VDS_OK)
-        st = hip_check(c, hipMemcpyAsync(p, r->psave, pbytes, hipMemcpyDeviceToDevice, c->stream), "copy");
+      if (st == VDS_OK) st = copy(p, r->psave);
       if (st != VDS_OK) return st;
+    } else {
+      st = freeze(r, p);
+      if (st != VDS_OK) return st;
+      if (at != FREEZE_START && half > 0) {
+        // operators at the state half a window on, predicted with the start's
+        st = copy(r->psave, p);
+        if (st != VDS_OK) return st;
+        rom_steps(r, p, half);
+        st = freeze(r, p);
+        if (st == VDS_OK) st = copy(p, r->psave);
+        if (st != VDS_OK) return st;
+      }
+    }
+    if (at == FREEZE_EXTRAPOLATED) {
+      st = copy(r->pprev, p);
+      if (st != VDS_OK) return st;
+      nprev = n;
     }
     rom_steps(r, p, n);
   }
@@ -1132,13 +1171,19 @@ extern "C" {
 vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
   if (r == nullptr) return VDS_ERR_ARG;
   if (!p || nsteps < 0 || freeze_every < 1) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
-  return rom_windows(r, p, nsteps, freeze_every, false, tau);
+  return rom_windows(r, p, nsteps, freeze_every, FREEZE_START, tau);
 }
 
 vds_status vds_rom_run_midpoint(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
   if (r == nullptr) return VDS_ERR_ARG;
   if (!p || nsteps < 0 || freeze_every < 1) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
-  return rom_windows(r, p, nsteps, freeze_every, true, tau);
+  return rom_windows(r, p, nsteps, freeze_every, FREEZE_MIDPOINT, tau);
+}
+
+vds_status vds_rom_run_extrapolated(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
+  if (r == nullptr) return VDS_ERR_ARG;
+  if (!p || nsteps < 0 || freeze_every < 1) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
+  return rom_windows(r, p, nsteps, freeze_every, FREEZE_EXTRAPOLATED, tau);
 }
 
 }  // extern "C"

@@ -203,20 +203,22 @@ def test_rom_run_small_vs_oracle(lib, tuning, R):
 
 @pytest.mark.parametrize("R", [12, 140, 250])
 @pytest.mark.parametrize("steps,every", [(30, 10), (23, 9)])
-def test_rom_run_midpoint_small_vs_oracle(lib, R, steps, every):
-    # operators at each window's predicted midpoint (vds_rom_run_midpoint)
-    # against the oracle's schedule; 23 steps in windows of 9 end with a
-    # window of 5 (a midpoint 2 steps in)
+@pytest.mark.parametrize("mode", [True, "extrapolated"])
+def test_rom_run_midpoint_small_vs_oracle(lib, R, steps, every, mode):
+    # operators at each window's predicted midpoint (vds_rom_run_midpoint),
+    # or at the midpoint extrapolated from the last two window starts
+    # (vds_rom_run_extrapolated), against the oracle's schedule; 23 steps in
+    # windows of 9 end with a window of 5 (a midpoint 2 steps in)
     P = 300
     U32, Uf, p32, prob = _small_rom_case(P, R, seed=7)
     ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
-    _say(f"reduced run with midpoint freezes P=300 R={R} {steps}/{every}")
+    _say(f"reduced run with midpoint freezes ({mode}) P=300 R={R} {steps}/{every}")
     rom = lib.Rom(ctx, _dev(U32))
     p = _dev(p32)
-    tau = rom.run(p, nsteps=steps, freeze_every=every, midpoint=True)
+    tau = rom.run(p, nsteps=steps, freeze_every=every, midpoint=mode)
     q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
     w = ovds.uniform_weights(P)
-    p_o = orom.rom_run(Uf, q0, w, prob, steps, every, midpoint=True)
+    p_o = orom.rom_run(Uf, q0, w, prob, steps, every, midpoint=mode)
     assert _rel(_np(p), p_o) < 1e-4
     tau_o = orom.reduced_stress(Uf, p_o, w, prob, P)
     assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
@@ -225,28 +227,33 @@ def test_rom_run_midpoint_small_vs_oracle(lib, R, steps, every):
     assert _rel(p_o, p_s) > 10 * _rel(_np(p), p_o)
 
 
-def test_rom_run_midpoint_edge_cases(lib):
+@pytest.mark.parametrize("mode", [True, "extrapolated"])
+def test_rom_run_midpoint_edge_cases(lib, mode):
     # windows of one step have no midpoint (the start-freeze run, bit for
-    # bit); a window longer than the run is one window; zero steps change
-    # nothing; a zero interval is rejected
+    # bit); a window longer than the run is one window (both midpoint forms
+    # then predict by reduced steps); zero steps change nothing; a zero
+    # interval is rejected
     P, R = 300, 12
     U32, Uf, p32, prob = _small_rom_case(P, R, seed=8)
     ctx = lib.Context(3, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
     rom = lib.Rom(ctx, _dev(U32))
     a, b = _dev(p32), _dev(p32)
     rom.run(a, nsteps=12, freeze_every=1)
-    rom.run(b, nsteps=12, freeze_every=1, midpoint=True)
+    rom.run(b, nsteps=12, freeze_every=1, midpoint=mode)
     assert bool((a == b).all().item())
     c = _dev(p32)
-    rom.run(c, nsteps=12, freeze_every=40, midpoint=True)
+    rom.run(c, nsteps=12, freeze_every=40, midpoint=mode)
     q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
     p_o = orom.rom_run(Uf, q0, ovds.uniform_weights(P), prob, 12, 40, midpoint=True)
     assert _rel(_np(c), p_o) < 1e-4
+    e = _dev(p32)
+    rom.run(e, nsteps=12, freeze_every=40, midpoint=True)
+    assert bool((c == e).all().item())
     d = _dev(p32)
-    rom.run(d, nsteps=0, freeze_every=5, midpoint=True)
+    rom.run(d, nsteps=0, freeze_every=5, midpoint=mode)
     assert bool((d == _dev(p32)).all().item())
     with pytest.raises(lib.VDSError):
-        rom.run(d, nsteps=4, freeze_every=0, midpoint=True)
+        rom.run(d, nsteps=4, freeze_every=0, midpoint=mode)
 
 
 @pytest.mark.parametrize("tuning", TUNINGS)
