@@ -29,6 +29,28 @@ def test_pod_recovers_known_factors():
     assert pod.remaining_energy(lam)[R - 1] == pytest.approx((sig[R:] ** 2).sum() / (sig ** 2).sum(), rel=1e-10)
 
 
+def test_subspace_distance_is_the_sine_of_the_largest_principal_angle():
+    # Planes in R^6 at known principal angles: span(e1, e2) against
+    # span(cos a e1 + sin a e3, cos b e2 + sin b e4) has principal angles a and b,
+    # so the distance is sin(max(a, b)); a rotation of the whole space, a change
+    # of basis inside either plane or swapping the arguments leaves it unchanged.
+    rng = np.random.default_rng(17)
+    e = np.eye(6)
+    for a, b in ((0.3, 0.0), (0.1, 0.7), (1.2, 0.4), (math.pi / 2, 0.2)):
+        U1 = e[:, :2]
+        U2 = np.stack([math.cos(a) * e[:, 0] + math.sin(a) * e[:, 2],
+                       math.cos(b) * e[:, 1] + math.sin(b) * e[:, 3]], axis=1)
+        want = math.sin(max(a, b))
+        assert pod.subspace_distance(U1, U2) == pytest.approx(want, abs=1e-14)
+        assert pod.subspace_distance(U2, U1) == pytest.approx(want, abs=1e-14)
+        Q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+        B1, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+        B2, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+        assert pod.subspace_distance(Q @ U1 @ B1, Q @ U2 @ B2) == pytest.approx(want, abs=1e-13)
+    # one shared direction and one orthogonal one: the largest angle is pi/2
+    assert pod.subspace_distance(e[:, [0, 1]], e[:, [0, 4]]) == pytest.approx(1.0, abs=1e-15)
+
+
 def test_snapshot_matrix_column_order_and_round_trip():
     q0 = wl.gaussian_bonds(1, 3, 10, 1.0)
     q1 = wl.gaussian_bonds(2, 3, 10, 1.0)
