@@ -5,13 +5,16 @@ Hookean chain under shear (P = 20000 particles, D = 9, h = 0.4, dt = 1e-3):
 centring and operand packing, the two O(P^2) kernel passes per fixed-point
 iteration, drift, update and convergence test, and the FP64 stress.  The
 headline value is pair-evaluations per second over the timed steps (one
-pair-evaluation is one ordered (I, J) in one pass).
+pair-evaluation is one ordered (I, J) in one pass), computed in FP32 on the
+FP32 matrix cores.
 
-Prints ONE JSON line.  Inputs are resident in HBM before the timed region.
-The roofline object covers the dominant kernel (the pair pass): algorithmic
-FLOP per launch / average launch time measured with HIP events on the
-launching stream, against the MI355X dense FP32 matrix peak.  The CPU baseline
-is the FP64 oracle timed on a bounded sample of the same workload.
+Output: one JSON line per extra measurement and one for the FP16-split pair
+form (a separate, labelled arithmetic), then the headline as the LAST line
+(under 2 KB).  Inputs are resident in HBM before the timed region.  The
+headline's roofline object covers the dominant kernel (the pair pass):
+algorithmic FLOP per launch / average launch time measured with HIP events on
+the launching stream, against the MI355X dense FP32 matrix peak.  The CPU
+baseline is the FP64 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -41,7 +44,9 @@ def flops_per_pair(D: int) -> int:
 
 
 def cpu_baseline(cfg, threads: int):
-    """One implicit step of the FP64 oracle on the same state (all rows), timed."""
+    """One implicit step of the FP64 oracle on the same state (all rows), timed
+    on `threads` host threads; then both kernel passes of the same oracle over
+    a sample of rows on one thread."""
     from oracle import vds as ovds
     import workloads as wl
     q = wl.f32_as_f64(wl.to_f32(cfg["q0"]))
@@ -52,10 +57,22 @@ def cpu_baseline(cfg, threads: int):
     _, iters = ovds.step_implicit(q, w, prob, threads=threads)
     dt = time.perf_counter() - t0
     pairs = 2.0 * P * P * iters
+    # one core: passes A and B for 1000 rows against all P columns (S of every
+    # column from the threaded run's own routine, untimed)
+    x = ovds.particle_major(q)
+    S_all = ovds.density_sums(x, w, prob.h, threads=threads)
+    rows = np.arange(1000)
+    t1 = time.perf_counter()
+    ovds.brownian_terms(x, w, prob.h, rows=rows, S_all=S_all, threads=1)
+    dt1 = time.perf_counter() - t1
+    pairs1 = 2.0 * len(rows) * P
     return dict(value=pairs / dt, unit="pair-evals/s", cores=threads, kind="oracle",
-                sample=f"one implicit step (fixed-point tolerance 1e-13, {iters} iterations, both kernel "
-                       f"passes per iteration over all rows) of the P={P}, D=9 chain workload, FP64 NumPy "
-                       f"row blocks on {threads} threads: {pairs:.3g} pair-evals in {dt:.1f} s")
+                sample=f"one implicit step of the P={P}, D=9 chain (fixed-point tol 1e-13, {iters} iterations, "
+                       f"both passes over all rows), FP64 NumPy row blocks on {threads} threads: "
+                       f"{pairs:.3g} pair-evals in {dt:.1f} s",
+                one_core={"value": pairs1 / dt1, "cores": 1,
+                          "sample": f"passes A and B of 1000 rows x {P} columns on one thread: "
+                                    f"{pairs1:.3g} pair-evals in {dt1:.2f} s"})
 
 
 def kernel_source_hash() -> str:
@@ -64,39 +81,64 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-PAIR_KERNEL = {0: "k_pair_mfma", 1: "k_pair_valu", 2: "k_pair_mfma16", 3: "k_pair_mfma16"}
+PAIR_KERNEL = {0: "k_pair_mfma", 1: "k_pair_valu", 2: "k_pair_mfma16", 3: "k_pair_mfma16", 4: "k_pair_mfma32"}
 PAIR_ARITHMETIC = {
-    0: "pair products on FP32 MFMA, FP32 exponentials",
-    1: "pair products as FP32 vector FMAs, FP32 exponentials",
-    2: "distances on FP32 MFMA, kernel-weighted sums on FP16 MFMA with split factors, FP32 accumulation",
-    3: "both pair products on FP16 MFMA with every factor split into high and low halves, FP32 accumulation "
-       "and exponentials",
+    0: "fp32: pair products on FP32 MFMA 16x16x4, FP32 exponentials",
+    1: "fp32: pair products as FP32 vector FMAs, FP32 exponentials",
+    2: "fp16 hi/lo split (~22-bit) sums: distances on FP32 MFMA, kernel-weighted sums on FP16 MFMA with split "
+       "factors, FP32 accumulation",
+    3: "fp16 hi/lo split (~22-bit): both pair products on FP16 MFMA with every factor split into high and low "
+       "halves, FP32 accumulation and exponentials",
+    4: "fp32: distances on FP32 MFMA 32x32x2, kernel-weighted sums on FP32 MFMA 4x4x1, FP32 exponentials",
 }
-# v_exp_f32 issues at a quarter of the FP32 lane rate: 8 lanes per cycle per SIMD
+# v_exp_f32 issues 8 lanes per cycle per SIMD (measured: 8 cycles per wave64 instruction)
 EXP_PER_S = 256 * 4 * 8 * 2.4e9
 PEAK_FP16_TFLOPS = 2500.0
 
 
-def secondary_ceilings(impl: int, D: int, pairs_per_s: float):
-    """Ceilings besides the FP32 rate: one exp per pair-eval on the
-    transcendental unit, and for the FP16-split kernels the FP16 matrix-core
-    rate over the FP16 MFMA work each pair-eval costs there."""
-    out = {"exp_unit": {"pair_evals_per_s": EXP_PER_S, "frac": pairs_per_s / EXP_PER_S}}
+def issued_mfma_flop_per_pair(impl: int, D: int) -> float:
+    """FLOP the matrix cores issue per pair-eval (padding included)."""
+    if impl == 4:
+        kp = (D + 2) & ~1
+        ng = (D + 4) // 4
+        return 2.0 * kp + 2.0 * 4 * ng
+    if impl == 0:
+        kk = (D + 2 + 3) // 4
+        return 2.0 * 4 * kk + 2.0 * 16
     if impl in (2, 3):
         slices = (3 * D + 2 + 31) // 32 if impl == 3 else 0
-        # per 16x16 tile: the weighted sums take 1.5 FP16 MFMAs (3 per 32 columns);
-        # distances take `slices` FP16 MFMAs (impl 3) or FP32 MFMAs (impl 2, not counted here)
-        fp16_flop_per_pair = (1.5 + slices) * 16 * 16 * 32 * 2 / 256
-        cap = PEAK_FP16_TFLOPS * 1e12 / fp16_flop_per_pair
-        out["fp16_mfma"] = {"fp16_flop_per_pair": fp16_flop_per_pair, "pair_evals_per_s": cap,
-                            "frac": pairs_per_s / cap}
+        return (1.5 + slices) * 16 * 16 * 32 * 2 / 256
+    return 0.0
+
+
+def secondary_ceilings(impl: int, D: int, pairs_per_s: float):
+    """Ceilings besides the algorithmic FP32 rate: one exp per pair-eval on the
+    transcendental unit, and the matrix-core rate of the MFMA work each
+    pair-eval issues (FP32 for the FP32 forms, FP16 for the split ones)."""
+    out = {"exp_unit": {"pair_evals_per_s": EXP_PER_S, "frac": pairs_per_s / EXP_PER_S}}
+    f = issued_mfma_flop_per_pair(impl, D)
+    if f:
+        peak = PEAK_FP16_TFLOPS if impl in (2, 3) else PEAK_FP32_TFLOPS
+        out["issued_mfma"] = {"dtype": "fp16" if impl in (2, 3) else "fp32", "flop_per_pair": f,
+                              "tflops": pairs_per_s * f / 1e12, "frac": pairs_per_s * f / (peak * 1e12)}
     return out
+
+
+def _compact(o, sig=4):
+    """Floats rounded to `sig` significant digits, for the JSON lines."""
+    if isinstance(o, float):
+        return float(f"{o:.{sig}g}")
+    if isinstance(o, dict):
+        return {k: _compact(v, sig) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [_compact(v, sig) for v in o]
+    return o
 
 
 def measured_traffic(kernel: str, tuning: dict, P: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
     if it was taken on the current kernel source and the same launch shape."""
-    path = os.path.join(ROOT, "profiles", "pair_pass_chain4_P20000_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_chain4_P{P}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -238,7 +280,10 @@ def measure_pod_rom(pkg, wl, torch, P):
 
 
 def measure_batched(pkg, wl, torch, steps):
-    """512 ensembles, explicit Euler, one graph-captured step replayed."""
+    """512 ensembles, explicit Euler, one graph-captured step replayed, to t_end
+    (`steps` steps); then a sample of ensembles run one by one on plain
+    contexts from the same states over the same steps: stress error of the
+    batched form at t_end against them, and the speedup."""
     ens = wl.ensembles()
     G = np.stack([wl.shear_gradient(r) for r in ens["rate"]])
     b = pkg.Batch(ens["P"], ens["h"], G)
@@ -247,6 +292,7 @@ def measure_batched(pkg, wl, torch, steps):
     tune = b.autotune(q0)
     q = q0.clone()
     b.step(q, nsteps=2)
+    q = q0.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tau = b.step(q, nsteps=steps, stress=True)
@@ -256,8 +302,6 @@ def measure_batched(pkg, wl, torch, steps):
     # plain single-ensemble contexts on a sample, same steps from the same start
     rng = np.random.default_rng(11)
     sample = rng.choice(ens["n_ens"], 12, replace=False)
-    qs = q0.clone()
-    tau_s = b.step(qs, nsteps=20, stress=True)
     t_plain, pairs_plain, errs = 0.0, 0.0, []
     for e in sample:
         e = int(e)
@@ -268,20 +312,20 @@ def measure_batched(pkg, wl, torch, steps):
         qe = states[e].clone()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        ctx.step(qe, nsteps=20)
+        ctx.step(qe, nsteps=steps)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t1
-        pairs_plain += 2.0 * float(ens["P"][e]) ** 2 * 20
+        pairs_plain += 2.0 * float(ens["P"][e]) ** 2 * steps
         tp = ctx.stress(qe)
-        errs.append(float(np.linalg.norm(tau_s[e] - tp) / np.linalg.norm(tp)))
+        errs.append(float(np.linalg.norm(tau[e] - tp) / np.linalg.norm(tp)))
     rate_b, rate_p = pairs / T_b, pairs_plain / t_plain
     return {
         "workload": f"{ens['n_ens']} independent 4-bead ensembles, P_b in [2000, 16000] (sum {int(ens['P'].sum())}), "
                     f"shear rate log-uniform [0.1, 10], h_b = 0.4 (P_b/20000)^(-1/13), explicit dt=1e-3, {steps} steps",
-        "tuning": tune, "seconds": T_b, "pair_evals_per_s": rate_b,
+        "tuning": tune, "seconds_to_t_end": T_b, "pair_evals_per_s": rate_b,
         "plain_single_ensemble_pair_evals_per_s": rate_p, "speedup_vs_plain_single": rate_b / rate_p,
         "plain_sample": [int(v) for v in sample],
-        "max_stress_rel_err_vs_plain_after_20_steps": max(errs),
+        "max_stress_rel_err_vs_plain_at_t_end": max(errs),
         "tau_mean_trace": float(np.mean([np.trace(t) for t in tau])),
     }
 
@@ -483,6 +527,35 @@ def measure_fene(pkg, wl, torch, steps):
             "tau": ctx.stress(q).tolist()}
 
 
+def _timed_steps(torch, ctx, q0, steps, warmup):
+    """`warmup` untimed steps, then `steps` timed implicit steps with HIP events
+    (no system fence) around every TIMING_STRIDE-th pair launch."""
+    from paper_2603_12550_amd import _vds
+    q = q0.clone()
+    if warmup:
+        ctx.step(q, nsteps=warmup)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True, stride=TIMING_STRIDE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = ctx.step(q, nsteps=steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tim = ctx.timing_read(_vds.VDS_TIMER_PAIR)
+    ctx.timing_enable(False)
+    return d, elapsed, tim
+
+
+def _pair_roofline(tune, P, D, iters, tim):
+    avg_ms = tim["ms"] / max(1, tim["launches"])
+    # every queued pair launch ran (none returned early past convergence), so
+    # the sampled average is that of full passes
+    all_ran = (2 * iters + TIMING_STRIDE - 1) // TIMING_STRIDE == tim["launches"]
+    flop_launch = P * P * flops_per_pair(D)
+    achieved = flop_launch / (avg_ms * 1e-3) / 1e12
+    return avg_ms, all_ran, flop_launch, achieved
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,12 +563,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--P", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--tuning", type=str, default="3,2,8",
-                    help="impl,rows_per_wave,col_splits of the pair kernel (the fastest shape measured on MI355X)")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="impl,rows_per_wave,col_splits of the FP32 pair kernel (default: the library's default)")
+    ap.add_argument("--fp16-tuning", type=str, default="3,2,8",
+                    help="impl,rows_per_wave,col_splits of the FP16-split line ('' skips it)")
     ap.add_argument("--autotune", action="store_true", help="let the library's autotuner pick the pair shape")
+    ap.add_argument("--no-t-end", action="store_true", help="skip the plain run to t_end (500 steps)")
     ap.add_argument("--copy-calibration", action="store_true", help="only run a plain copy of known size")
-    ap.add_argument("--sweep", action="store_true", help="only time every pair-kernel tuning and print a table")
-    ap.add_argument("--t-end", action="store_true", help="also time the full 500-step run to t_end")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the POD-reduced, batched, learned and FENE measurements")
     ap.add_argument("--extras", type=str, default="", help="comma-separated subset of the extra measurements")
@@ -519,107 +593,59 @@ def main():
 
     import torch
     import paper_2603_12550_amd as pkg
-    from paper_2603_12550_amd import _vds
     import workloads as wl
 
     torch.cuda.set_device(0)
     cfg = wl.chain4_shear(P=args.P)
     P, D = cfg["P"], 9
-    ctx = pkg.Context(3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit",
-                      picard_rtol=1e-6, picard_max=50, picard_batch=3)
+    mk = lambda: pkg.Context(3, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit",
+                             picard_rtol=1e-6, picard_max=50, picard_batch=3)
     q0 = torch.from_numpy(wl.to_f32(cfg["q0"])).cuda()
-    if args.sweep:
-        for impl, rbs in ((0, (1, 2, 4)), (2, (1, 2, 4)), (3, (1, 2, 4)), (1, (1,))):
-            for rb in rbs:
-                for sp in (1, 2, 4, 8, 16, 32):
-                    ctx.set_tuning(impl, rb, sp)
-                    q = q0.clone()
-                    ctx.step(q, nsteps=2)
-                    ctx.timing_enable(True)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    d = ctx.step(q, nsteps=5)
-                    torch.cuda.synchronize()
-                    el = time.perf_counter() - t0
-                    tim = ctx.timing_read(_vds.VDS_TIMER_PAIR)
-                    ctx.timing_enable(False)
-                    print(json.dumps({"impl": impl, "rows_per_wave": rb, "col_splits": sp,
-                                      "pair_avg_ms": tim["ms"] / max(1, tim["launches"]),
-                                      "step_ms": el * 1e3 / 5, "iters": d["iters"]}), flush=True)
-        return
+
+    # the FP16-split pair form: a different arithmetic, reported on its own line
+    if args.fp16_tuning:
+        c16 = mk()
+        c16.set_tuning(*[int(v) for v in args.fp16_tuning.split(",")])
+        t16 = c16.get_tuning()
+        d16, el16, tim16 = _timed_steps(torch, c16, q0, args.steps, args.warmup)
+        avg16, ran16, _, ach16 = _pair_roofline(t16, P, D, d16["iters"], tim16)
+        sec16 = secondary_ceilings(t16["impl"], D, P * P / (avg16 * 1e-3))
+        print(json.dumps(_compact({
+            "line": "fp16_split_pair_form", "dtype": "fp16 hi/lo split, ~22-bit",
+            "arithmetic": PAIR_ARITHMETIC[t16["impl"]], "tuning": t16,
+            "value": 2.0 * P * P * d16["iters"] / el16, "unit": "pair-evals/s", "ms_per_step": el16 * 1e3 / args.steps,
+            "pair_kernel": PAIR_KERNEL[t16["impl"]], "pair_avg_launch_ms": avg16, "all_timed_launches_ran": ran16,
+            "algorithmic_fp32_tflops": ach16,
+            "fp16_mfma": {"peak_tflops": PEAK_FP16_TFLOPS, **sec16["issued_mfma"]},
+            "exp_unit_frac": sec16["exp_unit"]["frac"]})), flush=True)
+        del c16
+
+    ctx = mk()
     if args.autotune:
         ctx.autotune(q0)
-    else:
+    elif args.tuning:
         ctx.set_tuning(*[int(v) for v in args.tuning.split(",")])
     tune = ctx.get_tuning()
-    q = q0.clone()
-
-    if args.warmup:
-        ctx.step(q, nsteps=args.warmup)
-    torch.cuda.synchronize()
-
-    # HIP events (no system fence) around every TIMING_STRIDE-th pair launch:
-    # the kernel's own time, sampled over the whole timed region
-    ctx.timing_enable(True, stride=TIMING_STRIDE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    d = ctx.step(q, nsteps=args.steps)
-    torch.cuda.synchronize()
+    if tune["impl"] not in (0, 1, 4):
+        print("bench.py: the headline runs an FP32 pair form (impl 0, 1 or 4)", file=sys.stderr)
+        sys.exit(2)
+    d, elapsed, tim = _timed_steps(torch, ctx, q0, args.steps, args.warmup)
     iters = d["iters"]
-    elapsed = time.perf_counter() - t0
-    tim = ctx.timing_read(_vds.VDS_TIMER_PAIR)
-    ctx.timing_enable(False)
+    avg_ms, all_ran, flop_launch, achieved = _pair_roofline(tune, P, D, iters, tim)
+    sec = secondary_ceilings(tune["impl"], D, P * P / (avg_ms * 1e-3))
 
-    pairs = 2.0 * P * P * iters
-    value = pairs / elapsed
-    avg_ms = tim["ms"] / max(1, tim["launches"])
-    # every queued pair launch ran (none returned early past convergence), so
-    # the sampled average is that of full passes
-    all_ran = (2 * iters + TIMING_STRIDE - 1) // TIMING_STRIDE == tim["launches"]
-    flop_launch = P * P * flops_per_pair(D)
-    achieved = flop_launch / (avg_ms * 1e-3) / 1e12
-
-    out = {
-        "metric": "kernel pair-evals/s (% FP32 peak); wall time to t_end vs plain VDS at <=1e-2 stress err",
-        "value": value,
-        "unit": "pair-evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "dtype_detail": PAIR_ARITHMETIC[tune["impl"]] + "; FP64 split sums and observables",
-        "data": "synthetic: 4-bead chain bonds drawn N(0, I/3), seed 2",
-        "config": {"workload": f"chain4_shear: 4-bead Hookean chain, P={P}, D=9, h=0.4, shear rate 1, "
-                               f"implicit Euler dt=1e-3, fixed-point rtol 1e-6",
-                   "P": P, "D": D, "pair_tuning": tune,
-                   "fixed_point_iterations_total": iters,
-                   "fixed_point_iterations_per_step": iters / max(1, args.steps)},
-        "roofline": {"bound": "mfma" if tune["impl"] == 0 else "alu", "achieved": achieved,
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic(PAIR_KERNEL[tune["impl"]], tune, P),
-                     "kernel": PAIR_KERNEL[tune["impl"]],
-                     "avg_launch_ms": avg_ms, "launches": tim["launches"], "timing_stride": TIMING_STRIDE,
-                     "all_timed_launches_ran": bool(all_ran),
-                     "flop_per_launch": flop_launch, "flop_per_pair": flops_per_pair(D),
-                     "secondary_ceilings": secondary_ceilings(tune["impl"], D, P * P / (avg_ms * 1e-3))},
-    }
-
-    if args.t_end:
+    # plain GPU VDS to t_end (the configuration's 500 steps), same context
+    t_end = None
+    if not args.no_t_end:
         qt = q0.clone()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        d = ctx.step(qt, nsteps=cfg["steps"])
+        dte = ctx.step(qt, nsteps=cfg["steps"])
         torch.cuda.synchronize()
-        out["t_end"] = {"steps": cfg["steps"], "seconds": time.perf_counter() - t1, "iterations": d["iters"],
-                        "tau": d["tau"].tolist()}
+        t_end = {"steps": cfg["steps"], "s": time.perf_counter() - t1, "iters": dte["iters"]}
 
+    extras = {}
     if not args.no_extras:
-        extras = {}
         for name, fn in (("pod_reduced", lambda: measure_pod_rom(pkg, wl, torch, P)),
                          ("batched", lambda: measure_batched(pkg, wl, torch, args.batched_steps)),
                          ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
@@ -635,13 +661,52 @@ def main():
                 continue
             t0 = time.perf_counter()
             extras[name] = fn()
-            print(f"[bench] {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-        out["extras"] = extras
+            print(json.dumps(_compact({"extra": name, "seconds": time.perf_counter() - t0, **extras[name]})),
+                  flush=True)
 
+    out = {
+        "metric": "kernel pair-evals/s (% FP32 peak); wall time to t_end vs plain VDS at <=1e-2 stress err",
+        "value": 2.0 * P * P * iters / elapsed,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic: 4-bead chain bonds drawn N(0, I/3), seed 2",
+        "config": {"workload": f"4-bead Hookean chain P={P} D=9 h=0.4 shear 1, implicit Euler dt=1e-3, "
+                               f"fixed-point rtol 1e-6",
+                   "pair_arithmetic": PAIR_ARITHMETIC[tune["impl"]],
+                   "tuning": [tune["impl"], tune["rows_per_wave"], tune["col_splits"]],
+                   "iters_per_step": iters / max(1, args.steps)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(PAIR_KERNEL[tune["impl"]], tune, P),
+                     "kernel": PAIR_KERNEL[tune["impl"]], "avg_launch_ms": avg_ms, "launches": tim["launches"],
+                     "all_timed_launches_ran": bool(all_ran), "flop_per_pair": flops_per_pair(D),
+                     "issued_mfma_frac": sec.get("issued_mfma", {}).get("frac"),
+                     "exp_unit_frac": sec["exp_unit"]["frac"]},
+        "t_end": t_end,
+    }
+    vs = {}
+    if "pod_reduced" in extras:
+        e = extras["pod_reduced"]
+        vs["pod_rom"] = {"time_ratio": e["T_rom_over_T_ref"], "stress_err": e["stress_rel_err_vs_plain"]}
+    if "batched" in extras:
+        e = extras["batched"]
+        vs["batched"] = {"speedup": e["speedup_vs_plain_single"], "stress_err": e["max_stress_rel_err_vs_plain_at_t_end"]}
+    if "learned" in extras:
+        e = extras["learned"]
+        vs["learned"] = {"speedup": e["speedup_vs_plain"], "stress_err": e["stress_rel_err_vs_plain"]}
+    if vs:
+        out["vs_plain_at_t_end"] = vs
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         out["cpu_baseline"] = cpu_baseline(cfg, threads)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_compact(out)), flush=True)
 
 
 if __name__ == "__main__":

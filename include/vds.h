@@ -47,7 +47,11 @@ typedef enum vds_status {
 enum { VDS_HOOKEAN = 0, VDS_FENE = 1 };
 enum { VDS_EXPLICIT = 0, VDS_IMPLICIT = 1 };
 /* Pair-kernel implementations (all compute the same sums):
- *   VDS_PAIR_MFMA       FP32 matrix cores for both products (distances, kernel-weighted sums);
+ *   VDS_PAIR_MFMA32     FP32 throughout (the default): distances on FP32 32x32x2 matrix
+ *                       instructions over augmented vectors with both squared norms in the
+ *                       contraction, kernel-weighted sums on FP32 4x4x1 matrix instructions
+ *                       (outputs in groups of four), FP32 exponentials;
+ *   VDS_PAIR_MFMA       FP32 matrix cores for both products on 16x16x4 tiles;
  *   VDS_PAIR_VALU       FP32 vector FMAs;
  *   VDS_PAIR_MFMA_F16X2 FP32 matrix cores for the distances, the kernel-weighted sums on FP16
  *                       matrix cores with both factors split into high and low halves (about
@@ -58,7 +62,8 @@ enum { VDS_EXPLICIT = 0, VDS_IMPLICIT = 1 };
  * The FP16-split forms are valid while every centred particle lies within about 1e3 h of
  * the weighted mean; further out the rounding of the expanded squared distance can exceed
  * the FP16 range (the FP32 forms have lost all accuracy there too). */
-enum { VDS_PAIR_MFMA = 0, VDS_PAIR_VALU = 1, VDS_PAIR_MFMA_F16X2 = 2, VDS_PAIR_MFMA_F16X2_ALL = 3 };
+enum { VDS_PAIR_MFMA = 0, VDS_PAIR_VALU = 1, VDS_PAIR_MFMA_F16X2 = 2, VDS_PAIR_MFMA_F16X2_ALL = 3,
+       VDS_PAIR_MFMA32 = 4 };
 
 /* Problem description (Sections 2.1, 2.2, 3.1; Appendix A).
  * Drift of bond k of particle I (eq. model_DymRepPar, convection dropped):
@@ -101,10 +106,12 @@ typedef struct vds_diag {
 } vds_diag;
 
 /* Pair-kernel launch shape (chosen by vds_autotune or set by hand; a new
- * context starts with VDS_PAIR_MFMA_F16X2_ALL, 2 row blocks per wave, 8 splits). */
+ * context starts with VDS_PAIR_MFMA32, 2 row blocks per wave, 16 splits).  The
+ * FP16-split forms are opt-in: they keep about 22 bits, not FP32's 24. */
 typedef struct vds_tuning {
   int32_t impl;          /* one of the VDS_PAIR_* implementations */
-  int32_t rows_per_wave; /* MFMA forms: 16-row blocks per wavefront (1, 2 or 4) */
+  int32_t rows_per_wave; /* MFMA forms: row blocks per wavefront (16 rows each: 1, 2 or 4;
+                          * VDS_PAIR_MFMA32: 32 rows each, 1 or 2) */
   int32_t col_splits;    /* column ranges summed separately, then reduced (>= 1) */
   int32_t reserved;
 } vds_tuning;
@@ -125,9 +132,10 @@ vds_status vds_bind_workspace(vds_ctx ctx, void *ws_dev, size_t bytes);
 const char *vds_last_error(vds_ctx ctx);
 vds_status vds_set_tuning(vds_ctx ctx, const vds_tuning *t);
 vds_status vds_get_tuning(vds_ctx ctx, vds_tuning *t);
-/* Times every admissible tuning on the state q_dev (a pair pass with the
- * finalisation that sums its column splits) and keeps the fastest
- * (synchronises). */
+/* Times every admissible launch shape (row blocks per wave, column splits) of
+ * the current implementation on the state q_dev (a pair pass with the
+ * finalisation that sums its column splits) and keeps the fastest; the
+ * implementation, and so the arithmetic, is left as set (synchronises). */
 vds_status vds_autotune(vds_ctx ctx, const float *q_dev, const float *w_dev);
 
 /* ---- the particle scheme (Sections 2.1-2.2, Appendix A) ----------------- */

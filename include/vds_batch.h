@@ -51,8 +51,10 @@ int64_t vds_batch_state_offset(vds_batch b, int32_t e);
 vds_status vds_batch_set_tuning(vds_batch b, int32_t impl, int32_t rows_per_wave, int32_t grid, int32_t use_graph);
 vds_status vds_batch_get_tuning(vds_batch b, int32_t *impl, int32_t *rows_per_wave, int32_t *grid,
                                 int32_t *use_graph);
-/* Times the admissible implementations and shapes on the packed state q_dev
- * and keeps the fastest (synchronises). */
+/* Times the admissible launch shapes (row blocks per wavefront, grid) of the
+ * current implementation on the packed state q_dev and keeps the fastest; the
+ * implementation, and so the arithmetic, is left as set (synchronises).  A new
+ * batch starts with VDS_PAIR_MFMA (FP32). */
 vds_status vds_batch_autotune(vds_batch b, const float *q_dev);
 
 /* Advances every ensemble of the packed state q_dev by nsteps explicit Euler

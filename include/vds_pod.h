@@ -75,10 +75,18 @@ vds_status vds_rom_operators(vds_rom rom, const float *p_dev, float *XH_dev, flo
 
 /* Advances p_dev[nb][R] by nsteps explicit Euler steps of eq.
  * model_DymReduced (Section 3.1), rebuilding X^B1 and X^B2 at q~ = U p before
- * steps 0, M, 2M, ... (M = freeze_every >= 1) and keeping p.  tau_host[9]
- * (may be NULL) receives the stress of the final reconstructed state,
- * evaluated from p and the M_ab (no reconstruction).  Synchronises. */
-vds_status vds_rom_run(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every, double *tau_host);
+ * steps 0, M, 2M, ... (M = freeze_every >= 1) and keeping p.
+ * tau_hist_host (may be NULL) receives the stress history of the reconstructed
+ * states (Section 2.1; the quantity of the stress comparisons of Section 3),
+ * each evaluated from p and the M_ab without reconstruction, row-major 3 x 3
+ * per entry: with output_every >= 1, entry i holds the stress after step
+ * min((i + 1) output_every, nsteps), so ceil(nsteps / output_every) entries
+ * (the last one after the final step); with output_every == 0, one entry, the
+ * stress after the final step (also for nsteps == 0).  The host buffer must
+ * hold that many entries of 9 doubles.  VDS_ERR_ARG for nsteps < 0,
+ * freeze_every < 1 or output_every < 0.  Synchronises. */
+vds_status vds_rom_run(vds_rom rom, float *p_dev, int32_t nsteps, int32_t freeze_every, int32_t output_every,
+                       double *tau_hist_host);
 
 /* As vds_rom_run, with the operators of each window (n steps) rebuilt at the
  * state predicted for its midpoint (not in the paper): after the freeze at the

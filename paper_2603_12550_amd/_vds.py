@@ -86,7 +86,7 @@ _sigs.update({
     "vds_rom_create": ([_P, _P, C.c_int32, _P, C.c_size_t, C.POINTER(_P)], C.c_int),
     "vds_rom_destroy": ([_P], None),
     "vds_rom_operators": ([_P, _P, _P, _P, _P], C.c_int),
-    "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "vds_rom_run": ([_P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_run_midpoint": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_run_extrapolated": ([_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "vds_rom_stress": ([_P, _P, C.POINTER(C.c_double)], C.c_int),
@@ -353,18 +353,26 @@ class Rom:
         _check(_lib.vds_rom_operators(self.rom, _ptr(p), _ptr(XH), _ptr(XB1), _ptr(XB2)), self.ctx.ctx)
         return XH, XB1, XB2
 
-    def run(self, p, nsteps, freeze_every, midpoint=False):
-        """Reduced explicit Euler steps; with `midpoint` the operators of each
-        window come from its predicted midpoint (vds_rom_run_midpoint), with
-        `midpoint="extrapolated"` from the midpoint extrapolated from the last
-        two window starts (vds_rom_run_extrapolated)."""
-        tau = (C.c_double * 9)()
-        if midpoint == "extrapolated":
-            fn = _lib.vds_rom_run_extrapolated
-        else:
-            fn = _lib.vds_rom_run_midpoint if midpoint else _lib.vds_rom_run
-        _check(fn(self.rom, _ptr(p), int(nsteps), int(freeze_every), tau), self.ctx.ctx)
-        return np.array(tau[:]).reshape(3, 3)
+    def run(self, p, nsteps, freeze_every, midpoint=False, output_every=0):
+        """Reduced explicit Euler steps; returns the final stress, or with
+        output_every >= 1 the stress history (vds_rom_run), shape
+        (ceil(nsteps / output_every), 3, 3).  With `midpoint` the operators of
+        each window come from its predicted midpoint (vds_rom_run_midpoint),
+        with `midpoint="extrapolated"` from the midpoint extrapolated from the
+        last two window starts (vds_rom_run_extrapolated)."""
+        if midpoint:
+            if output_every:
+                raise ValueError("the midpoint forms return the final stress only")
+            tau = (C.c_double * 9)()
+            fn = _lib.vds_rom_run_extrapolated if midpoint == "extrapolated" else _lib.vds_rom_run_midpoint
+            _check(fn(self.rom, _ptr(p), int(nsteps), int(freeze_every), tau), self.ctx.ctx)
+            return np.array(tau[:]).reshape(3, 3)
+        nout = -(-int(nsteps) // int(output_every)) if output_every > 0 else 1
+        tau = (C.c_double * (9 * max(1, nout)))()
+        _check(_lib.vds_rom_run(self.rom, _ptr(p), int(nsteps), int(freeze_every), int(output_every), tau),
+               self.ctx.ctx)
+        hist = np.array(tau[:]).reshape(-1, 3, 3)
+        return hist if output_every > 0 else hist[0]
 
     def stress(self, p):
         tau = (C.c_double * 9)()

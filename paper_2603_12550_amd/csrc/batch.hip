@@ -35,7 +35,7 @@ struct vds_batch_s {
   char *ws = nullptr;
   hipStream_t user = nullptr, priv = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  int impl = VDS_PAIR_MFMA_F16X2_ALL, rb = 2, grid = 1024, use_graph = 1;
+  int impl = VDS_PAIR_MFMA, rb = 2, grid = 1024, use_graph = 1;
   int nitems = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -143,6 +143,7 @@ void set_formats(vds_batch b) {
   for (EnsDesc &d : b->ens) {
     d.p.vhalf = (b->impl == VDS_PAIR_MFMA_F16X2 || b->impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
     d.p.qhalf = b->impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
+    d.p.f32x = 0;  // the batched pair kernels read the 16-row FP32 layout
   }
 }
 
@@ -383,7 +384,8 @@ vds_status vds_batch_autotune(vds_batch b, const float *q) {
   (void)hipEventCreate(&t1);
   float best = 1e30f;
   int best_impl = b->impl, best_rb = b->rb, best_grid = b->grid;
-  for (int impl : {VDS_PAIR_MFMA, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL}) {
+  // the launch shape only: the arithmetic (implementation) stays the caller's choice
+  for (int impl : {b->impl}) {
     st = vds_batch_set_tuning(b, impl, b->rb, b->grid, b->use_graph);
     if (st != VDS_OK) break;
     pass_a(b, q, b->priv);  // operands in this implementation's format

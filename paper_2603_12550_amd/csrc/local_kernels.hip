@@ -77,6 +77,8 @@ __device__ inline void store_v(const EvalParams &p, float *V, int64_t J, int n, 
     const int64_t i = vh_index(J, n);
     h[i] = hi;
     h[i + p.Ppad * 16] = (_Float16)(v - (float)hi);
+  } else if (p.f32x) {
+    V[vc_index(J, n)] = v;
   } else {
     V[v_index(J, n)] = v;
   }
@@ -215,7 +217,17 @@ __device__ void prep_write(const EvalParams &p, int64_t I, int n, float x, float
   if (n == 0) wv[I] = wi;
   if (n < p.D) xc[I * p.D + n] = x;
   // the FP32 distance operands are read only by the FP32-distance pair forms
-  for (int k = n; k < (p.qhalf ? 0 : 4 * p.KK); k += 16) {
+  // (KP can exceed the sixteen lanes: slots k = n, n + 16)
+  for (int k = n; k < (p.f32x ? p.KP : 0); k += 16) {
+    float ka = 0.f;
+    if (real) {
+      if (k < p.D) ka = 2.f * p.kappa * x;  // k < D <= 15 only for k == n
+      else if (k == p.D) ka = -p.kappa * nrm;
+      else if (k == p.D + 1) ka = 1.f;
+    }
+    KA[kc_index(I, k, p.KP)] = ka;
+  }
+  for (int k = n; k < ((p.qhalf || p.f32x) ? 0 : 4 * p.KK); k += 16) {
     float qa = 0.f, ka = 0.f;
     if (real) {
       if (k < p.D) {
@@ -653,6 +665,10 @@ __global__ __launch_bounds__(kRedBlock) void k_density_rows(EvalParams p, const 
     x[a] = I < ny ? y[I * p.D + a] - mean_sh[a] : 0.f;
     nrm = fmaf(x[a], x[a], nrm);
   }
+  if (p.f32x) {  // plain centred coordinates, read by VDS_PAIR_MFMA32
+    for (int a = 0; a < p.D; ++a) QB[I * p.D + a] = x[a];
+    return;
+  }
   for (int k = 0; k < 4 * p.KK; ++k) {
     float qa = 0.f;
     if (I < ny) {
@@ -671,6 +687,38 @@ __global__ __launch_bounds__(kRedBlock) void k_density_rows(EvalParams p, const 
       qh[dh_index(I, sl, p.KQ)] = qv;
     }
     f16.RN[I] = I < ny ? -p.kappa * nrm : 0.f;
+  }
+}
+
+// QB/KA in the 16-row FP32 layout (qk_index) from the centred coordinates,
+// one thread per particle (padding rows: zeros).
+__global__ __launch_bounds__(kRedBlock) void k_pack_qk(EvalParams p, const float *__restrict__ xc,
+                                                       float *__restrict__ QB, float *__restrict__ KA) {
+  const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  if (I >= p.Ppad) return;
+  const bool real = I < p.P;
+  float x[kMaxD];
+  float nrm = 0.f;
+  for (int a = 0; a < p.D; ++a) {
+    x[a] = real ? xc[I * p.D + a] : 0.f;
+    nrm = fmaf(x[a], x[a], nrm);
+  }
+  for (int k = 0; k < 4 * p.KK; ++k) {
+    float qa = 0.f, ka = 0.f;
+    if (real) {
+      if (k < p.D) {
+        qa = x[k];
+        ka = 2.f * p.kappa * x[k];
+      } else if (k == p.D) {
+        qa = -p.kappa * nrm;
+        ka = 1.f;
+      } else if (k == p.D + 1) {
+        qa = 1.f;
+        ka = -p.kappa * nrm;
+      }
+    }
+    QB[qk_index(I, k, p.KK)] = qa;
+    KA[qk_index(I, k, p.KK)] = ka;
   }
 }
 
@@ -795,6 +843,9 @@ void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const 
   // rows are padded to a multiple of 256 within the Ppad-row operand buffer
   const int64_t nrows_pad = round_up(ny, kRowAlign);
   k_density_rows<<<nblocks(nrows_pad), kRedBlock, 0, s>>>(p, y, ny, meanp, nmeanp, QB, ops, nrows_pad);
+}
+void launch_pack_qk(const EvalParams &p, const float *xc, float *QB, float *KA, hipStream_t s) {
+  k_pack_qk<<<nblocks(p.Ppad), kRedBlock, 0, s>>>(p, xc, QB, KA);
 }
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm, float *f,
                         hipStream_t s) {

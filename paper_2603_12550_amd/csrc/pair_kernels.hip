@@ -171,6 +171,203 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
                     partial + (int64_t)blockIdx.y * part_stride_rows * 16, rb0);
 }
 
+// ---- FP32, 32x32 distance tiles and 4x4 sum blocks --------------------------
+//
+// On gfx950 the FP32 matrix instructions and the exponentials do not overlap
+// (the VALU work of one wave and the MFMAs of another share the SIMD's issue),
+// so a pass costs its MFMA cycles plus its exponential cycles and the MFMA
+// work per pair-eval is what to cut.  This form issues, per 1024 pairs (a
+// 32-row by 32-column tile):
+//  * distances: ceil((D+2)/2) v_mfma_f32_32x32x2f32 over the augmented
+//    vectors K_J = (2 kappa x_J, -kappa |x_J|^2, 1) and Q_I = (x_I, 1,
+//    -kappa |x_I|^2) (D = 9: 6 instead of 12 16x16x4 steps; the row norm in a
+//    K slot costs one 32x32x2 step, what setting every accumulator to it would
+//    cost in moves, and no registers);
+//  * kernel-weighted sums: 16 * ceil((D+1)/4) v_mfma_f32_4x4x1f32, whose 4x4
+//    blocks need only ceil((D+1)/4) groups of four outputs (D = 9: 12 output
+//    slots instead of the 16 of a 16x16 tile).
+// Lane l of the distance product holds t[J][I] for I = l % 32 and the sixteen
+// columns J = 8 (v / 4) + 4 (l / 32) + v % 4 of its registers v.  Taken as the
+// A operand of a 4x4x1 product, register v gives block b = l / 4 the rows
+// I = 4 (b % 8) + i and the single column J(b, v), which is the layout the
+// sums need: block b accumulates O[I][4 g + j] over the columns of lane half
+// b / 8, and the two halves are added at every FP64 flush (a cross-half
+// shuffle that leaves lane half h with rows i = h and i = 2 + h).
+// The four waves of a workgroup take the same column chunks, which are staged
+// once per workgroup in LDS, double buffered with one barrier per chunk.
+// Accumulation: FP32 within groups of kFlush32 chunks (128 columns), then
+// FP64, and the difference sums are formed in FP64 as for the other forms.
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kFlush32 = 4;  // 32-column chunks per FP32 accumulation group
+
+template <int D>
+struct Mfma32Shape {
+  static constexpr int KP = mfma32_kslots(D);  // K slots: D coordinates and the two norm terms, even
+  static constexpr int NK = KP / 2;             // 32x32x2 steps of the distance product
+  static constexpr int NG = (D + 4) / 4;        // four-wide output groups covering the D + 1 sums
+  static constexpr int KF4 = KP * 8;            // float4s of a chunk's K operand (KP x 32 floats)
+  static constexpr int VS = 5;                  // LDS float4 stride of one column's V (16 floats + 4 padding)
+  static constexpr int LF4 = KF4 + 32 * VS;     // LDS float4s of one chunk buffer
+  static constexpr int GF4 = KF4 + 128;         // float4s of one chunk in global memory
+};
+
+template <int D, int RB>
+__global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ xr, int nrb32,
+                                                     const float4 *__restrict__ KC, const float4 *__restrict__ VC,
+                                                     int nchunks, int chunks_per_split, int exclude_self, float kappa,
+                                                     float *__restrict__ partial, int64_t part_stride_rows,
+                                                     const int *__restrict__ done) {
+  using S = Mfma32Shape<D>;
+  __shared__ float4 sb[2][S::LF4];
+  // FP64 running sums, one slot per lane and value (only its own lane touches
+  // a slot, so plain read-add-write keeps the summation order): held in LDS,
+  // they leave the registers to the arithmetic
+  __shared__ double stot[4][RB][S::NG][2][64];
+  if (done != nullptr && *done) return;  // the whole grid returns: no barrier is left waiting
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int h = lane >> 5;   // lane half
+  const int li = lane & 31;  // row of the 32x32 tile (distance product) / column slot of the K operand
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int rb0 = ((int)blockIdx.x * 4 + wave) * RB;  // first 32-row block of this wave
+  const int c0 = (int)blockIdx.y * chunks_per_split;
+  const int c1 = min(nchunks, c0 + chunks_per_split);
+
+  // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
+  // row norm term -kappa |x_I|^2 (k == D + 1), 0 beyond
+  float qv[RB][S::NK];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int rb = rb0 + r < nrb32 ? rb0 + r : 0;  // waves past the rows compute on row block 0, unwritten
+    const float *x = xr + ((int64_t)rb * 32 + li) * D;
+    float nrm = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
+#pragma unroll
+    for (int kk = 0; kk < S::NK; ++kk) {
+      const int k = 2 * kk + h;
+      qv[r][kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? -kappa * nrm : 0.f));
+    }
+  }
+
+  // thread t stages float4s t, t + 256, ... of a chunk: the K operand first,
+  // then V into rows of VS float4s
+  constexpr int NST = (S::GF4 + 255) / 256;
+  auto stage_dst = [&](int u) { return u < S::KF4 ? u : S::KF4 + ((u - S::KF4) >> 2) * S::VS + ((u - S::KF4) & 3); };
+  auto chunk_src = [&](int c, int u) -> float4 {
+    return u < S::KF4 ? KC[(int64_t)c * S::KF4 + u] : VC[(int64_t)c * 128 + (u - S::KF4)];
+  };
+  if (c0 < c1) {
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+      const int u = t + 256 * i;
+      if (u < S::GF4) sb[0][stage_dst(u)] = chunk_src(c0, u);
+    }
+  }
+  __syncthreads();
+
+  double(*tot)[S::NG][2][64] = stot[wave];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int g = 0; g < S::NG; ++g) tot[r][g][0][lane] = tot[r][g][1][lane] = 0.0;
+
+  for (int c = c0; c < c1;) {
+    const int gend = min(c1, c + kFlush32);
+    floatx4 acc[RB][S::NG];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; c < gend; ++c) {
+      const int buf = (c - c0) & 1;
+      const bool more = c + 1 < c1;
+      float4 pre[NST];  // next chunk, stored after this one's arithmetic
+#pragma unroll
+      for (int i = 0; i < NST; ++i) {
+        const int u = t + 256 * i;
+        pre[i] = (more && u < S::GF4) ? chunk_src(c + 1, u) : float4{0.f, 0.f, 0.f, 0.f};
+      }
+      // per-lane bases; every read below is at a constant offset from them
+      const float *sK = reinterpret_cast<const float *>(sb[buf]) + h * 32 + li;
+      const float4 *sV = sb[buf] + S::KF4 + 4 * h * S::VS + (lane & 3);
+      float ka[S::NK];
+#pragma unroll
+      for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
+      floatx16 e[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < S::NK; ++kk) e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
+        // no clamp: the expanded squared distance exceeds zero only by its rounding
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
+        if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
+          // an empty volatile asm keeps this a branch: if-converted into selects
+          // it would cost sixteen VALU instructions on every tile
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
+        const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int g = 0; g < S::NG; ++g) acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
+      }
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          const int u = t + 256 * i;
+          if (u < S::GF4) sb[buf ^ 1][stage_dst(u)] = pre[i];
+        }
+      }
+      __syncthreads();
+    }
+    // the two lane halves hold the same outputs over different columns: half h
+    // keeps rows h and 2 + h and adds the partner half's partial of them
+    // (__builtin_amdgcn_permlane32_swap would do this in one instruction, but
+    // this compiler mistranslates it on MFMA result registers)
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int g = 0; g < S::NG; ++g) {
+        const float keep0 = h ? acc[r][g][1] : acc[r][g][0], send0 = h ? acc[r][g][0] : acc[r][g][1];
+        const float keep1 = h ? acc[r][g][3] : acc[r][g][2], send1 = h ? acc[r][g][2] : acc[r][g][3];
+        tot[r][g][0][lane] += (double)(keep0 + __shfl_xor(send0, 32));
+        tot[r][g][1][lane] += (double)(keep1 + __shfl_xor(send1, 32));
+      }
+  }
+
+  // lane l holds rows 4 ((l % 32) / 4) + h + 2 s (s = 0, 1) and outputs n = 4 g + l % 4;
+  // the weighted kernel sum O[.][D] sits in the lane of the same quad with l % 4 = D % 4
+  float *out = partial + (int64_t)blockIdx.y * part_stride_rows * 16;
+  const int src = (lane & ~3) | (D & 3);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (rb0 + r >= nrb32) break;
+#pragma unroll
+    for (int sidx = 0; sidx < 2; ++sidx) {
+      const int64_t row = (int64_t)(rb0 + r) * 32 + 4 * (li >> 2) + h + 2 * sidx;
+      const double sv = tot[r][D / 4][sidx][src];
+#pragma unroll
+      for (int g = 0; g < S::NG; ++g) {
+        const int n = 4 * g + (lane & 3);
+        if (n < D) out[row * 16 + n] = (float)((double)xr[row * D + n] * sv - tot[r][g][sidx][lane]);
+        else if (n == D) out[row * 16 + n] = (float)sv;
+      }
+    }
+  }
+}
+
 // ---- FP16-split variant ----------------------------------------------------
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -570,6 +767,7 @@ bool pair_shape_ok(const vds_tuning &t, int D) {
   if (t.col_splits < 1 || t.col_splits > kMaxSplits) return false;
   if (t.impl == VDS_PAIR_MFMA || t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL)
     return t.rows_per_wave == 1 || t.rows_per_wave == 2 || t.rows_per_wave == 4;
+  if (t.impl == VDS_PAIR_MFMA32) return t.rows_per_wave == 1 || t.rows_per_wave == 2;
   return t.impl == VDS_PAIR_VALU;
 }
 
@@ -596,13 +794,42 @@ static void launch_mfma16_k(int rb, dim3 grid, const PairF16Ops &ops, int nrb, i
   }
 }
 
+template <int D>
+static void launch_mfma32_d(int rb, dim3 grid, const float *xr, int nrb32, const float *KC, const float *VC,
+                            int nch, int cps, int ex, float kappa, float *partial, int64_t stride, const int *done,
+                            hipStream_t s) {
+  const float4 *kc = reinterpret_cast<const float4 *>(KC), *vc = reinterpret_cast<const float4 *>(VC);
+  if (rb == 1)
+    k_pair_mfma32<D, 1><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, nch, cps, ex, kappa, partial, stride, done);
+  else
+    k_pair_mfma32<D, 2><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, nch, cps, ex, kappa, partial, stride, done);
+}
+
 void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64_t nrow_blocks, const float *KA,
                       const float *VB, int64_t ncol_chunks, int64_t ncol_pad, const float *xc, bool exclude_self,
                       const float *wscale, const F16Operands &f16, float *partial, int64_t part_stride_rows,
-                      const int *done, hipStream_t s) {
+                      const int *done, hipStream_t s, float kappa) {
   const int ex = exclude_self ? 1 : 0;
   const int splits = t.col_splits;
   const int64_t cps = (ncol_chunks + splits - 1) / splits;
+  if (t.impl == VDS_PAIR_MFMA32) {
+    // rows in blocks of 32 (nrow_blocks counts 16-row blocks of a multiple of 256 rows, so
+    // every workgroup of 4 waves x RB blocks is full); columns in chunks of 32, the last
+    // inside the padding (ncol_pad is a multiple of 256 columns), whose weights are zero
+    const int rb = t.rows_per_wave;
+    const int nrb32 = (int)(nrow_blocks / 2);
+    const int nch = (int)((ncol_chunks + 1) / 2);
+    const int cps32 = (nch + splits - 1) / splits;
+    dim3 grid((unsigned)((nrb32 + 4 * rb - 1) / (4 * rb)), (unsigned)splits);
+    switch (D) {
+      case 3: launch_mfma32_d<3>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 6: launch_mfma32_d<6>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 9: launch_mfma32_d<9>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 12: launch_mfma32_d<12>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
+      default: launch_mfma32_d<15>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
+    }
+    return;
+  }
   if (t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL) {
     // chunk pairs; the second chunk of the last pair lies inside the padding
     // (ncol_pad is a multiple of 32 columns), whose V is zero

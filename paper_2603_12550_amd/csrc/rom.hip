@@ -792,6 +792,8 @@ vds_status freeze(vds_rom r, const float *p) {
       }
     });
   } else {
+    // the FP32 kernel GEMM reads the 16-row operand layout
+    if (c->ep.f32x) launch_pack_qk(c->ep, c->xc, c->QB, c->KA, s);
     k_rom_bsw<<<nblk256(Ppad * L.ldy), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, L.NB16, r->Bsw);
     const int nrb = (int)(Ppad / 16), ncc = (int)((P + 15) / 16);
     dim3 grid((unsigned)((nrb + 3) / 4), (unsigned)((L.NB16 + kNBG - 1) / kNBG));
@@ -1119,8 +1121,36 @@ void rom_steps(vds_rom r, float *p, int n) {
 // frozen operators are O(L^2) from those at the true midpoint.
 enum FreezeAt { FREEZE_START = 0, FREEZE_MIDPOINT = 1, FREEZE_EXTRAPOLATED = 2 };
 
-vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, FreezeAt at, double *tau) {
+// Stress of the reduced state p from the M_ab, copied into tau_host[9] in
+// stream order (the caller synchronises before reading it).
+vds_status rom_stress_async(vds_rom r, const float *p, double *tau_host) {
   vds_ctx c = r->ctx;
+  k_rom_stress<<<9, 256, 0, c->stream>>>(r->Mbig, p, c->prob.nb, r->R, c->ep, r->red);
+  return hip_check(c, hipMemcpyAsync(tau_host, r->red, sizeof(double) * 9, hipMemcpyDeviceToHost, c->stream),
+                   "copy stress");
+}
+
+// With output_every >= 1 the stress after steps output_every, 2 output_every,
+// ... and after the last step goes to tau[9 i ...]; with output_every == 0 only
+// the stress after the last step (tau may be NULL).
+vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, FreezeAt at, double *tau,
+                       int output_every = 0) {
+  vds_ctx c = r->ctx;
+  int nout = 0;
+  // steps [k, k + n) of the run, split at the output steps
+  auto steps_out = [&](int k, int n) -> vds_status {
+    while (n > 0) {
+      const int m = output_every > 0 ? std::min(n, output_every - k % output_every) : n;
+      rom_steps(r, p, m);
+      k += m;
+      n -= m;
+      if (tau != nullptr && ((output_every > 0 && k % output_every == 0) || k == nsteps)) {
+        vds_status st = rom_stress_async(r, p, tau + 9 * nout++);
+        if (st != VDS_OK) return st;
+      }
+    }
+    return VDS_OK;
+  };
   const int64_t np = (int64_t)c->prob.nb * r->R;
   const size_t pbytes = sizeof(float) * (size_t)np;
   auto copy = [&](float *dst, const float *src) {
@@ -1156,11 +1186,13 @@ vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, Freeze
       if (st != VDS_OK) return st;
       nprev = n;
     }
-    rom_steps(r, p, n);
+    vds_status so = steps_out(s0, n);
+    if (so != VDS_OK) return so;
   }
   vds_status st = hip_check(c, hipGetLastError(), "reduced steps");
   if (st != VDS_OK) return st;
-  if (tau) return vds_rom_stress(r, p, tau);
+  if (tau != nullptr && nsteps == 0) st = rom_stress_async(r, p, tau);
+  if (st != VDS_OK) return st;
   return hip_check(c, hipStreamSynchronize(c->stream), "synchronise");
 }
 
@@ -1168,10 +1200,11 @@ vds_status rom_windows(vds_rom r, float *p, int nsteps, int freeze_every, Freeze
 
 extern "C" {
 
-vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {
+vds_status vds_rom_run(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, int32_t output_every,
+                       double *tau_hist) {
   if (r == nullptr) return VDS_ERR_ARG;
-  if (!p || nsteps < 0 || freeze_every < 1) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
-  return rom_windows(r, p, nsteps, freeze_every, FREEZE_START, tau);
+  if (!p || nsteps < 0 || freeze_every < 1 || output_every < 0) return set_err(r->ctx, VDS_ERR_ARG, "bad arguments");
+  return rom_windows(r, p, nsteps, freeze_every, FREEZE_START, tau_hist, output_every);
 }
 
 vds_status vds_rom_run_midpoint(vds_rom r, float *p, int32_t nsteps, int32_t freeze_every, double *tau) {

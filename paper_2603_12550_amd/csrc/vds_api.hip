@@ -60,8 +60,9 @@ void pair_pass(vds_ctx c, const float *V, const float *wscale, const int *done) 
   const int64_t nrb = c->ep.Ppad / 16;
   const double pairs = (double)c->prob.P * (double)c->prob.P;
   timed(c, VDS_TIMER_PAIR, pairs, [&] {
-    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->QB, nrb, c->KA, V, ncol_chunks(c), c->ep.Ppad, c->xc, true,
-                     wscale, c->f16, c->part, c->ep.Ppad, done, c->stream);
+    // VDS_PAIR_MFMA32 takes its rows straight from the centred coordinates
+    launch_pair_pass(c->tune, c->ep.KK, c->ep.D, c->ep.f32x ? c->xc : c->QB, nrb, c->KA, V, ncol_chunks(c),
+                     c->ep.Ppad, c->xc, true, wscale, c->f16, c->part, c->ep.Ppad, done, c->stream, c->ep.kappa);
   });
 }
 
@@ -71,6 +72,7 @@ void apply_tuning(vds_ctx c, const vds_tuning &t) {
   c->tune = t;
   c->ep.vhalf = (t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
   c->ep.qhalf = t.impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
+  c->ep.f32x = t.impl == VDS_PAIR_MFMA32 ? 1 : 0;
 }
 
 void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, bool centre) {
@@ -177,6 +179,7 @@ void fill_params(vds_ctx c) {
   e.log_norm = (float)(0.5 * e.D * std::log(2.0 * M_PI * p.h * p.h));
   e.KQ = f16_slices(e.D);
   e.cs = (float)std::sqrt(2.0 * 1.4426950408889634 / (2.0 * p.h * p.h));
+  e.KP = mfma32_kslots(e.D);
   c->nblk = (int)((p.P + kRedBlock - 1) / kRedBlock);
   c->nblk_comb = (int)((p.P * 16 + kRedBlock - 1) / kRedBlock);
   apply_tuning(c, c->tune);  // operand formats of the default implementation
@@ -606,7 +609,7 @@ vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float
     const int64_t nrb = round_up(nr, kRowAlign) / 16;
     timed(c, VDS_TIMER_PAIR, (double)nr * (double)c->prob.P, [&] {
       launch_pair_pass(c->tune, e.KK, e.D, c->QB, nrb, c->KA, c->VA, ncol_chunks(c), e.Ppad, c->xc, false,
-                       c->wscale, c->f16, c->part, e.Ppad, nullptr, c->stream);
+                       c->wscale, c->f16, c->part, e.Ppad, nullptr, c->stream, e.kappa);
     });
     launch_density_out(e, c->part, c->tune.col_splits, nr, norm, f + r0, c->stream);
   }
@@ -644,24 +647,23 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
   hipEvent_t a = get_event(c), b = get_event(c);
   vds_tuning best = c->tune;
   float best_ms = 1e30f;
-  const int splits_list[] = {1, 2, 4, 8, 16, 32};
+  const int splits_list[] = {1, 2, 4, 6, 8, 12, 16, 20, 24, 32};
   const int rb_list[] = {1, 2, 4};
   std::vector<vds_tuning> cands;
-  for (int impl : {VDS_PAIR_MFMA, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL})
-    for (int rb : rb_list)
-      for (int sp : splits_list) cands.push_back(vds_tuning{impl, rb, sp, 0});
-  for (int sp : splits_list) cands.push_back(vds_tuning{VDS_PAIR_VALU, 1, sp, 0});
+  // the launch shape only: the implementation, and so the arithmetic, stays the caller's choice
+  for (int rb : rb_list)
+    for (int sp : splits_list) cands.push_back(vds_tuning{c->tune.impl, rb, sp, 0});
   const bool was_timing = c->timing;
   c->timing = false;
   int prepared = -1;
   for (const vds_tuning &t : cands) {
     if (!pair_shape_ok(t, c->ep.D)) continue;
     apply_tuning(c, t);
-    if (c->ep.vhalf + 2 * c->ep.qhalf != prepared) {  // operand formats follow the implementation
+    if (c->ep.vhalf + 2 * c->ep.qhalf + 4 * c->ep.f32x != prepared) {  // operand formats follow the implementation
       launch_mean_partials(c->ep, q, w, c->meanp, nullptr, nullptr, c->stream);
       launch_prep(c->ep, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, nullptr,
                   c->stream);
-      prepared = c->ep.vhalf + 2 * c->ep.qhalf;
+      prepared = c->ep.vhalf + 2 * c->ep.qhalf + 4 * c->ep.f32x;
     }
     // each candidate is timed with the finalisation that sums its column splits
     auto pass = [&] {

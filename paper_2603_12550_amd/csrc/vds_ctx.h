@@ -29,7 +29,7 @@ struct vds_ctx_s {
   std::vector<double> H;
   hipStream_t stream = nullptr;
   vds::EvalParams ep{};
-  vds_tuning tune{VDS_PAIR_MFMA_F16X2_ALL, 2, 8, 0};
+  vds_tuning tune{VDS_PAIR_MFMA32, 2, 16, 0};
   vds::Layout lay{};
   char *ws = nullptr;
   size_t ws_bytes = 0;

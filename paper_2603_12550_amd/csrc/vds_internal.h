@@ -63,7 +63,20 @@ struct EvalParams {
   int qhalf;          // FP16 distance operands QH/KH and row norms RN written too (VDS_PAIR_MFMA_F16X2_ALL)
   int KQ;             // FP16 distance slices of 32 products: f16_slices(D)
   float cs;           // sqrt(2 kappa): the distance operands are cs x
+  int f32x;           // FP32 operands in the per-chunk layout of VDS_PAIR_MFMA32 (KC in the KA buffer,
+                      // V in VA/VB at vc_index); QB/KA in the 16-row layout are then not written
+  int KP;             // K slots of that kernel's distance product: D + 2 rounded up to even
 };
+
+// FP32 operands of VDS_PAIR_MFMA32, per chunk of 32 columns (see pair_kernels.hip):
+//   KC: slot k < KP of column J at [((J / 32) * KP + k) * 32 + J % 32], slot k < D holding
+//       2 kappa x_J[k], slot D the column norm term -kappa |x_J|^2, slot D + 1 one (the row
+//       side holds x_I, 1 and the row norm term there), zero beyond;
+//   V:  element n < 16 of V_J at [J * 16 + (n % 4) * 4 + n / 4], so that the float4 at
+//       J * 4 + j holds elements j, 4 + j, 8 + j, 12 + j.
+__host__ __device__ constexpr int mfma32_kslots(int D) { return (D + 3) & ~1; }
+__host__ __device__ inline int64_t kc_index(int64_t J, int k, int KP) { return ((J >> 5) * KP + k) * 32 + (J & 31); }
+__host__ __device__ inline int64_t vc_index(int64_t J, int n) { return J * 16 + (n & 3) * 4 + (n >> 2); }
 
 // FP16 MFMA slices (32 products each) of the split distance product: three
 // per configuration component and two for the column norm.
@@ -145,10 +158,13 @@ enum CombineMode { MODE_TERMS = 0, MODE_VELOCITY = 1, MODE_EXPLICIT = 2, MODE_PI
 // the padded column count the V operand was written for.  With the FP16-split
 // implementation the V weights were divided by *wscale (NULL: by one), which
 // the pass multiplies back.
+// VDS_PAIR_MFMA32 reads its rows from QB as plain coordinates [nrow_blocks * 16][D] (the
+// centred particles, or centred foreign rows), KC from KA and V from VB in the per-chunk
+// layout above; kappa = log2(e) / 2h^2.
 void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64_t nrow_blocks,
                       const float *KA, const float *VB, int64_t ncol_chunks, int64_t ncol_pad, const float *xc,
                       bool exclude_self, const float *wscale, const F16Operands &f16, float *partial,
-                      int64_t part_stride_rows, const int *done, hipStream_t s);
+                      int64_t part_stride_rows, const int *done, hipStream_t s, float kappa = 0.f);
 bool pair_shape_ok(const vds_tuning &t, int D);
 // Batched pair pass over the (ensemble, row tile) work list `items` with a
 // persistent grid of `grid` workgroups; rb = row blocks per wavefront.
@@ -201,8 +217,12 @@ void launch_step_end(const EvalParams &p, Ctrl *ctrl, const PicardCheck &chk, co
 // packing combine; host-driven iterations).
 void launch_picard_check(const PicardCheck &chk, const float *blockmax, int nblk_chk, hipStream_t s);
 void launch_stress(const EvalParams &p, const float *q, const float *w, double *redp, hipStream_t s);
+// With p.f32x the centred rows go to QB as plain coordinates [rows][D] (VDS_PAIR_MFMA32).
 void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const double *meanp, int nmeanp,
                          float *QB, const F16Operands *f16, hipStream_t s);
+// QB/KA in the 16-row FP32 layout from the centred coordinates xc (the FP32 kernel GEMM of
+// the reduced model reads them; under p.f32x the prep kernels write the per-chunk layout).
+void launch_pack_qk(const EvalParams &p, const float *xc, float *QB, float *KA, hipStream_t s);
 void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm,
                         float *f, hipStream_t s);
 void launch_copy(const float *src, float *dst, int64_t n, const int *done_flag_or_null, hipStream_t s);

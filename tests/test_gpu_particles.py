@@ -49,10 +49,11 @@ def _rel(a, b):
 
 
 TUNINGS = [(0, 1, 1), (0, 2, 8), (0, 4, 3), (1, 1, 1), (1, 1, 5), (2, 1, 1), (2, 2, 8), (2, 4, 3),
-           (3, 1, 1), (3, 2, 8), (3, 4, 3)]
-# the default (FP16-split distances and sums), the FP32 MFMA form and the
-# FP16-split sums alone, at benchmark shapes
-IMPLS = [None, (0, 4, 16), (2, 4, 16)]
+           (3, 1, 1), (3, 2, 8), (3, 4, 3), (4, 1, 1), (4, 2, 8), (4, 1, 3), (4, 2, 5)]
+# the default (FP32, 32x32 distance tiles and 4x4 sum blocks), the 16x16 FP32
+# form, the FP16-split sums alone and the FP16-split form throughout, at
+# benchmark shapes
+IMPLS = [None, (0, 4, 16), (2, 4, 16), (3, 2, 8)]
 
 
 @pytest.mark.parametrize("P", [1, 2, 3, 17, 63, 64, 300])
@@ -477,7 +478,8 @@ def test_autotune_picks_a_valid_shape(lib):
     q32 = wl.to_f32(cfg["q0"])
     ctx = _ctx(lib, 3, cfg["P"], cfg["h"], H=cfg["H"], G=cfg["G"])
     t = ctx.autotune(_dev(q32))
-    assert t["impl"] in (0, 1, 2, 3) and 1 <= t["col_splits"] <= 32
+    # the shape only: the default FP32 implementation stays
+    assert t["impl"] == 4 and t["rows_per_wave"] in (1, 2) and 1 <= t["col_splits"] <= 32
     err, _, _ = _velocity_check(lib, cfg, tuning=(t["impl"], t["rows_per_wave"], t["col_splits"]))
     assert err < 1e-5
 
