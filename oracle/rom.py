@@ -97,6 +97,60 @@ def brownian(U: np.ndarray, qt: np.ndarray, w: np.ndarray, h: float):
     return -XB1 / h ** 2, -XB2 / h ** 2
 
 
+def brownian_rows(U: np.ndarray, qt: np.ndarray, w: np.ndarray, h: float, block: int = 256,
+                  threads: int = 1):
+    """`brownian` with the kernel matrix formed one block of rows at a time, for
+    sizes where Z (P x P) does not fit in memory: the same sums, grouped by row
+    blocks.  S = Z w and T = Z (w/S) are row sums; the terms of X^B1 and X^B2
+    are sums over rows I of U_a[I]^T (row-I quantities), so each row block
+    contributes its share and the shares are added in block order."""
+    from concurrent.futures import ThreadPoolExecutor
+    nb, P, d = qt.shape
+    R = U.shape[1]
+    x = vds.particle_major(qt)
+    Ua = mode_blocks(U, P, d)
+    blocks = [(lo, min(P, lo + block)) for lo in range(0, P, block)]
+
+    def zrows(lo, hi):
+        # |x_I - x_J|^2 by direct differences, one component at a time
+        r2 = np.zeros((hi - lo, P))
+        for a in range(x.shape[1]):
+            diff = x[lo:hi, a, None] - x[None, :, a]
+            r2 += diff * diff
+        return np.exp(-r2 / (2.0 * h * h))
+
+    def pmap(fn):
+        if threads > 1:
+            # one BLAS thread per worker: the workers already fill the cores
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"), ThreadPoolExecutor(threads) as ex:
+                return list(ex.map(fn, blocks))
+        return [fn(b) for b in blocks]
+
+    S = np.concatenate(pmap(lambda b: zrows(*b) @ w))
+    T = np.concatenate(pmap(lambda b: zrows(*b) @ (w / S)))
+    wU = [w[:, None] * Ua[a] for a in range(d)]
+    wsU = [(w / S)[:, None] * Ua[a] for a in range(d)]
+
+    def share(b):
+        lo, hi = b
+        Z = zrows(lo, hi)
+        X1 = np.zeros((R, R))
+        X2 = np.zeros((R, R))
+        for a in range(d):
+            Ub = Ua[a][lo:hi]
+            X1 += Ub.T @ Ub - Ub.T @ ((Z @ wU[a]) / S[lo:hi, None])
+            X2 += Ub.T @ (T[lo:hi, None] * Ub) - Ub.T @ (Z @ wsU[a])
+        return X1, X2
+
+    XB1 = np.zeros((R, R))
+    XB2 = np.zeros((R, R))
+    for X1, X2 in pmap(share):
+        XB1 += X1
+        XB2 += X2
+    return -XB1 / h ** 2, -XB2 / h ** 2
+
+
 def reduced_rhs(p: np.ndarray, XH: np.ndarray, XB: np.ndarray, prob: vds.Problem) -> np.ndarray:
     """Right side of eq. model_DymReduced for p[k][s]:
     dp_k/dt = X^H p_k - (1/zeta)[k_B T sum_j A_kj (X^B1 + X^B2) p_j + sum_j H_j A_kj p_j]."""

@@ -155,8 +155,10 @@ def _small_rom_case(P=300, R=12, seed=5):
     return U32, Uf, p32, prob
 
 
-# default: FP16-split pair kernels and kernel-GEMM; (0, 4, 16): the FP32 MFMA forms
-TUNINGS = [None, (0, 4, 16)]
+# default: the FP32 pair kernel (32x32 distances, 4x4 sums) and the FP32 kernel GEMM;
+# (0, 4, 16): the 16x16 FP32 pair form; (3, 2, 8): the FP16-split pair kernels and
+# the LDS-tiled FP16-split kernel GEMM
+TUNINGS = [None, (0, 4, 16), (3, 2, 8)]
 
 
 def _tuned(ctx, tuning):

@@ -68,6 +68,25 @@ def _small_case(P=12, nb=2, seed=5):
     return q, prob
 
 
+def test_row_blocked_operators_equal_the_literal_and_factored_sums():
+    # the row-blocked evaluation (used at sizes where the kernel matrix does not
+    # fit in memory) against the paper's literal index sums and the factored
+    # form, with ragged blocks and threads
+    q, prob = _small_case(P=13)
+    P = q.shape[1]
+    rng = np.random.default_rng(8)
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, 9)))
+    _, B1_l, B2_l = rom.operators_literal(U, q, prob)
+    for block, threads in ((5, 1), (4, 3), (13, 1), (64, 2)):
+        B1, B2 = rom.brownian_rows(U, q, vds.uniform_weights(P), prob.h, block=block, threads=threads)
+        assert np.allclose(B1, B1_l, rtol=1e-11, atol=1e-12), block
+        assert np.allclose(B2, B2_l, rtol=1e-11, atol=1e-12), block
+    w = wl.random_weights(3, P)
+    F1, F2 = rom.brownian(U, q, w, prob.h)
+    B1, B2 = rom.brownian_rows(U, q, w, prob.h, block=6, threads=2)
+    assert np.allclose(B1, F1, rtol=1e-12, atol=1e-13) and np.allclose(B2, F2, rtol=1e-12, atol=1e-13)
+
+
 def test_factored_operators_equal_the_papers_literal_sums():
     q, prob = _small_case()
     P = q.shape[1]
