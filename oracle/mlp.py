@@ -33,6 +33,27 @@ def forward(layers, X: np.ndarray):
     return a, (pres, acts)
 
 
+def bf16_round(x) -> np.ndarray:
+    """Round to bfloat16 (8 significant bits, FP32's exponent range) to nearest,
+    ties to even, from the FP32 value: keep the upper 16 bits of the FP32
+    pattern after adding 0x7fff plus the lowest kept bit.  Finite values only."""
+    u = np.ascontiguousarray(np.asarray(x, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(layers, X: np.ndarray) -> np.ndarray:
+    """The inference arithmetic of the learned step's BF16 form: every layer's
+    weights and inputs (the network input, then each hidden activation, as FP32
+    values) rounded to bfloat16, the products summed exactly (FP64 here), FP32
+    biases, SiLU between layers."""
+    a = np.asarray(X, dtype=np.float64)
+    for i, (W, b) in enumerate(layers):
+        z = bf16_round(a) @ bf16_round(W).T + np.asarray(b, dtype=np.float32).astype(np.float64)
+        a = silu(z) if i < len(layers) - 1 else z
+    return a
+
+
 def loss(layers, X, Y) -> float:
     y, _ = forward(layers, X)
     return float(((y - Y) ** 2).mean())

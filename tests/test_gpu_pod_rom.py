@@ -203,6 +203,32 @@ def test_rom_run_small_vs_oracle(lib, tuning, R):
     assert np.linalg.norm(tau - tau_o) / np.linalg.norm(tau_o) < 1e-4
 
 
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_rom_run_inhomogeneous_springs_vs_oracle(lib, tuning):
+    # H_k = k (Table 6): the reduced spring term sum_j H_j A_kj p_j and the
+    # reduced stress weight each bond by its own constant
+    P, R = 300, 30
+    U32, Uf, p32, prob = _small_rom_case(P, R, seed=9)
+    prob.H = np.array([1.0, 2.0, 3.0])
+    ctx = _tuned(lib.Context(3, P, prob.h, H=prob.H, G=prob.G, dt=prob.dt, scheme="explicit", poison=True),
+                 tuning)
+    _say(f"reduced run H_k = k P=300 R={R} tuning {tuning}")
+    rom = lib.Rom(ctx, _dev(U32))
+    p = _dev(p32)
+    hist = rom.run(p, nsteps=40, freeze_every=10, output_every=20)
+    q0 = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    w = ovds.uniform_weights(P)
+    taus = {}
+    p_o = orom.rom_run(Uf, q0, w, prob, 40, 10,
+                       callback=lambda s, pp: taus.__setitem__(s, orom.reduced_stress(Uf, pp, w, prob, P)))
+    assert _rel(_np(p), p_o) < 1e-4
+    for i, s in enumerate((20, 40)):
+        assert np.linalg.norm(hist[i] - taus[s]) / np.linalg.norm(taus[s]) < 1e-4
+    # and the springs matter: the homogeneous oracle run is far from it
+    prob_h = ovds.Problem(nb=3, h=prob.h, dt=prob.dt, G=prob.G)
+    assert _rel(orom.rom_run(Uf, q0, w, prob_h, 40, 10), p_o) > 100 * _rel(_np(p), p_o)
+
+
 @pytest.mark.parametrize("R", [12, 140, 250])
 @pytest.mark.parametrize("steps,every", [(30, 10), (23, 9)])
 @pytest.mark.parametrize("mode", [True, "extrapolated"])

@@ -265,3 +265,36 @@ def test_midpoint_freeze_is_second_order_in_the_window():
     # both midpoint forms predict by reduced steps
     a = rom.rom_run(U, q, w, prob, 12, freeze_every=16, midpoint=True)
     assert np.array_equal(a, rom.rom_run(U, q, w, prob, 12, freeze_every=16, midpoint="extrapolated"))
+
+
+def test_bf16_rounding_matches_torch_bfloat16():
+    # round to nearest even at 8 significant bits, checked against torch's CPU
+    # conversion on ordinary values, exact ties, both tie directions, signs and
+    # tiny/large magnitudes
+    import torch
+    rng = np.random.default_rng(12)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 1.0 + 2.0 ** -9,
+                         0.0, -0.0, 65504.0, 3.0e38]]).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), want)
+    # ties: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7 and goes to the even 1
+    assert mlp.bf16_round(np.float32(1.0 + 2.0 ** -8)) == 1.0
+    assert mlp.bf16_round(np.float32(1.0 + 3 * 2.0 ** -8)) == 1.0 + 2.0 ** -6
+
+
+def test_bf16_forward_reduces_to_the_fp64_forward_on_bf16_exact_operands():
+    # weights and inputs already representable in bfloat16, and hidden
+    # activations rounded by the bf16 form only: with a single linear layer
+    # the two forwards agree exactly
+    rng = np.random.default_rng(13)
+    W = mlp.bf16_round(rng.standard_normal((7, 11)))
+    b = rng.standard_normal(7).astype(np.float32).astype(np.float64)
+    X = mlp.bf16_round(rng.standard_normal((5, 11)))
+    y, _ = mlp.forward([(W, b)], X)
+    assert np.array_equal(mlp.forward_bf16([(W, b)], X), y)
+    # two layers: the hidden activation is rounded, so they differ by about 2^-9
+    W2 = mlp.bf16_round(rng.standard_normal((3, 7)))
+    y2, _ = mlp.forward([(W, b), (W2, b[:3])], X)
+    y2b = mlp.forward_bf16([(W, b), (W2, b[:3])], X)
+    assert 0 < np.abs(y2b - y2).max() < 2.0 ** -6 * np.abs(y2).max()
