@@ -18,7 +18,11 @@
  * - Every call is ordered on the HIP stream given at creation.  Calls that
  *   return host values synchronise that stream; the others are asynchronous.
  * - The library allocates no device memory for contexts: the caller binds a
- *   device workspace of the size the *_workspace_bytes query returns.
+ *   device workspace of the size the *_workspace_bytes query returns.  The one
+ *   exception is rocBLAS: the FP64 eigensolve of vds_pod_basis and the exact
+ *   window integrator vds_rom_run_exact use a rocBLAS handle that the context
+ *   creates on its first such call and keeps until vds_destroy; rocBLAS
+ *   allocates that handle's own device workspace.
  * - Errors: every call returns a vds_status.  Arguments are validated on the
  *   host before anything is launched; on error nothing is launched and
  *   vds_last_error() describes it.  Asynchronous device faults surface as

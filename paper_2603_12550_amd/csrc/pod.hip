@@ -243,12 +243,10 @@ vds_status vds_pod_basis(vds_ctx c, const float *X, int64_t m, int32_t n, int32_
   if (st != VDS_OK) return st;
   launch_f32_to_f64(gram, gram64, (int64_t)n * n, c->stream);
 
-  rocblas_handle h = nullptr;
-  if (rocblas_create_handle(&h) != rocblas_status_success) return set_err(c, VDS_ERR_HIP, "rocblas_create_handle");
-  rocblas_set_stream(h, c->stream);
+  rocblas_handle h = static_cast<rocblas_handle>(blas_handle(c));
+  if (h == nullptr) return VDS_ERR_HIP;
   const rocblas_status rs =
       rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, gram64, n, eig, offd, info);
-  rocblas_destroy_handle(h);
   if (rs != rocblas_status_success) return set_err(c, VDS_ERR_HIP, "rocsolver_dsyevd failed");
 
   std::vector<double> lam(n);

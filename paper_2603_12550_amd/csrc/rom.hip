@@ -985,9 +985,8 @@ vds_status vds_rom_run_exact(vds_rom r, float *p, int32_t nsteps, int32_t freeze
   double *Tm = take(sizeof(double) * n * n), *Cm = take(sizeof(double) * n * n);
   double *pv = take(sizeof(double) * n), *pw = take(sizeof(double) * n), *cs = take(sizeof(double) * n);
   float *ptrial = reinterpret_cast<float *>(take(sizeof(float) * n));  // trial state of an adaptive window
-  rocblas_handle hb = nullptr;
-  if (rocblas_create_handle(&hb) != rocblas_status_success) return set_err(c, VDS_ERR_HIP, "rocblas_create_handle");
-  rocblas_set_stream(hb, s);
+  rocblas_handle hb = static_cast<rocblas_handle>(blas_handle(c));
+  if (hb == nullptr) return VDS_ERR_HIP;
   rocblas_set_pointer_mode(hb, rocblas_pointer_mode_host);
   vds_status st = VDS_OK;
   const unsigned nn_blocks = (unsigned)nblk256(n * n);
@@ -1074,7 +1073,7 @@ vds_status vds_rom_run_exact(vds_rom r, float *p, int32_t nsteps, int32_t freeze
       if (gap < 0.25 * bound) tw = std::min(2.0 * tw, tw_max);  // grows back, up to the requested interval
     }
   }
-  rocblas_destroy_handle(hb);
+
   if (st != VDS_OK) return st;
   if (stats) {
     stats->windows = windows;

@@ -6,6 +6,8 @@
 #include <cstring>
 #include <new>
 
+#include <rocblas/rocblas.h>
+
 #include "vds_ctx.h"
 #include "vds_internal.h"
 
@@ -45,6 +47,20 @@ hipEvent_t get_event(vds_ctx c) {
   hipEvent_t e = nullptr;
   (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
   return e;
+}
+
+void *blas_handle(vds_ctx c) {
+  if (c->blas == nullptr) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+      set_err(c, VDS_ERR_HIP, "rocblas_create_handle");
+      return nullptr;
+    }
+    c->blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(c->blas);
+  rocblas_set_stream(h, c->stream);
+  return h;
 }
 
 int64_t ncol_chunks(const vds_ctx c) { return (c->prob.P + 15) / 16; }
@@ -308,6 +324,7 @@ void vds_destroy(vds_ctx c) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->blas != nullptr) rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
   delete c;
 }
 

@@ -48,6 +48,7 @@ struct vds_ctx_s {
   vds::Ctrl *ctrl;
   int nblk;       // blocks of the one-thread-per-particle kernels
   int nblk_comb;  // blocks of the sixteen-lanes-per-particle combine kernel
+  void *blas = nullptr;  // rocblas_handle of the FP64 eigensolve and exact windows, made on first use
 };
 
 namespace vds {
@@ -56,6 +57,9 @@ vds_status set_err(vds_ctx c, vds_status st, const std::string &m);
 vds_status hip_check(vds_ctx c, hipError_t e, const char *what);
 vds_status ready(vds_ctx c);
 hipEvent_t get_event(vds_ctx c);
+// The context's rocBLAS handle on the context's stream, created on the first call
+// (NULL on failure, with the error set).  Destroyed with the context.
+void *blas_handle(vds_ctx c);
 
 // Runs `fn` (which launches work on the context stream), bracketed by an event
 // pair when timing is on; `work` is the pair-evaluations or FLOP it performs.
