@@ -152,6 +152,22 @@ vds_status vds_autotune(vds_ctx ctx, const float *q_dev, const float *w_dev);
 vds_status vds_pair_sums(vds_ctx ctx, const float *q_dev, const float *w_dev,
                          float *S_dev, float *term1_dev, float *term2_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): vds_pair_sums
+ * with the same arguments and results (the same kernels, bit for bit), on a
+ * context with or without a bound workspace, using instead a static device
+ * scratch of 64 MiB that the library holds on every GPU it runs on until the
+ * process ends.  It allocates nothing: no hipMalloc or hipFree, no library
+ * routine that allocates, no kernel timing.  VDS_ERR_ARG (nothing launched)
+ * when vds_workspace_bytes of the context's problem exceeds 64 MiB (e.g. the
+ * 4-bead chain fits up to P = 25600).  Every call on a GPU shares that
+ * GPU's scratch, so calls that overlap on one GPU (concurrent streams or
+ * threads) race; the scratch keeps the last call's contents, and this path
+ * reads none of them before writing.  A workspace bound to the context is left
+ * bound and untouched.  Asynchronous, as vds_pair_sums. */
+vds_status vds_pair_sums_noalloc(vds_ctx ctx, const float *q_dev, const float *w_dev,
+                                 float *S_dev, float *term1_dev, float *term2_dev);
+
 /* Particle velocity v = dq/dt of eq. model_DymRepPar into v_dev[nb][P][3].
  * `diag` (host, may be NULL) receives the stress and, at no extra kernel
  * cost, F_h, dissipation and work at q.

@@ -66,6 +66,7 @@ _sigs = {
     "vds_get_tuning": ([_P, C.POINTER(vds_tuning)], C.c_int),
     "vds_autotune": ([_P, _P, _P], C.c_int),
     "vds_pair_sums": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "vds_pair_sums_noalloc": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "vds_velocity": ([_P, _P, _P, _P, C.POINTER(vds_diag)], C.c_int),
     "vds_step": ([_P, _P, _P, C.c_int32, C.POINTER(vds_diag)], C.c_int),
     "vds_stress": ([_P, _P, _P, C.POINTER(C.c_double)], C.c_int),

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include <rocblas/rocblas.h>
@@ -13,8 +14,18 @@
 
 using namespace vds;
 
+// Device scratch of vds_pair_sums_noalloc: one copy per GPU, held until the
+// process ends.  Its name is a host-side stand-in; device addresses come from
+// hipGetSymbolAddress (scratch_base below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices] = {};  // address of `scratch` on each device, once resolved
 }  // namespace
 
 namespace vds {
@@ -330,12 +341,13 @@ void vds_destroy(vds_ctx c) {
 
 const char *vds_last_error(vds_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
-  if (c == nullptr) return VDS_ERR_ARG;
-  if (ws == nullptr) return set_err(c, VDS_ERR_ARG, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return set_err(c, VDS_ERR_ARG, "workspace must be 256-byte aligned");
-  if (bytes < c->lay.total) return set_err(c, VDS_ERR_NOMEM, "workspace smaller than vds_workspace_bytes()");
-  c->ws = static_cast<char *>(ws);
+}  // extern "C"
+
+namespace {
+
+// Points the context's workspace views into `base` (bytes >= c->lay.total).
+void bind_views(vds_ctx c, char *base, size_t bytes) {
+  c->ws = base;
   c->ws_bytes = bytes;
   const Layout &L = c->lay;
   c->QB = reinterpret_cast<float *>(c->ws + L.QB);
@@ -359,6 +371,18 @@ vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
   c->xb[0] = reinterpret_cast<float *>(c->ws + L.xb0);
   c->xb[1] = reinterpret_cast<float *>(c->ws + L.xb1);
   c->xpred = reinterpret_cast<float *>(c->ws + L.xpred);
+}
+
+}  // namespace
+
+extern "C" {
+
+vds_status vds_bind_workspace(vds_ctx c, void *ws, size_t bytes) {
+  if (c == nullptr) return VDS_ERR_ARG;
+  if (ws == nullptr) return set_err(c, VDS_ERR_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return set_err(c, VDS_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < c->lay.total) return set_err(c, VDS_ERR_NOMEM, "workspace smaller than vds_workspace_bytes()");
+  bind_views(c, static_cast<char *>(ws), bytes);
   return VDS_OK;
 }
 
@@ -382,6 +406,66 @@ vds_status vds_pair_sums(vds_ctx c, const float *q, const float *w, float *S, fl
   evaluate(c, q, w, MODE_TERMS, false, nullptr, t1, t2, nullptr);
   return hip_check(c, hipMemcpyAsync(S, c->S, sizeof(float) * c->prob.P, hipMemcpyDeviceToDevice, c->stream),
                    "copy S");
+}
+
+}  // extern "C"
+
+namespace {
+
+// This device's copy of `scratch`: resolved once per device, with that device
+// current, and kept.
+vds_status scratch_base(vds_ctx c, char **out) {
+  int dev = 0;
+  vds_status st = hip_check(c, hipGetDevice(&dev), "hipGetDevice");
+  if (st != VDS_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return set_err(c, VDS_ERR_HIP, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void *p = nullptr;
+    st = hip_check(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (st != VDS_OK) return st;
+    if (p == nullptr) return set_err(c, VDS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return VDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vds_status vds_pair_sums_noalloc(vds_ctx c, const float *q, const float *w, float *S, float *t1, float *t2) {
+  if (c == nullptr) return VDS_ERR_ARG;
+  if (!q || !S || !t1 || !t2) return set_err(c, VDS_ERR_ARG, "null array");
+  if (c->lay.total > kScratchBytes)
+    return set_err(c, VDS_ERR_ARG,
+                   "problem too large for the static scratch: it needs " + std::to_string(c->lay.total) +
+                       " bytes (vds_workspace_bytes) and the scratch holds " + std::to_string(kScratchBytes) +
+                       "; vds_pair_sums with a bound workspace has no such limit");
+  char *base = nullptr;
+  vds_status st = scratch_base(c, &base);
+  if (st != VDS_OK) return st;
+  // the evaluation of vds_pair_sums on views into the scratch; every scratch
+  // element it reads is written earlier in the same call, so nothing needs
+  // clearing.  No kernel timing (its events would be created on demand).
+  char *old = c->ws;
+  const size_t old_bytes = c->ws_bytes;
+  const bool was_timing = c->timing;
+  c->timing = false;
+  bind_views(c, base, kScratchBytes);
+  evaluate(c, q, w, MODE_TERMS, false, nullptr, t1, t2, nullptr);
+  st = hip_check(c, hipMemcpyAsync(S, c->S, sizeof(float) * c->prob.P, hipMemcpyDeviceToDevice, c->stream),
+                 "copy S");
+  if (old != nullptr) {
+    bind_views(c, old, old_bytes);
+  } else {
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  c->timing = was_timing;
+  if (st == VDS_OK) st = hip_check(c, hipGetLastError(), "launch");
+  return st;
 }
 
 vds_status vds_velocity(vds_ctx c, const float *q, const float *w, float *v, vds_diag *d) {
