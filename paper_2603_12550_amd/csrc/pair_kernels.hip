@@ -191,16 +191,28 @@ __global__ __launch_bounds__(256) void k_pair_mfma(const float *__restrict__ QB,
 // A operand of a 4x4x1 product, register v gives block b = l / 4 the rows
 // I = 4 (b % 8) + i and the single column J(b, v), which is the layout the
 // sums need: block b accumulates O[I][4 g + j] over the columns of lane half
-// b / 8, and the two halves are added at every FP64 flush (a cross-half
-// shuffle that leaves lane half h with rows i = h and i = 2 + h).
+// b / 8, and the two halves are added at every FP64 flush (a permlane32 swap
+// that leaves lane half h with rows i = h and i = 2 + h).
 // The four waves of a workgroup take the same column chunks, which are staged
 // once per workgroup in LDS, double buffered with one barrier per chunk.
-// Accumulation: FP32 within groups of kFlush32 chunks (128 columns), then
-// FP64, and the difference sums are formed in FP64 as for the other forms.
+// Accumulation: FP32 within groups of kFlush32 chunks (each lane half sums 128
+// columns), then FP64, and the difference sums are formed in FP64 as for the
+// other forms.
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kFlush32 = 4;  // 32-column chunks per FP32 accumulation group
+constexpr int kFlush32 = 8;  // 32-column chunks per FP32 accumulation group (128 columns per lane half)
+constexpr int kStage32 = 2;  // 32-column chunks staged in LDS per barrier (divides kFlush32)
+
+// v_permlane32_swap: exchanges lanes 32..63 of `a` with lanes 0..31 of `b`.
+// Inline asm because __builtin_amdgcn_permlane32_swap is mistranslated by this
+// compiler when its operands come from MFMA results (both results become the
+// first operand).  The compiler does not account for the wait an MFMA result
+// needs before a VALU instruction may read it when the reader is inline asm,
+// so the asm waits 8 cycles itself (a 4x4x1 result needs fewer).
+__device__ inline void permlane32_swap(float &a, float &b) {
+  asm volatile("s_nop 7\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
 
 template <int D>
 struct Mfma32Shape {
@@ -220,7 +232,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ x
                                                      float *__restrict__ partial, int64_t part_stride_rows,
                                                      const int *__restrict__ done) {
   using S = Mfma32Shape<D>;
-  __shared__ float4 sb[2][S::LF4];
+  __shared__ float4 sb[2][kStage32 * S::LF4];
   // FP64 running sums, one slot per lane and value (only its own lane touches
   // a slot, so plain read-add-write keeps the summation order): held in LDS,
   // they leave the registers to the arithmetic
@@ -253,17 +265,21 @@ __global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ x
   }
 
   // thread t stages float4s t, t + 256, ... of a chunk: the K operand first,
-  // then V into rows of VS float4s
+  // then V into rows of VS float4s; a stage is kStage32 consecutive chunks,
+  // one barrier each
   constexpr int NST = (S::GF4 + 255) / 256;
   auto stage_dst = [&](int u) { return u < S::KF4 ? u : S::KF4 + ((u - S::KF4) >> 2) * S::VS + ((u - S::KF4) & 3); };
   auto chunk_src = [&](int c, int u) -> float4 {
     return u < S::KF4 ? KC[(int64_t)c * S::KF4 + u] : VC[(int64_t)c * 128 + (u - S::KF4)];
   };
-  if (c0 < c1) {
 #pragma unroll
-    for (int i = 0; i < NST; ++i) {
-      const int u = t + 256 * i;
-      if (u < S::GF4) sb[0][stage_dst(u)] = chunk_src(c0, u);
+  for (int cc = 0; cc < kStage32; ++cc) {
+    if (c0 + cc < c1) {
+#pragma unroll
+      for (int i = 0; i < NST; ++i) {
+        const int u = t + 256 * i;
+        if (u < S::GF4) sb[0][cc * S::LF4 + stage_dst(u)] = chunk_src(c0 + cc, u);
+      }
     }
   }
   __syncthreads();
@@ -274,76 +290,89 @@ __global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ x
 #pragma unroll
     for (int g = 0; g < S::NG; ++g) tot[r][g][0][lane] = tot[r][g][1][lane] = 0.0;
 
+  floatx4 acc[RB][S::NG];
+  // one chunk of 32 columns from its LDS buffer
+  auto chunk = [&](int c, const float4 *cb) {
+    // per-lane bases; every read below is at a constant offset from them
+    const float *sK = reinterpret_cast<const float *>(cb) + h * 32 + li;
+    const float4 *sV = cb + S::KF4 + 4 * h * S::VS + (lane & 3);
+    float ka[S::NK];
+#pragma unroll
+    for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
+    floatx16 e[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < S::NK; ++kk) e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
+      // no clamp: the expanded squared distance exceeds zero only by its rounding
+#pragma unroll
+      for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
+      if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
+        // an empty volatile asm keeps this a branch: if-converted into selects
+        // it would cost sixteen VALU instructions on every tile
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
+      const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int g = 0; g < S::NG; ++g) acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
+    }
+  };
+
   for (int c = c0; c < c1;) {
+    // groups start kFlush32 (a multiple of kStage32) chunks apart, so a stage
+    // never crosses a group boundary
     const int gend = min(c1, c + kFlush32);
-    floatx4 acc[RB][S::NG];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (; c < gend; ++c) {
-      const int buf = (c - c0) & 1;
-      const bool more = c + 1 < c1;
-      float4 pre[NST];  // next chunk, stored after this one's arithmetic
+    for (; c < gend; c += kStage32) {
+      const int buf = ((c - c0) / kStage32) & 1;
+      const int cn = c + kStage32;  // first chunk of the next stage
+      float4 pre[kStage32][NST];   // the next stage, stored after this one's arithmetic
 #pragma unroll
-      for (int i = 0; i < NST; ++i) {
-        const int u = t + 256 * i;
-        pre[i] = (more && u < S::GF4) ? chunk_src(c + 1, u) : float4{0.f, 0.f, 0.f, 0.f};
-      }
-      // per-lane bases; every read below is at a constant offset from them
-      const float *sK = reinterpret_cast<const float *>(sb[buf]) + h * 32 + li;
-      const float4 *sV = sb[buf] + S::KF4 + 4 * h * S::VS + (lane & 3);
-      float ka[S::NK];
-#pragma unroll
-      for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
-      floatx16 e[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < S::NK; ++kk) e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
-        // no clamp: the expanded squared distance exceeds zero only by its rounding
-#pragma unroll
-        for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
-        if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
-          // an empty volatile asm keeps this a branch: if-converted into selects
-          // it would cost sixteen VALU instructions on every tile
-          asm volatile("" ::: "memory");
-#pragma unroll
-          for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
-        const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-          for (int g = 0; g < S::NG; ++g) acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
-      }
-      if (more) {
+      for (int cc = 0; cc < kStage32; ++cc)
 #pragma unroll
         for (int i = 0; i < NST; ++i) {
           const int u = t + 256 * i;
-          if (u < S::GF4) sb[buf ^ 1][stage_dst(u)] = pre[i];
+          pre[cc][i] = (cn + cc < c1 && u < S::GF4) ? chunk_src(cn + cc, u) : float4{0.f, 0.f, 0.f, 0.f};
         }
+#pragma unroll
+      for (int cc = 0; cc < kStage32; ++cc)
+        if (c + cc < gend) chunk(c + cc, sb[buf] + cc * S::LF4);
+      if (cn < c1) {
+#pragma unroll
+        for (int cc = 0; cc < kStage32; ++cc)
+#pragma unroll
+          for (int i = 0; i < NST; ++i) {
+            const int u = t + 256 * i;
+            if (cn + cc < c1 && u < S::GF4) sb[buf ^ 1][cc * S::LF4 + stage_dst(u)] = pre[cc][i];
+          }
       }
       __syncthreads();
     }
-    // the two lane halves hold the same outputs over different columns: half h
-    // keeps rows h and 2 + h and adds the partner half's partial of them
-    // (__builtin_amdgcn_permlane32_swap would do this in one instruction, but
-    // this compiler mistranslates it on MFMA result registers)
+    // the two lane halves hold the same outputs over different columns: after a
+    // swap of rows (0, 1) and one of rows (2, 3), each sum of the pair leaves
+    // half h with the full row h and the full row 2 + h
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int g = 0; g < S::NG; ++g) {
-        const float keep0 = h ? acc[r][g][1] : acc[r][g][0], send0 = h ? acc[r][g][0] : acc[r][g][1];
-        const float keep1 = h ? acc[r][g][3] : acc[r][g][2], send1 = h ? acc[r][g][2] : acc[r][g][3];
-        tot[r][g][0][lane] += (double)(keep0 + __shfl_xor(send0, 32));
-        tot[r][g][1][lane] += (double)(keep1 + __shfl_xor(send1, 32));
+        float a0 = acc[r][g][0], a1 = acc[r][g][1], a2 = acc[r][g][2], a3 = acc[r][g][3];
+        permlane32_swap(a0, a1);
+        permlane32_swap(a2, a3);
+        tot[r][g][0][lane] += (double)(a0 + a1);
+        tot[r][g][1][lane] += (double)(a2 + a3);
       }
   }
 
