@@ -243,8 +243,18 @@ __global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ x
   const int h = lane >> 5;   // lane half
   const int li = lane & 31;  // row of the 32x32 tile (distance product) / column slot of the K operand
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int rb0 = ((int)blockIdx.x * 4 + wave) * RB;  // first 32-row block of this wave
-  const int c0 = (int)blockIdx.y * chunks_per_split;
+  // workgroups go to the 8 XCDs round robin by linear id, and each XCD has its
+  // own L2: with a multiple of 8 splits, XCD x runs splits x, x + 8, ... for
+  // every row group, so its L2 fetches only those splits' columns
+  int rg = (int)blockIdx.x, split = (int)blockIdx.y;
+  if (gridDim.y % 8 == 0) {
+    const int lin = (int)blockIdx.x + (int)gridDim.x * (int)blockIdx.y;
+    const int k = lin / 8;
+    rg = k % (int)gridDim.x;
+    split = lin % 8 + 8 * (k / (int)gridDim.x);
+  }
+  const int rb0 = (rg * 4 + wave) * RB;  // first 32-row block of this wave
+  const int c0 = split * chunks_per_split;
   const int c1 = min(nchunks, c0 + chunks_per_split);
 
   // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ x
 
   // lane l holds rows 4 ((l % 32) / 4) + h + 2 s (s = 0, 1) and outputs n = 4 g + l % 4;
   // the weighted kernel sum O[.][D] sits in the lane of the same quad with l % 4 = D % 4
-  float *out = partial + (int64_t)blockIdx.y * part_stride_rows * 16;
+  float *out = partial + (int64_t)split * part_stride_rows * 16;
   const int src = (lane & ~3) | (D & 3);
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
