@@ -110,13 +110,17 @@ typedef struct vds_diag {
 } vds_diag;
 
 /* Pair-kernel launch shape (chosen by vds_autotune or set by hand; a new
- * context starts with VDS_PAIR_MFMA32, 2 row blocks per wave, 16 splits).  The
- * FP16-split forms are opt-in: they keep about 22 bits, not FP32's 24. */
+ * context starts with VDS_PAIR_MFMA32, 2 row blocks per wave, 4 workgroups per
+ * compute unit).  The FP16-split forms are opt-in: they keep about 22 bits, not
+ * FP32's 24. */
 typedef struct vds_tuning {
   int32_t impl;          /* one of the VDS_PAIR_* implementations */
   int32_t rows_per_wave; /* MFMA forms: row blocks per wavefront (16 rows each: 1, 2 or 4;
                           * VDS_PAIR_MFMA32: 32 rows each, 1 or 2) */
-  int32_t col_splits;    /* column ranges summed separately, then reduced (>= 1) */
+  int32_t col_splits;    /* 1..32.  Column ranges summed separately, then reduced; for
+                          * VDS_PAIR_MFMA32 the workgroups per compute unit of its balanced
+                          * grid, whose workgroups take equal runs of (row group, column
+                          * chunk) work and leave one partial sum per row group they cover */
   int32_t reserved;
 } vds_tuning;
 

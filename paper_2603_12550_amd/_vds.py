@@ -24,7 +24,7 @@ _lib = C.CDLL(LIB_PATH)
 VDS_OK, VDS_ERR_ARG, VDS_ERR_HIP, VDS_ERR_NOMEM, VDS_ERR_NOT_CONVERGED, VDS_ERR_STATE = range(6)
 VDS_HOOKEAN, VDS_FENE = 0, 1
 VDS_EXPLICIT, VDS_IMPLICIT = 0, 1
-VDS_PAIR_MFMA, VDS_PAIR_VALU, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL = 0, 1, 2, 3
+VDS_PAIR_MFMA, VDS_PAIR_VALU, VDS_PAIR_MFMA_F16X2, VDS_PAIR_MFMA_F16X2_ALL, VDS_PAIR_MFMA32 = 0, 1, 2, 3, 4
 VDS_TIMER_PAIR, VDS_TIMER_GEMM, VDS_TIMER_KGEMM, VDS_TIMER_PROJ = range(4)
 STATUS_NAMES = {0: "VDS_OK", 1: "VDS_ERR_ARG", 2: "VDS_ERR_HIP", 3: "VDS_ERR_NOMEM",
                 4: "VDS_ERR_NOT_CONVERGED", 5: "VDS_ERR_STATE"}
@@ -220,7 +220,7 @@ class Context:
             self.ctx = None
 
     # -- tuning / timing --
-    def set_tuning(self, impl=VDS_PAIR_MFMA_F16X2_ALL, rows_per_wave=2, col_splits=8):
+    def set_tuning(self, impl=VDS_PAIR_MFMA32, rows_per_wave=2, col_splits=4):
         t = vds_tuning(impl, rows_per_wave, col_splits, 0)
         _check(_lib.vds_set_tuning(self.ctx, C.byref(t)), self.ctx)
 

@@ -308,16 +308,16 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
   prep_body(p, blockIdx.x, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, f16, cmean);
 }
 
-// Component n of row I summed over the column splits in split order, in FP64.
-__device__ inline double sum_splits(const EvalParams &p, const float *__restrict__ partial, int splits, int64_t I,
-                                    int n) {
-  return ordered_sum<double>(partial + I * 16 + n, splits, p.Ppad * 16);
+// Component n of row I summed over its partial-sum slots in slot order, in FP64.
+__device__ inline double sum_splits(const EvalParams &p, const float *__restrict__ partial, const SplitMap &splits,
+                                    int64_t I, int n) {
+  return ordered_sum<double>(partial + I * 16 + n, splits.count(I), p.Ppad * 16);
 }
 
 // Pass-A finalisation: S_I = w_I + sum_{J != I} w_J e_IJ,
 // term1_I = -(1/h^2) sum_J w_J e_IJ (x_I - x_J) / S_I, and the pass-B operand
 // with weights w_J / S_J.
-__device__ void finalize_a_body(const EvalParams &p, int64_t lb, const float *__restrict__ partial, int splits,
+__device__ void finalize_a_body(const EvalParams &p, int64_t lb, const float *__restrict__ partial, const SplitMap &splits,
                                 const float *__restrict__ xc, const float *__restrict__ wv, float *__restrict__ S,
                                 float *__restrict__ t1, float *__restrict__ VB) {
   const int64_t I = group_particle(lb);
@@ -342,7 +342,7 @@ __device__ void finalize_a_body(const EvalParams &p, int64_t lb, const float *__
   store_v(p, VB, I, n, v);  // wb <= 1, so the FP16 form needs no normalisation
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, int splits,
+__global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const float *__restrict__ partial, SplitMap splits,
                                                           const float *__restrict__ xc, const float *__restrict__ wv,
                                                           float *__restrict__ S, float *__restrict__ t1,
                                                           float *__restrict__ VB, const int *__restrict__ done) {
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize_a(EvalParams p, const fl
 // operands as the prep kernel would: the same lanes hold the same coordinates
 // there.
 __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs, const float *__restrict__ partial,
-                             int splits, const float *xc, const float *__restrict__ t1,
+                             const SplitMap &splits, const float *xc, const float *__restrict__ t1,
                              const float *__restrict__ S, const float *wv, const float *qin,
                              const float *__restrict__ qs, float *out, float *out2, double *__restrict__ redp,
                              float *__restrict__ blockmax, const PackOps &pack, int *fene_out) {
@@ -481,7 +481,7 @@ __device__ void combine_body(const EvalParams &p, int64_t lb, int mode, int obs,
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_combine(EvalParams p, int mode, int obs,
-                                                       const float *__restrict__ partial, int splits,
+                                                       const float *__restrict__ partial, SplitMap splits,
                                                        const float *xc, const float *__restrict__ t1,
                                                        const float *__restrict__ S, const float *wv,
                                                        const float *qin, const float *__restrict__ qs,
@@ -722,12 +722,12 @@ __global__ __launch_bounds__(kRedBlock) void k_pack_qk(EvalParams p, const float
   }
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_density_out(const float *__restrict__ partial, int splits,
+__global__ __launch_bounds__(kRedBlock) void k_density_out(const float *__restrict__ partial, SplitMap splits,
                                                            int64_t stride_rows, int64_t ny, int D, float norm,
                                                            float *__restrict__ f) {
   const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
   if (I >= ny) return;
-  f[I] = ordered_sum<float>(partial + I * 16 + D, splits, stride_rows * 16) * norm;
+  f[I] = ordered_sum<float>(partial + I * 16 + D, splits.count(I), stride_rows * 16) * norm;
 }
 
 // ---- batched ensembles: the same bodies, per ensemble ----
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_finalize_a(BatchView b, con
                                                                 float *__restrict__ t1, float *__restrict__ VB) {
   const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
   const int64_t o = d.pad_off;
-  finalize_a_body(d.p, blockIdx.x - d.blk16, partial + o * 16, 1, xc + o * b.D, wv + o, S + o, t1 + o * b.D,
+  finalize_a_body(d.p, blockIdx.x - d.blk16, partial + o * 16, SplitMap{}, xc + o * b.D, wv + o, S + o, t1 + o * b.D,
                   VB + o * 16);
 }
 
@@ -774,7 +774,7 @@ __global__ __launch_bounds__(kRedBlock) void k_batch_explicit(BatchView b, const
                                                               const float *__restrict__ wv, float *q) {
   const EnsDesc &d = b.ens[b.blk16_ens[blockIdx.x]];
   const int64_t o = d.pad_off;
-  combine_body(d.p, blockIdx.x - d.blk16, MODE_EXPLICIT, 0, partial + o * 16, 1, xc + o * b.D, t1 + o * b.D, S + o,
+  combine_body(d.p, blockIdx.x - d.blk16, MODE_EXPLICIT, 0, partial + o * 16, SplitMap{}, xc + o * b.D, t1 + o * b.D, S + o,
                wv + o, q + d.q_off, nullptr, q + d.q_off, nullptr, nullptr, nullptr, PackOps{}, nullptr);
 }
 
@@ -810,11 +810,11 @@ void launch_prep(const EvalParams &p, const float *q, const float *w, const doub
   k_prep<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, q, w, meanp, nmeanp, xc, wv, QB, KA, VA, wscale, ops, done,
                                                     cmean, begin);
 }
-void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
+void launch_finalize_a(const EvalParams &p, const float *partial, const SplitMap &splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s) {
   k_finalize_a<<<nblocks(p.Ppad * 16), kRedBlock, 0, s>>>(p, partial, splits, xc, wv, S, t1, VB, done);
 }
-void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
+void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, const SplitMap &splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
                     float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s,
                     const PackOps *pack, int *fene_out) {
@@ -847,7 +847,7 @@ void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const 
 void launch_pack_qk(const EvalParams &p, const float *xc, float *QB, float *KA, hipStream_t s) {
   k_pack_qk<<<nblocks(p.Ppad), kRedBlock, 0, s>>>(p, xc, QB, KA);
 }
-void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm, float *f,
+void launch_density_out(const EvalParams &p, const float *partial, const SplitMap &splits, int64_t ny, float norm, float *f,
                         hipStream_t s) {
   k_density_out<<<nblocks(ny), kRedBlock, 0, s>>>(partial, splits, p.Ppad, ny, p.D, norm, f);
 }

@@ -50,6 +50,9 @@
 // the difference sum, but for an isolated particle it dominates the kernel sum
 // and would swamp its neighbours' contributions in FP32.  The caller adds the
 // self weight back in FP64.
+#include <algorithm>
+#include <type_traits>
+
 #include "vds_internal.h"
 
 namespace vds {
@@ -225,13 +228,30 @@ struct Mfma32Shape {
   static constexpr int GF4 = KF4 + 128;         // float4s of one chunk in global memory
 };
 
+// Largest row-norm term kappa |x_I|^2 that a row block may fold out of the
+// exponent (see k_pair_mfma32): e' <= 2^100, and a group of 128 products
+// e' V stays far below the FP32 range.
+constexpr float kFoldMax = 100.f;
+
+// Waves per SIMD the FP32 32x32 kernel is compiled for: four (128 VGPRs) where
+// the workgroup's LDS lets four workgroups share a compute unit.
 template <int D, int RB>
-__global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ xr, int nrb32,
+constexpr int mfma32_waves() {
+  return sizeof(double) * 4 * RB * Mfma32Shape<D>::NG * 2 * 64 + sizeof(float4) * 2 * kStage32 * Mfma32Shape<D>::LF4 <=
+                 40960
+             ? 4
+             : 3;
+}
+
+template <int D, int RB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_waves<D, RB>()))) void k_pair_mfma32(const float *__restrict__ xr, int nrb32,
                                                      const float4 *__restrict__ KC, const float4 *__restrict__ VC,
-                                                     int nchunks, int chunks_per_split, int exclude_self, float kappa,
+                                                     SplitMap map, int exclude_self, float kappa,
                                                      float *__restrict__ partial, int64_t part_stride_rows,
                                                      const int *__restrict__ done) {
   using S = Mfma32Shape<D>;
+  // odd D: the last distance step holds only the row-norm slot and padding
+  constexpr bool kFold = (D % 2) == 1;
   __shared__ float4 sb[2][kStage32 * S::LF4];
   // FP64 running sums, one slot per lane and value (only its own lane touches
   // a slot, so plain read-add-write keeps the summation order): held in LDS,
@@ -244,164 +264,194 @@ __global__ __launch_bounds__(256) void k_pair_mfma32(const float *__restrict__ x
   const int li = lane & 31;  // row of the 32x32 tile (distance product) / column slot of the K operand
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   // workgroups go to the 8 XCDs round robin by linear id, and each XCD has its
-  // own L2: with a multiple of 8 splits, XCD x runs splits x, x + 8, ... for
-  // every row group, so its L2 fetches only those splits' columns
-  int rg = (int)blockIdx.x, split = (int)blockIdx.y;
-  if (gridDim.y % 8 == 0) {
-    const int lin = (int)blockIdx.x + (int)gridDim.x * (int)blockIdx.y;
-    const int k = lin / 8;
-    rg = k % (int)gridDim.x;
-    split = lin % 8 + 8 * (k / (int)gridDim.x);
-  }
-  const int rb0 = (rg * 4 + wave) * RB;  // first 32-row block of this wave
-  const int c0 = split * chunks_per_split;
-  const int c1 = min(nchunks, c0 + chunks_per_split);
-
-  // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
-  // row norm term -kappa |x_I|^2 (k == D + 1), 0 beyond
-  float qv[RB][S::NK];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    const int rb = rb0 + r < nrb32 ? rb0 + r : 0;  // waves past the rows compute on row block 0, unwritten
-    const float *x = xr + ((int64_t)rb * 32 + li) * D;
-    float nrm = 0.f;
-#pragma unroll
-    for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
-#pragma unroll
-    for (int kk = 0; kk < S::NK; ++kk) {
-      const int k = 2 * kk + h;
-      qv[r][kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? -kappa * nrm : 0.f));
-    }
-  }
-
-  // thread t stages float4s t, t + 256, ... of a chunk: the K operand first,
-  // then V into rows of VS float4s; a stage is kStage32 consecutive chunks,
-  // one barrier each
+  // own L2: with a multiple of 8 runs, XCD x takes the consecutive runs
+  // x G / 8 .. (x + 1) G / 8 - 1, i.e. a band of row groups against all columns
+  const int G = (int)gridDim.x;
+  const int L = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int64_t nch = map.nch;
+  const int64_t u_end = map.run_start(L + 1);
+  double(*tot)[S::NG][2][64] = stot[wave];
   constexpr int NST = (S::GF4 + 255) / 256;
   auto stage_dst = [&](int u) { return u < S::KF4 ? u : S::KF4 + ((u - S::KF4) >> 2) * S::VS + ((u - S::KF4) & 3); };
   auto chunk_src = [&](int c, int u) -> float4 {
     return u < S::KF4 ? KC[(int64_t)c * S::KF4 + u] : VC[(int64_t)c * 128 + (u - S::KF4)];
   };
-#pragma unroll
-  for (int cc = 0; cc < kStage32; ++cc) {
-    if (c0 + cc < c1) {
-#pragma unroll
-      for (int i = 0; i < NST; ++i) {
-        const int u = t + 256 * i;
-        if (u < S::GF4) sb[0][cc * S::LF4 + stage_dst(u)] = chunk_src(c0 + cc, u);
-      }
-    }
-  }
-  __syncthreads();
 
-  double(*tot)[S::NG][2][64] = stot[wave];
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-#pragma unroll
-    for (int g = 0; g < S::NG; ++g) tot[r][g][0][lane] = tot[r][g][1][lane] = 0.0;
+  // one segment per row group this run covers: chunks [c0, c1) of row group rg
+  for (int64_t u = map.run_start(L); u < u_end;) {
+    const int64_t rg = u / nch;
+    const int c0 = (int)(u - rg * nch);
+    const int c1 = (int)min(nch, u_end - rg * nch);
+    const int slot = (int)(L - map.run_of(rg * nch));
+    u = rg * nch + c1;
+    const int rb0 = ((int)rg * 4 + wave) * RB;  // first 32-row block of this wave
 
-  floatx4 acc[RB][S::NG];
-  // one chunk of 32 columns from its LDS buffer
-  auto chunk = [&](int c, const float4 *cb) {
-    // per-lane bases; every read below is at a constant offset from them
-    const float *sK = reinterpret_cast<const float *>(cb) + h * 32 + li;
-    const float4 *sV = cb + S::KF4 + 4 * h * S::VS + (lane & 3);
-    float ka[S::NK];
-#pragma unroll
-    for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
-    floatx16 e[RB];
+    // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
+    // row norm term -kappa |x_I|^2 (k == D + 1), 0 beyond.  With kFold, a wave
+    // whose row-norm terms all lie within kFoldMax leaves out the last step (the
+    // row-norm slot): its exponents are t + kappa |x_I|^2, and the factor
+    // 2^(-kappa |x_I|^2) of each row is applied to its sums in FP64 at the end
+    float qv[RB][S::NK];
+    bool in_range = true;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
+      const int rb = rb0 + r < nrb32 ? rb0 + r : 0;  // waves past the rows compute on row block 0, unwritten
+      const float *x = xr + ((int64_t)rb * 32 + li) * D;
+      float nrm = 0.f;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
+      for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
+      const float rn = -kappa * nrm;
 #pragma unroll
-      for (int kk = 0; kk < S::NK; ++kk) e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
-      // no clamp: the expanded squared distance exceeds zero only by its rounding
+      for (int kk = 0; kk < S::NK; ++kk) {
+        const int k = 2 * kk + h;
+        qv[r][kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? rn : 0.f));
+      }
+      in_range = in_range && rn >= -kFoldMax;
+    }
+    const int fold = kFold ? __builtin_amdgcn_readfirstlane(__all(in_range ? 1 : 0) ? 1 : 0) : 0;
+
+    // thread t stages float4s t, t + 256, ... of a chunk: the K operand first,
+    // then V into rows of VS float4s; a stage is kStage32 consecutive chunks,
+    // one barrier each
 #pragma unroll
-      for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
-      if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
-        // an empty volatile asm keeps this a branch: if-converted into selects
-        // it would cost sixteen VALU instructions on every tile
-        asm volatile("" ::: "memory");
+    for (int cc = 0; cc < kStage32; ++cc) {
+      if (c0 + cc < c1) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
+        for (int i = 0; i < NST; ++i) {
+          const int v = t + 256 * i;
+          if (v < S::GF4) sb[0][cc * S::LF4 + stage_dst(v)] = chunk_src(c0 + cc, v);
+        }
       }
     }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
-      const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int g = 0; g < S::NG; ++g) acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
-    }
-  };
-
-  for (int c = c0; c < c1;) {
-    // groups start kFlush32 (a multiple of kStage32) chunks apart, so a stage
-    // never crosses a group boundary
-    const int gend = min(c1, c + kFlush32);
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (; c < gend; c += kStage32) {
-      const int buf = ((c - c0) / kStage32) & 1;
-      const int cn = c + kStage32;  // first chunk of the next stage
-      float4 pre[kStage32][NST];   // the next stage, stored after this one's arithmetic
+      for (int g = 0; g < S::NG; ++g) tot[r][g][0][lane] = tot[r][g][1][lane] = 0.0;
+    __syncthreads();
+
+    floatx4 acc[RB][S::NG];
+    // one chunk of 32 columns from its LDS buffer; NKS distance steps
+    auto chunk = [&](int c, const float4 *cb, auto nks) {
+      constexpr int NKS = decltype(nks)::value;
+      // per-lane bases; every read below is at a constant offset from them
+      const float *sK = reinterpret_cast<const float *>(cb) + h * 32 + li;
+      const float4 *sV = cb + S::KF4 + 4 * h * S::VS + (lane & 3);
+      float ka[S::NK];
 #pragma unroll
-      for (int cc = 0; cc < kStage32; ++cc)
+      for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
+      floatx16 e[RB];
 #pragma unroll
-        for (int i = 0; i < NST; ++i) {
-          const int u = t + 256 * i;
-          pre[cc][i] = (cn + cc < c1 && u < S::GF4) ? chunk_src(cn + cc, u) : float4{0.f, 0.f, 0.f, 0.f};
+      for (int r = 0; r < RB; ++r) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < NKS; ++kk)
+          e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
+        // no clamp: the expanded squared distance exceeds zero only by its rounding
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
+        if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
+          // an empty volatile asm keeps this a branch: if-converted into selects
+          // it would cost sixteen VALU instructions on every tile
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
         }
+      }
 #pragma unroll
-      for (int cc = 0; cc < kStage32; ++cc)
-        if (c + cc < gend) chunk(c + cc, sb[buf] + cc * S::LF4);
-      if (cn < c1) {
+      for (int v = 0; v < 16; ++v) {
+        const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
+        const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int g = 0; g < S::NG; ++g)
+            acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
+      }
+    };
+
+    // the chunk loop, in two copies (all steps, or the folded wave's NK - 1);
+    // both pass the same barriers
+    auto chunks = [&](auto nks) {
+    for (int c = c0; c < c1;) {
+      // groups start kFlush32 (a multiple of kStage32) chunks apart, so a stage
+      // never crosses a group boundary
+      const int gend = min(c1, c + kFlush32);
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (; c < gend; c += kStage32) {
+        const int buf = ((c - c0) / kStage32) & 1;
+        const int cn = c + kStage32;  // first chunk of the next stage
+        float4 pre[kStage32][NST];    // the next stage, stored after this one's arithmetic
 #pragma unroll
         for (int cc = 0; cc < kStage32; ++cc)
 #pragma unroll
           for (int i = 0; i < NST; ++i) {
-            const int u = t + 256 * i;
-            if (cn + cc < c1 && u < S::GF4) sb[buf ^ 1][cc * S::LF4 + stage_dst(u)] = pre[cc][i];
+            const int v = t + 256 * i;
+            pre[cc][i] = (cn + cc < c1 && v < S::GF4) ? chunk_src(cn + cc, v) : float4{0.f, 0.f, 0.f, 0.f};
           }
+#pragma unroll
+        for (int cc = 0; cc < kStage32; ++cc)
+          if (c + cc < gend) chunk(c + cc, sb[buf] + cc * S::LF4, nks);
+        if (cn < c1) {
+#pragma unroll
+          for (int cc = 0; cc < kStage32; ++cc)
+#pragma unroll
+            for (int i = 0; i < NST; ++i) {
+              const int v = t + 256 * i;
+              if (cn + cc < c1 && v < S::GF4) sb[buf ^ 1][cc * S::LF4 + stage_dst(v)] = pre[cc][i];
+            }
+        }
+        // every stage ends at a barrier, the segment's last one too: the next
+        // segment may overwrite either buffer
+        __syncthreads();
       }
-      __syncthreads();
+      // the two lane halves hold the same outputs over different columns: after a
+      // swap of rows (0, 1) and one of rows (2, 3), each sum of the pair leaves
+      // half h with the full row h and the full row 2 + h
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int g = 0; g < S::NG; ++g) {
+          float a0 = acc[r][g][0], a1 = acc[r][g][1], a2 = acc[r][g][2], a3 = acc[r][g][3];
+          permlane32_swap(a0, a1);
+          permlane32_swap(a2, a3);
+          tot[r][g][0][lane] += (double)(a0 + a1);
+          tot[r][g][1][lane] += (double)(a2 + a3);
+        }
     }
-    // the two lane halves hold the same outputs over different columns: after a
-    // swap of rows (0, 1) and one of rows (2, 3), each sum of the pair leaves
-    // half h with the full row h and the full row 2 + h
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int g = 0; g < S::NG; ++g) {
-        float a0 = acc[r][g][0], a1 = acc[r][g][1], a2 = acc[r][g][2], a3 = acc[r][g][3];
-        permlane32_swap(a0, a1);
-        permlane32_swap(a2, a3);
-        tot[r][g][0][lane] += (double)(a0 + a1);
-        tot[r][g][1][lane] += (double)(a2 + a3);
-      }
-  }
+    };
+    if (fold)  // scalar branch
+      chunks(std::integral_constant<int, S::NK - 1>{});
+    else
+      chunks(std::integral_constant<int, S::NK>{});
 
-  // lane l holds rows 4 ((l % 32) / 4) + h + 2 s (s = 0, 1) and outputs n = 4 g + l % 4;
-  // the weighted kernel sum O[.][D] sits in the lane of the same quad with l % 4 = D % 4
-  float *out = partial + (int64_t)split * part_stride_rows * 16;
-  const int src = (lane & ~3) | (D & 3);
+    // lane l holds rows 4 ((l % 32) / 4) + h + 2 s (s = 0, 1) and outputs n = 4 g + l % 4;
+    // the weighted kernel sum O[.][D] sits in the lane of the same quad with l % 4 = D % 4
+    float *out = partial + (int64_t)slot * part_stride_rows * 16;
+    const int src = (lane & ~3) | (D & 3);
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    if (rb0 + r >= nrb32) break;
+    for (int r = 0; r < RB; ++r) {
+      if (rb0 + r >= nrb32) break;
 #pragma unroll
-    for (int sidx = 0; sidx < 2; ++sidx) {
-      const int64_t row = (int64_t)(rb0 + r) * 32 + 4 * (li >> 2) + h + 2 * sidx;
-      const double sv = tot[r][D / 4][sidx][src];
+      for (int sidx = 0; sidx < 2; ++sidx) {
+        const int64_t row = (int64_t)(rb0 + r) * 32 + 4 * (li >> 2) + h + 2 * sidx;
+        double f = 1.0;  // the factor a folded wave's sums still carry
+        if (fold) {
+          float nrm = 0.f;
 #pragma unroll
-      for (int g = 0; g < S::NG; ++g) {
-        const int n = 4 * g + (lane & 3);
-        if (n < D) out[row * 16 + n] = (float)((double)xr[row * D + n] * sv - tot[r][g][sidx][lane]);
-        else if (n == D) out[row * 16 + n] = (float)sv;
+          for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(xr[row * D + a], xr[row * D + a], nrm);
+          f = exp2((double)(-kappa * nrm));
+        }
+        const double sv = f * tot[r][D / 4][sidx][src];
+#pragma unroll
+        for (int g = 0; g < S::NG; ++g) {
+          const int n = 4 * g + (lane & 3);
+          if (n < D) out[row * 16 + n] = (float)((double)xr[row * D + n] * sv - f * tot[r][g][sidx][lane]);
+          else if (n == D) out[row * 16 + n] = (float)sv;
+        }
       }
     }
   }
@@ -834,14 +884,55 @@ static void launch_mfma16_k(int rb, dim3 grid, const PairF16Ops &ops, int nrb, i
 }
 
 template <int D>
-static void launch_mfma32_d(int rb, dim3 grid, const float *xr, int nrb32, const float *KC, const float *VC,
-                            int nch, int cps, int ex, float kappa, float *partial, int64_t stride, const int *done,
-                            hipStream_t s) {
+static void launch_mfma32_d(int rb, const float *xr, int nrb32, const float *KC, const float *VC, const SplitMap &map,
+                            int ex, float kappa, float *partial, int64_t stride, const int *done, hipStream_t s) {
   const float4 *kc = reinterpret_cast<const float4 *>(KC), *vc = reinterpret_cast<const float4 *>(VC);
+  const dim3 grid((unsigned)map.G);
   if (rb == 1)
-    k_pair_mfma32<D, 1><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, nch, cps, ex, kappa, partial, stride, done);
+    k_pair_mfma32<D, 1><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, map, ex, kappa, partial, stride, done);
   else
-    k_pair_mfma32<D, 2><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, nch, cps, ex, kappa, partial, stride, done);
+    k_pair_mfma32<D, 2><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, map, ex, kappa, partial, stride, done);
+}
+
+namespace {
+
+// Compute units of the current device (256 on MI355X), looked up once per device.
+int device_cu_count() {
+  constexpr int kDevs = 64;
+  static int cache[kDevs] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return 256;
+  if (cache[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+}  // namespace
+
+SplitMap pair_split_map(const vds_tuning &t, int64_t nrow_blocks, int64_t ncol_chunks) {
+  SplitMap m;
+  if (t.impl != VDS_PAIR_MFMA32) {
+    m.splits = t.col_splits;
+    return m;
+  }
+  // rows in blocks of 32, four waves of RB blocks per row group; columns in chunks of 32
+  const int rb = t.rows_per_wave;
+  const int64_t nrb32 = nrow_blocks / 2;
+  m.rows_per_group = 4 * rb * 32;
+  m.n_rg = (nrb32 + 4 * rb - 1) / (4 * rb);
+  m.nch = (ncol_chunks + 1) / 2;
+  m.splits = kMaxSplits;
+  // col_splits workgroups per compute unit; runs of at least qmin units, so
+  // that at most kMaxSplits runs meet in one row group
+  const int64_t U = m.units();
+  const int64_t qmin = (m.nch + kMaxSplits - 2) / (kMaxSplits - 1);
+  int64_t G = std::min<int64_t>((int64_t)t.col_splits * device_cu_count(), U / qmin);
+  if (G >= 8) G -= G % 8;
+  m.G = (int)std::max<int64_t>(G, 1);
+  return m;
 }
 
 void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64_t nrow_blocks, const float *KA,
@@ -853,19 +944,17 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
   const int64_t cps = (ncol_chunks + splits - 1) / splits;
   if (t.impl == VDS_PAIR_MFMA32) {
     // rows in blocks of 32 (nrow_blocks counts 16-row blocks of a multiple of 256 rows, so
-    // every workgroup of 4 waves x RB blocks is full); columns in chunks of 32, the last
+    // every row group of 4 waves x RB blocks is whole); columns in chunks of 32, the last
     // inside the padding (ncol_pad is a multiple of 256 columns), whose weights are zero
+    const SplitMap map = pair_split_map(t, nrow_blocks, ncol_chunks);
     const int rb = t.rows_per_wave;
     const int nrb32 = (int)(nrow_blocks / 2);
-    const int nch = (int)((ncol_chunks + 1) / 2);
-    const int cps32 = (nch + splits - 1) / splits;
-    dim3 grid((unsigned)((nrb32 + 4 * rb - 1) / (4 * rb)), (unsigned)splits);
     switch (D) {
-      case 3: launch_mfma32_d<3>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
-      case 6: launch_mfma32_d<6>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
-      case 9: launch_mfma32_d<9>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
-      case 12: launch_mfma32_d<12>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
-      default: launch_mfma32_d<15>(rb, grid, QB, nrb32, KA, VB, nch, cps32, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 3: launch_mfma32_d<3>(rb, QB, nrb32, KA, VB, map, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 6: launch_mfma32_d<6>(rb, QB, nrb32, KA, VB, map, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 9: launch_mfma32_d<9>(rb, QB, nrb32, KA, VB, map, ex, kappa, partial, part_stride_rows, done, s); break;
+      case 12: launch_mfma32_d<12>(rb, QB, nrb32, KA, VB, map, ex, kappa, partial, part_stride_rows, done, s); break;
+      default: launch_mfma32_d<15>(rb, QB, nrb32, KA, VB, map, ex, kappa, partial, part_stride_rows, done, s); break;
     }
     return;
   }

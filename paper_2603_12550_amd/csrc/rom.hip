@@ -97,7 +97,7 @@ __global__ void k_hydro(const float *__restrict__ Mbig, int R, EvalParams p, flo
 }
 
 // T_I = w_I / S_I + sum_{K != I} (w_K / S_K) e_IK from the pass-B partials, and 1/S.
-__global__ void k_rom_scalars(const float *__restrict__ part, int splits, int64_t Ppad, int64_t P, int D,
+__global__ void k_rom_scalars(const float *__restrict__ part, SplitMap splits, int64_t Ppad, int64_t P, int D,
                               const float *__restrict__ S, const float *__restrict__ wv, float *__restrict__ T,
                               float *__restrict__ invS) {
   const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -107,7 +107,7 @@ __global__ void k_rom_scalars(const float *__restrict__ part, int splits, int64_
     invS[I] = 0.f;
     return;
   }
-  const double o = ordered_sum<double>(part + I * 16 + D, splits, Ppad * 16);
+  const double o = ordered_sum<double>(part + I * 16 + D, splits.count(I), Ppad * 16);
   const double Si = (double)S[I];
   T[I] = (float)(o + (double)wv[I] / Si);
   invS[I] = (float)(1.0 / Si);
@@ -757,7 +757,7 @@ vds_status freeze(vds_rom r, const float *p) {
   // S and T at q~ (uniform weights), Q/K operands for Z
   eval_pass_a(c, r->qt, nullptr, nullptr);
   eval_pass_b(c, nullptr);
-  k_rom_scalars<<<nblk256(Ppad), 256, 0, s>>>(c->part, c->tune.col_splits, Ppad, P, c->ep.D, c->S, c->wv, r->T,
+  k_rom_scalars<<<nblk256(Ppad), 256, 0, s>>>(c->part, c->smap, Ppad, P, c->ep.D, c->S, c->wv, r->T,
                                               r->invS);
   // Y = Z B, in the FP16-split form when the context's pair kernels use it
   if (c->ep.vhalf) {

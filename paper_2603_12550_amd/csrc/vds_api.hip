@@ -97,6 +97,7 @@ void pair_pass(vds_ctx c, const float *V, const float *wscale, const int *done) 
 // with the pair implementation.
 void apply_tuning(vds_ctx c, const vds_tuning &t) {
   c->tune = t;
+  c->smap = pair_split_map(t, c->ep.Ppad / 16, ncol_chunks(c));
   c->ep.vhalf = (t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
   c->ep.qhalf = t.impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
   c->ep.f32x = t.impl == VDS_PAIR_MFMA32 ? 1 : 0;
@@ -107,7 +108,7 @@ void eval_pass_a(vds_ctx c, const float *q, const float *w, const int *done, boo
   if (centre) launch_mean_partials(e, q, w, c->meanp, done, nullptr, c->stream);
   launch_prep(e, q, w, c->meanp, c->nblk, c->xc, c->wv, c->QB, c->KA, c->VA, c->wscale, &c->f16, done, c->stream);
   pair_pass(c, c->VA, c->wscale, done);
-  launch_finalize_a(e, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
+  launch_finalize_a(e, c->part, c->smap, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
 }
 
 void eval_pass_b(vds_ctx c, const int *done) { pair_pass(c, c->VB, nullptr, done); }
@@ -238,7 +239,7 @@ void evaluate(vds_ctx c, const float *q, const float *w, int mode, bool obs, con
   const EvalParams &e = c->ep;
   eval_pass_a(c, q, w, done, centre);
   eval_pass_b(c, done);
-  launch_combine(e, mode, obs, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, q0, out, out2, c->redp,
+  launch_combine(e, mode, obs, c->part, c->smap, c->xc, c->t1, c->S, c->wv, q, q0, out, out2, c->redp,
                  c->blockmax, done, c->stream, nullptr, fene_flag(c));
   if (obs) launch_reduce_final(c->redp, c->nblk_comb, 12, c->redout, done, c->stream);
 }
@@ -501,10 +502,10 @@ void explicit_steps(vds_ctx c, float *q, const float *w, int nsteps) {
                   c->stream, c->cmean);
     }
     pair_pass(c, c->VA, c->wscale, nullptr);
-    launch_finalize_a(c->ep, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
+    launch_finalize_a(c->ep, c->part, c->smap, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
     eval_pass_b(c, nullptr);
     const bool pack = s + 1 < nsteps && (s + 1) % kQueueSteps != 0;
-    launch_combine(c->ep, MODE_EXPLICIT, false, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, q, nullptr,
+    launch_combine(c->ep, MODE_EXPLICIT, false, c->part, c->smap, c->xc, c->t1, c->S, c->wv, q, nullptr,
                    q, nullptr, c->redp, c->blockmax, nullptr, c->stream, pack ? &pk : nullptr, fene_flag(c));
   }
 }
@@ -596,10 +597,10 @@ vds_status implicit_steps(vds_ctx c, float *q, const float *w, int nsteps, StepC
                               c->stream);
         }
         pair_pass(c, c->VA, c->wscale, done);
-        launch_finalize_a(c->ep, c->part, c->tune.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
+        launch_finalize_a(c->ep, c->part, c->smap, c->xc, c->wv, c->S, c->t1, c->VB, done, c->stream);
         eval_pass_b(c, done);
         const PackOps pk{c->xc, c->wv, c->QB, c->KA, c->VA, c->f16, c->cmean};
-        launch_combine(c->ep, MODE_PICARD, false, c->part, c->tune.col_splits, c->xc, c->t1, c->S, c->wv, xin, q,
+        launch_combine(c->ep, MODE_PICARD, false, c->part, c->smap, c->xc, c->t1, c->S, c->wv, xin, q,
                        c->xb[m & 1], nullptr, c->redp, c->blockmax, done, c->stream, m + 1 < batch ? &pk : nullptr,
                        fene_flag(c));
       }
@@ -712,7 +713,7 @@ vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float
       launch_pair_pass(c->tune, e.KK, e.D, c->QB, nrb, c->KA, c->VA, ncol_chunks(c), e.Ppad, c->xc, false,
                        c->wscale, c->f16, c->part, e.Ppad, nullptr, c->stream, e.kappa);
     });
-    launch_density_out(e, c->part, c->tune.col_splits, nr, norm, f + r0, c->stream);
+    launch_density_out(e, c->part, pair_split_map(c->tune, nrb, ncol_chunks(c)), nr, norm, f + r0, c->stream);
   }
   return hip_check(c, hipGetLastError(), "launch");
 }
@@ -748,7 +749,10 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
   hipEvent_t a = get_event(c), b = get_event(c);
   vds_tuning best = c->tune;
   float best_ms = 1e30f;
-  const int splits_list[] = {1, 2, 4, 6, 8, 12, 16, 20, 24, 32};
+  // column splits, or for VDS_PAIR_MFMA32 workgroups per compute unit of its balanced grid
+  const std::vector<int> splits_list = c->tune.impl == VDS_PAIR_MFMA32
+                                           ? std::vector<int>{1, 2, 3, 4, 5, 6, 8, 12, 16}
+                                           : std::vector<int>{1, 2, 4, 6, 8, 12, 16, 20, 24, 32};
   const int rb_list[] = {1, 2, 4};
   std::vector<vds_tuning> cands;
   // the launch shape only: the implementation, and so the arithmetic, stays the caller's choice
@@ -769,7 +773,7 @@ vds_status vds_autotune(vds_ctx c, const float *q, const float *w) {
     // each candidate is timed with the finalisation that sums its column splits
     auto pass = [&] {
       pair_pass(c, c->VA, c->wscale, nullptr);
-      launch_finalize_a(c->ep, c->part, t.col_splits, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
+      launch_finalize_a(c->ep, c->part, c->smap, c->xc, c->wv, c->S, c->t1, c->VB, nullptr, c->stream);
     };
     pass();  // warm-up
     (void)hipEventRecord(a, c->stream);

@@ -29,7 +29,8 @@ struct vds_ctx_s {
   std::vector<double> H;
   hipStream_t stream = nullptr;
   vds::EvalParams ep{};
-  vds_tuning tune{VDS_PAIR_MFMA32, 2, 16, 0};
+  vds_tuning tune{VDS_PAIR_MFMA32, 2, 4, 0};
+  vds::SplitMap smap{};  // partial-sum slots of a pass over the particle rows under `tune`
   vds::Layout lay{};
   char *ws = nullptr;
   size_t ws_bytes = 0;

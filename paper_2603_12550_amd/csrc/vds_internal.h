@@ -138,6 +138,30 @@ __host__ __device__ inline int strided_count(int first, int end, int step) {
   return first < end ? (end - first + step - 1) / step : 0;
 }
 
+// Where a pair pass leaves its partial sums: partial[slot][row][16] for the
+// slots 0 .. count(row) - 1, which the consuming kernels add in slot order.
+// Fixed splits (G == 0): every row has `splits` slots, one per column range.
+// Balanced grid (VDS_PAIR_MFMA32): the row-group-major sequence of
+// (row group, column chunk) units is cut into G runs of equal length, one per
+// workgroup; a run leaves one slot in every row group it covers, and the runs
+// covering a row group fill its slots in run order.
+struct SplitMap {
+  int splits = 1;          // fixed splits; with G > 0, a bound on count()
+  int G = 0;               // runs (workgroups) of the balanced grid, 0 for fixed splits
+  int rows_per_group = 0;  // rows of one row group
+  int64_t nch = 0;         // column chunks per row group
+  int64_t n_rg = 0;        // row groups
+  __host__ __device__ int64_t units() const { return n_rg * nch; }
+  // first unit of run L, and the run holding unit u
+  __host__ __device__ int64_t run_start(int64_t L) const { return L * units() / G; }
+  __host__ __device__ int64_t run_of(int64_t u) const { return ((u + 1) * G - 1) / units(); }
+  __host__ __device__ int count(int64_t row) const {
+    if (G == 0) return splits;
+    const int64_t rg = row / rows_per_group;
+    return (int)(run_of((rg + 1) * nch - 1) - run_of(rg * nch) + 1);
+  }
+};
+
 // Operands the combine kernel packs for the next fixed-point iterate, as the
 // prep kernel would (VA == nullptr: no packing).  cmean holds the step's
 // centre in slots 0..D-1 and the weight maximum in slot 15, as the prep
@@ -166,6 +190,9 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
                       bool exclude_self, const float *wscale, const F16Operands &f16, float *partial,
                       int64_t part_stride_rows, const int *done, hipStream_t s, float kappa = 0.f);
 bool pair_shape_ok(const vds_tuning &t, int D);
+// The slots a pass of tuning t over nrow_blocks 16-row blocks and ncol_chunks
+// 16-column chunks writes (launch_pair_pass takes its grid from the same map).
+SplitMap pair_split_map(const vds_tuning &t, int64_t nrow_blocks, int64_t ncol_chunks);
 // Batched pair pass over the (ensemble, row tile) work list `items` with a
 // persistent grid of `grid` workgroups; rb = row blocks per wavefront.
 // impl selects the pair implementation (VDS_PAIR_MFMA or one of the FP16-split
@@ -189,7 +216,7 @@ void launch_mean_partials(const EvalParams &p, const float *q, const float *w, d
 void launch_prep(const EvalParams &p, const float *q, const float *w, const double *meanp, int nmeanp,
                  float *xc, float *wv, float *QB, float *KA, float *VA, float *wscale, const F16Operands *f16,
                  const int *done, hipStream_t s, float *cmean = nullptr, Ctrl *begin = nullptr);
-void launch_finalize_a(const EvalParams &p, const float *partial, int splits, const float *xc, const float *wv,
+void launch_finalize_a(const EvalParams &p, const float *partial, const SplitMap &splits, const float *xc, const float *wv,
                        float *S, float *t1, float *VB, const int *done, hipStream_t s);
 // In MODE_PICARD, q0 is the state at the start of the step (the flow term is
 // taken there) and each block leaves its maxima of |dx| and |x| in blockmax.
@@ -198,7 +225,7 @@ void launch_finalize_a(const EvalParams &p, const float *partial, int splits, co
 // kernel's work for it).
 // With fene_out (FENE springs), a bond of qin outside the spring's domain sets
 // *fene_out to 1.
-void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, int splits, const float *xc,
+void launch_combine(const EvalParams &p, int mode, bool obs, const float *partial, const SplitMap &splits, const float *xc,
                     const float *t1, const float *S, const float *wv, const float *qin, const float *q0,
                     float *out, float *out2, double *redp, float *blockmax, const int *done, hipStream_t s,
                     const PackOps *pack = nullptr, int *fene_out = nullptr);
@@ -223,7 +250,7 @@ void launch_density_rows(const EvalParams &p, const float *y, int64_t ny, const 
 // QB/KA in the 16-row FP32 layout from the centred coordinates xc (the FP32 kernel GEMM of
 // the reduced model reads them; under p.f32x the prep kernels write the per-chunk layout).
 void launch_pack_qk(const EvalParams &p, const float *xc, float *QB, float *KA, hipStream_t s);
-void launch_density_out(const EvalParams &p, const float *partial, int splits, int64_t ny, float norm,
+void launch_density_out(const EvalParams &p, const float *partial, const SplitMap &splits, int64_t ny, float norm,
                         float *f, hipStream_t s);
 void launch_copy(const float *src, float *dst, int64_t n, const int *done_flag_or_null, hipStream_t s);
 // q[k][i] = sum_r U[r][i] p[k][r] for i < m, k < nb (U is m x R column-major; pod.hip).

@@ -60,7 +60,7 @@ IMPLS = [None, (0, 4, 16), (2, 4, 16), (3, 2, 8)]
 
 
 @pytest.mark.parametrize("P", [1, 2, 3, 17, 63, 64, 300])
-@pytest.mark.parametrize("nb", [1, 3, 5])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5])
 def test_pair_sums_brute_force_small(lib, P, nb):
     q64 = wl.gaussian_bonds(100 + P, nb, P, 0.5)
     q = wl.f32_as_f64(wl.to_f32(q64))
@@ -81,6 +81,43 @@ def test_pair_sums_brute_force_small(lib, P, nb):
         scale = max(np.linalg.norm(b_o), 1e-3 * math.sqrt(b_o.size) / h ** 2)
         assert np.linalg.norm(b - b_o) / scale < 1e-5, (impl, rb, sp)
         assert np.linalg.norm(t1 - ovds.bond_major(t1_o, nb)) / scale < 1e-5
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 5])
+def test_pair_sums_far_particles_mix_folded_and_full_rows(lib, nb):
+    """A few particles far from the rest (kappa |x|^2 well above 100 after
+    centring) among ordinary ones: the FP32 32x32 kernel takes every distance
+    step for the waves holding them and folds the row-norm term out of the
+    exponent for the others.  Both kinds of row, and the isolated particles'
+    own sums (self term only, up to FP32 underflow), match the oracle for every
+    launch shape of that kernel."""
+    P, h = 1000, 0.45
+    q64 = wl.gaussian_bonds(41 + nb, nb, P, 0.5)
+    far = np.array([5, 6, 333, 700, 999])
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=(nb, far.size, 3))
+    q64[:, far, :] += 9.0 * d / np.sqrt((d ** 2).sum(axis=(0, 2)))[None, :, None]  # |offset| = 9 in R^D
+    q = wl.f32_as_f64(wl.to_f32(q64))
+    w = wl.f32_as_f64(wl.to_f32(wl.random_weights(17, P)))
+    x = ovds.particle_major(q)
+    kappa = math.log2(math.e) / (2 * h * h)
+    xc = x - (w[:, None] * x).sum(axis=0)
+    assert (kappa * (xc ** 2).sum(axis=1))[far].min() > 150  # these rows take every step
+    S_o, t1_o, t2_o = ovds.brownian_terms(x, w, h)
+    b_o = ovds.bond_major(t1_o + t2_o, nb)
+    ctx = _ctx(lib, nb, P, h, scheme="explicit")
+    for rb, sp in [(1, 1), (2, 4), (1, 3), (2, 8)]:
+        _say(f"far particles nb={nb} impl=4 rb={rb} per-CU={sp}")
+        ctx.set_tuning(4, rb, sp)
+        S, t1, t2 = ctx.pair_sums(_dev(q), _dev(w))
+        S, t1, t2 = S.cpu().numpy(), t1.cpu().numpy(), t2.cpu().numpy()
+        assert np.max(np.abs(S - S_o) / S_o) < 1e-5
+        b = t1.astype(np.float64) + t2
+        scale = max(np.linalg.norm(b_o), 1e-3 * math.sqrt(b_o.size) / h ** 2)
+        assert np.linalg.norm(b - b_o) / scale < 1e-5, (rb, sp)
+        # per particle, against the same global scale: no row may carry the error
+        row_err = np.sqrt(((b - b_o) ** 2).sum(axis=(0, 2)))
+        assert row_err.max() / scale < 1e-5, (rb, sp, int(row_err.argmax()))
 
 
 def test_uniform_weights_null_pointer_matches_explicit_uniform(lib):
