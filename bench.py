@@ -354,11 +354,15 @@ def _learned_rollout_vs_plain(torch, ctx, m, U, q0, rate, rollout_steps):
     torch.cuda.synchronize()
     T_plain = time.perf_counter() - t1
     tau_ref = ctx.stress(q)
+    # what the basis alone can reach: the plain final state projected and reconstructed
+    qp = ctx.pod_reconstruct(U, ctx.pod_project(U, q))
+    floor = float(np.linalg.norm(ctx.stress(qp) - tau_ref) / np.linalg.norm(tau_ref))
     p = ctx.pod_project(U, q0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     st = m.rollout(ctx, U, p, math.log(rate), nsteps=rollout_steps, check_every=50, resid_tol=0.2, energy_tol=0.5)
     torch.cuda.synchronize()
+    st["projection_floor_stress"] = floor
     return T_plain, tau_ref, time.perf_counter() - t2, st
 
 
@@ -418,6 +422,7 @@ def measure_learned(pkg, wl, torch, P, n_runs, n_snap_runs, run_steps, epochs, r
         "T_plain_s": T_plain, "T_rollout_s": T_roll, "speedup_vs_plain": T_plain / T_roll,
         "stress_rel_err_vs_plain": err(st["tau"]), "checks": st["checks"], "fallbacks": st["fallbacks"],
         "max_resid": st["max_resid"], "max_energy_gap": st["max_energy_gap"],
+        "projection_floor_stress": st["projection_floor_stress"],
         "without_network_pod_galerkin": {"T_s": T_gal, "stress_rel_err_vs_plain": err(tau_gal),
                                          "speedup_vs_plain": T_plain / T_gal},
     }
@@ -453,6 +458,7 @@ def measure_learned_fene(pkg, wl, torch, n_runs, R, run_steps, epochs, rollout_s
         "T_plain_s": T_plain, "T_rollout_s": T_roll, "speedup_vs_plain": T_plain / T_roll,
         "stress_rel_err_vs_plain": err, "checks": st["checks"], "fallbacks": st["fallbacks"],
         "max_resid": st["max_resid"], "max_energy_gap": st["max_energy_gap"],
+        "projection_floor_stress": st["projection_floor_stress"],
     }
 
 

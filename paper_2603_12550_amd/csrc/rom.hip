@@ -22,9 +22,12 @@ using namespace vds;
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int kMaxR = 1024;
 constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the kernel-GEMM
 constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
+constexpr int kK32Waves = 8;  // waves (32-row blocks) per workgroup of the FP32 32x32 kernel-GEMM
+constexpr int kK32NB = 3;     // its column blocks of 32 per workgroup: 96 columns
 
 struct RomLayout {
   size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, pprev, total;
@@ -51,7 +54,9 @@ RomLayout rom_layout(const vds_problem &p, int R) {
   L.XB1 = take(sizeof(float) * R * R);
   L.XB2 = take(sizeof(float) * R * R);
   L.XB = take(sizeof(float) * R * R);
-  L.Bsw = take(sizeof(float) * (size_t)Ppad * L.ldy);
+  // B of the kernel-GEMM: the 16-column swizzled layout, or that of the 32x32 form
+  const int64_t ncg32 = (ncols + 32 * kK32NB - 1) / (32 * kK32NB);
+  L.Bsw = take(sizeof(float) * (size_t)Ppad * std::max<int64_t>(L.ldy, ncg32 * 128));
   L.Y = take(sizeof(float) * (size_t)Ppad * L.ldy);
   L.qt = take(sizeof(float) * (size_t)p.nb * P * 3);
   L.T = take(sizeof(float) * Ppad);
@@ -205,6 +210,143 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
     for (int i = 0; i < 4; ++i) {
       const int64_t row = (int64_t)rb * 16 + 4 * (lane >> 4) + i;
       Y[row * ldy + (int64_t)(nb0 + g) * 16 + (lane & 15)] = (float)tot[g][i];
+    }
+  }
+}
+
+// ---- FP32 kernel-GEMM on 32x32 tiles (the operands of VDS_PAIR_MFMA32) -----
+//
+// Y[I][col] = sum_J Z_IJ B[J][col] with a workgroup of kK32Waves waves owning
+// kK32Waves 32-row blocks (256 rows) and kK32NB column blocks of 32 (96
+// columns).  Per chunk of 32 columns of Z it stages the chunk's B block and
+// the K operand of its distance product (the pair kernel's per-chunk KC
+// layout) in LDS once, double buffered with one barrier.  Each wave forms its
+// 32x32 piece of Z on v_mfma_f32_32x32x2_f32 from the centred row coordinates
+// (Z_II = 1 set exactly) and multiplies it by the staged B block on the same
+// instruction: the distance product leaves lane l with row I = l % 32 and, in
+// register v, column J = 8 (v / 4) + 4 (l / 32) + v % 4, which is the A-operand
+// layout of step v of the product over J.  B of step v for column block nb
+// sits in lane l at row J(v, l / 32), column 32 nb + l % 32.  FP32
+// accumulation over all columns of Z (as the FP16-split form: ~1e-6 of the
+// sums).
+// B of the FP32 32x32 kernel-GEMM, one block of 32 rows J x 96 columns per
+// (chunk c, column group cg): element (jj, col = 96 cg + 32 nb + l) at
+// [((c NCG + cg) 32 + jj) 128 + 4 l + nb] (slot nb = 3 of each lane is zero).
+__global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict__ wv, const float *__restrict__ invS,
+                          int64_t P, int64_t Ppad, int R, int NCG, float *__restrict__ Bk) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= Ppad * NCG * 128) return;
+  const int e = (int)(t & 127);
+  const int64_t blk = t >> 7;  // (c NCG + cg) 32 + jj
+  const int jj = (int)(blk & 31);
+  const int64_t cb = blk >> 5;
+  const int cg = (int)(cb % NCG);
+  const int64_t J = (cb / NCG) * 32 + jj;
+  const int l = e >> 2, nb = e & 3;
+  const int col = cg * 32 * kK32NB + 32 * nb + l;
+  const int dR = 3 * R;
+  float v = 0.f;
+  if (nb < kK32NB && J < P && col < 2 * dR) {
+    const int h = col / dR, rem = col % dR, a = rem / R, tt = rem % R;
+    const float wgt = h == 0 ? wv[J] : wv[J] * invS[J];
+    v = wgt * Ude[((int64_t)a * R + tt) * P + J];
+  }
+  Bk[t] = v;
+}
+
+template <int D>
+__global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_kernel_gemm32(
+    const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC, int nch, const float4 *__restrict__ Bk,
+    int NCG, int ncols, float kappa, float *__restrict__ Y, int64_t ldy) {
+  constexpr int KP = mfma32_kslots(D), NK = KP / 2;
+  constexpr int KF4 = KP * 8;             // float4s of a chunk's K operand
+  constexpr int BF4 = 32 * 128 / 4;       // float4s of a chunk's B block
+  constexpr int SF4 = KF4 + BF4;          // float4s staged per chunk
+  constexpr int NST = (SF4 + kK32Waves * 64 - 1) / (kK32Waves * 64);
+  __shared__ float4 sb[2][SF4];
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, li = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int rb = (int)blockIdx.x * kK32Waves + wave;  // this wave's 32-row block
+  const int cg = (int)blockIdx.y;
+  // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
+  // row norm term (k == D + 1), 0 beyond
+  float qv[NK];
+  {
+    const int rr = rb < nrb32 ? rb : 0;  // waves past the rows compute on block 0, unwritten
+    const float *x = xr + ((int64_t)rr * 32 + li) * D;
+    float nrm = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int k = 2 * kk + h;
+      qv[kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? -kappa * nrm : 0.f));
+    }
+  }
+  auto src = [&](int c, int u) -> float4 {
+    return u < KF4 ? KC[(int64_t)c * KF4 + u] : Bk[((int64_t)c * NCG + cg) * BF4 + (u - KF4)];
+  };
+  float4 pre[NST];
+#pragma unroll
+  for (int i = 0; i < NST; ++i) {
+    const int u = t + kK32Waves * 64 * i;
+    if (u < SF4) sb[0][u] = src(0, u);
+  }
+  __syncthreads();
+  floatx16 acc[kK32NB];
+#pragma unroll
+  for (int nb = 0; nb < kK32NB; ++nb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) {
+#pragma unroll
+      for (int i = 0; i < NST; ++i) {
+        const int u = t + kK32Waves * 64 * i;
+        pre[i] = u < SF4 ? src(c + 1, u) : float4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+    const float *sK = reinterpret_cast<const float *>(sb[buf]) + h * 32 + li;
+    const float4 *sB = sb[buf] + KF4 + h * 128 + li;  // row J(v, h) = 8 (v / 4) + 4 h + v % 4
+    floatx16 z;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) z[v] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) z = __builtin_amdgcn_mfma_f32_32x32x2f32(sK[kk * 64], qv[kk], z, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) z[v] = __builtin_amdgcn_exp2f(z[v]);
+    if (c == rb) {  // scalar branch: the self pair has Z_II = K_h(0) = 1 exactly
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int v = 0; v < 16; ++v) z[v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 1.f : z[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float4 b = sB[(8 * (v >> 2) + (v & 3)) * 32];
+      const float bv[3] = {b.x, b.y, b.z};
+#pragma unroll
+      for (int nb = 0; nb < kK32NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[v], bv[nb], acc[nb], 0, 0, 0);
+    }
+    if (c + 1 < nch) {
+#pragma unroll
+      for (int i = 0; i < NST; ++i) {
+        const int u = t + kK32Waves * 64 * i;
+        if (u < SF4) sb[buf ^ 1][u] = pre[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (rb >= nrb32) return;
+  // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 96 cg + 32 nb + li
+#pragma unroll
+  for (int nb = 0; nb < kK32NB; ++nb) {
+    const int col = cg * 32 * kK32NB + 32 * nb + li;
+    if (col >= ncols) break;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = (int64_t)rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+      Y[row * ldy + col] = acc[nb][v];
     }
   }
 }
@@ -791,9 +933,26 @@ vds_status freeze(vds_rom r, const float *p) {
         default: k_kernel_gemm16<5><<<grid, 256, 0, s>>>(c->QB, c->KA, nrb, ncc, bh, lo_off, L.NB16, 3 * R, s0, s1, 1.f, r->Y, L.ldy); break;
       }
     });
+  } else if (c->ep.f32x) {
+    // the 32x32 form reads the pair kernel's operands as the passes left them
+    const int NCG = (int)((2 * 3 * R + 32 * kK32NB - 1) / (32 * kK32NB));
+    k_rom_b32<<<nblk256(Ppad * NCG * 128), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, NCG, r->Bsw);
+    const int nrb32 = (int)(Ppad / 32), nch = (int)((P + 31) / 32);
+    const dim3 grid((unsigned)((nrb32 + kK32Waves - 1) / kK32Waves), (unsigned)NCG);
+    const float4 *kc = reinterpret_cast<const float4 *>(c->KA), *bk = reinterpret_cast<const float4 *>(r->Bsw);
+    const double flops = 2.0 * (double)P * P * 2 * 3 * R;
+    const int ncols = 2 * 3 * R;
+    timed(c, VDS_TIMER_KGEMM, flops, [&] {
+      switch (c->ep.D) {
+        case 3: k_kernel_gemm32<3><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
+        case 6: k_kernel_gemm32<6><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
+        case 9: k_kernel_gemm32<9><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
+        case 12: k_kernel_gemm32<12><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
+        default: k_kernel_gemm32<15><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
+      }
+    });
   } else {
-    // the FP32 kernel GEMM reads the 16-row operand layout
-    if (c->ep.f32x) launch_pack_qk(c->ep, c->xc, c->QB, c->KA, s);
+    // the 16x16 FP32 forms (VDS_PAIR_MFMA, VDS_PAIR_VALU) read the 16-row operand layout
     k_rom_bsw<<<nblk256(Ppad * L.ldy), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, L.NB16, r->Bsw);
     const int nrb = (int)(Ppad / 16), ncc = (int)((P + 15) / 16);
     dim3 grid((unsigned)((nrb + 3) / 4), (unsigned)((L.NB16 + kNBG - 1) / kNBG));
