@@ -43,9 +43,10 @@ const char *vds_batch_last_error(vds_batch b);
  * (ensembles stored back to back in order); e = nens gives the total length. */
 int64_t vds_batch_state_offset(vds_batch b, int32_t e);
 
-/* Pair-pass implementation (VDS_PAIR_MFMA, VDS_PAIR_MFMA_F16X2 or
- * VDS_PAIR_MFMA_F16X2_ALL; see vds.h) and launch shape: row blocks per
- * wavefront (1, 2, 4) and persistent grid size (workgroups, >= 1);
+/* Pair-pass implementation (VDS_PAIR_MFMA32, VDS_PAIR_MFMA, VDS_PAIR_MFMA_F16X2
+ * or VDS_PAIR_MFMA_F16X2_ALL; see vds.h) and launch shape: row blocks per
+ * wavefront (1, 2, 4; 1 or 2 for VDS_PAIR_MFMA32, whose blocks hold 32 rows)
+ * and persistent grid size (workgroups, >= 1);
  * use_graph = 0 launches each step eagerly.  Changing the implementation
  * synchronises (the ensemble table is re-uploaded). */
 vds_status vds_batch_set_tuning(vds_batch b, int32_t impl, int32_t rows_per_wave, int32_t grid, int32_t use_graph);
@@ -54,7 +55,8 @@ vds_status vds_batch_get_tuning(vds_batch b, int32_t *impl, int32_t *rows_per_wa
 /* Times the admissible launch shapes (row blocks per wavefront, grid) of the
  * current implementation on the packed state q_dev and keeps the fastest; the
  * implementation, and so the arithmetic, is left as set (synchronises).  A new
- * batch starts with VDS_PAIR_MFMA (FP32). */
+ * batch starts with VDS_PAIR_MFMA32 (FP32), 2 row blocks per wavefront and
+ * 1024 workgroups. */
 vds_status vds_batch_autotune(vds_batch b, const float *q_dev);
 
 /* Advances every ensemble of the packed state q_dev by nsteps explicit Euler

@@ -35,7 +35,7 @@ struct vds_batch_s {
   char *ws = nullptr;
   hipStream_t user = nullptr, priv = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  int impl = VDS_PAIR_MFMA, rb = 2, grid = 1024, use_graph = 1;
+  int impl = VDS_PAIR_MFMA32, rb = 2, grid = 1024, use_graph = 1;
   int nitems = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -103,14 +103,17 @@ BatchLayout batch_layout(int nens, const int64_t *P, int nb) {
   return L;
 }
 
-// (ensemble, row tile) items, costliest ensembles first.
+// (ensemble, row tile) items, costliest ensembles first.  A row tile is the
+// 4 rb 16-row blocks of the 16x16 forms, or the 4 rb 32-row blocks of
+// VDS_PAIR_MFMA32.
 std::vector<int2> make_items(const vds_batch b, int rb) {
+  const int64_t rows_per_block = b->impl == VDS_PAIR_MFMA32 ? 32 : 16;
   std::vector<int> order(b->nens);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->P[x] > b->P[y]; });
   std::vector<int2> items;
   for (int e : order) {
-    const int64_t tiles = (pad(b->P[e]) / 16 + 4 * rb - 1) / (4 * rb);
+    const int64_t tiles = (pad(b->P[e]) / rows_per_block + 4 * rb - 1) / (4 * rb);
     for (int64_t t = 0; t < tiles; ++t) items.push_back(make_int2(e, (int)t));
   }
   return items;
@@ -143,7 +146,7 @@ void set_formats(vds_batch b) {
   for (EnsDesc &d : b->ens) {
     d.p.vhalf = (b->impl == VDS_PAIR_MFMA_F16X2 || b->impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
     d.p.qhalf = b->impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
-    d.p.f32x = 0;  // the batched pair kernels read the 16-row FP32 layout
+    d.p.f32x = b->impl == VDS_PAIR_MFMA32 ? 1 : 0;  // its per-chunk operand layout
   }
 }
 
@@ -266,6 +269,7 @@ vds_status vds_batch_create(int32_t nens, const int64_t *P, const double *h, con
     p.log_norm = (float)(0.5 * b->D * std::log(2.0 * M_PI * h[e] * h[e]));
     p.KQ = f16_slices(b->D);
     p.cs = (float)std::sqrt(2.0 * 1.4426950408889634 / (2.0 * h[e] * h[e]));
+    p.KP = mfma32_kslots(b->D);
     d.pad_off = pad_off;
     d.q_off = q_off;
     d.blk16 = (int)(pad_off / 16);
@@ -347,11 +351,13 @@ int64_t vds_batch_state_offset(vds_batch b, int32_t e) {
 
 vds_status vds_batch_set_tuning(vds_batch b, int32_t impl, int32_t rb, int32_t grid, int32_t use_graph) {
   if (b == nullptr) return VDS_ERR_ARG;
-  if (impl != VDS_PAIR_MFMA && impl != VDS_PAIR_MFMA_F16X2 && impl != VDS_PAIR_MFMA_F16X2_ALL)
-    return berr(b, VDS_ERR_ARG, "impl must be VDS_PAIR_MFMA or one of the FP16-split forms");
-  if (!(rb == 1 || rb == 2 || rb == 4) || grid < 1 || grid > (1 << 20))
-    return berr(b, VDS_ERR_ARG, "rows_per_wave must be 1, 2 or 4 and grid >= 1");
-  const bool items_change = rb != b->rb;
+  if (impl != VDS_PAIR_MFMA32 && impl != VDS_PAIR_MFMA && impl != VDS_PAIR_MFMA_F16X2 &&
+      impl != VDS_PAIR_MFMA_F16X2_ALL)
+    return berr(b, VDS_ERR_ARG, "impl must be VDS_PAIR_MFMA32, VDS_PAIR_MFMA or one of the FP16-split forms");
+  if (!(rb == 1 || rb == 2 || (rb == 4 && impl != VDS_PAIR_MFMA32)) || grid < 1 || grid > (1 << 20))
+    return berr(b, VDS_ERR_ARG, "rows_per_wave must be 1, 2 or 4 (1 or 2 for VDS_PAIR_MFMA32) and grid >= 1");
+  // row tiles of the work list follow rb and the implementation's block height
+  const bool items_change = rb != b->rb || (impl == VDS_PAIR_MFMA32) != (b->impl == VDS_PAIR_MFMA32);
   const bool impl_change = impl != b->impl;
   b->impl = impl;
   b->rb = rb;
@@ -390,6 +396,7 @@ vds_status vds_batch_autotune(vds_batch b, const float *q) {
     if (st != VDS_OK) break;
     pass_a(b, q, b->priv);  // operands in this implementation's format
     for (int rb : {1, 2, 4}) {
+      if (rb == 4 && impl == VDS_PAIR_MFMA32) continue;
       for (int per_cu : {2, 4, 8}) {
         st = vds_batch_set_tuning(b, impl, rb, 256 * per_cu, b->use_graph);
         if (st != VDS_OK) break;

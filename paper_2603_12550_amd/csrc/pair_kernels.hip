@@ -229,40 +229,228 @@ struct Mfma32Shape {
 };
 
 // Largest row-norm term kappa |x_I|^2 that a row block may fold out of the
-// exponent (see k_pair_mfma32): e' <= 2^100, and a group of 128 products
+// exponent (see mfma32_segment): e' <= 2^100, and a group of 128 products
 // e' V stays far below the FP32 range.
 constexpr float kFoldMax = 100.f;
 
-// Waves per SIMD the FP32 32x32 kernel is compiled for: four (128 VGPRs) where
-// the workgroup's LDS lets four workgroups share a compute unit.
+// LDS of one workgroup of the FP32 32x32 form: staged chunks (double buffered)
+// and the FP64 running sums of its four waves (one slot per lane and value;
+// only its own lane touches a slot, so plain read-add-write keeps the
+// summation order; held in LDS, they leave the registers to the arithmetic).
+template <int D, int RB>
+struct Mfma32Lds {
+  float4 sb[2][kStage32 * Mfma32Shape<D>::LF4];
+  double stot[4][RB][Mfma32Shape<D>::NG][2][64];
+};
+
+// Waves per SIMD the FP32 32x32 kernels are compiled for: four (128 VGPRs)
+// where the workgroup's LDS lets four workgroups share a compute unit.
 template <int D, int RB>
 constexpr int mfma32_waves() {
-  return sizeof(double) * 4 * RB * Mfma32Shape<D>::NG * 2 * 64 + sizeof(float4) * 2 * kStage32 * Mfma32Shape<D>::LF4 <=
-                 40960
-             ? 4
-             : 3;
+  return sizeof(Mfma32Lds<D, RB>) <= 40960 ? 4 : 3;
 }
 
+// One segment of the FP32 32x32 form: the workgroup's four waves take row
+// group rg (wave w: 32-row blocks (4 rg + w) RB ..), the columns of chunks
+// [c0, c1), and write partial sums for their rows to out[row][16].  Every
+// thread of the workgroup calls it with the same arguments (it holds barriers).
 template <int D, int RB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_waves<D, RB>()))) void k_pair_mfma32(const float *__restrict__ xr, int nrb32,
-                                                     const float4 *__restrict__ KC, const float4 *__restrict__ VC,
-                                                     SplitMap map, int exclude_self, float kappa,
-                                                     float *__restrict__ partial, int64_t part_stride_rows,
-                                                     const int *__restrict__ done) {
+__device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC,
+                               const float4 *__restrict__ VC, int rg, int c0, int c1, int exclude_self, float kappa,
+                               float *__restrict__ out, Mfma32Lds<D, RB> &lds) {
   using S = Mfma32Shape<D>;
   // odd D: the last distance step holds only the row-norm slot and padding
   constexpr bool kFold = (D % 2) == 1;
-  __shared__ float4 sb[2][kStage32 * S::LF4];
-  // FP64 running sums, one slot per lane and value (only its own lane touches
-  // a slot, so plain read-add-write keeps the summation order): held in LDS,
-  // they leave the registers to the arithmetic
-  __shared__ double stot[4][RB][S::NG][2][64];
-  if (done != nullptr && *done) return;  // the whole grid returns: no barrier is left waiting
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int h = lane >> 5;   // lane half
   const int li = lane & 31;  // row of the 32x32 tile (distance product) / column slot of the K operand
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  auto &sb = lds.sb;
+  double(*tot)[S::NG][2][64] = lds.stot[wave];
+  constexpr int NST = (S::GF4 + 255) / 256;
+  auto stage_dst = [&](int u) { return u < S::KF4 ? u : S::KF4 + ((u - S::KF4) >> 2) * S::VS + ((u - S::KF4) & 3); };
+  auto chunk_src = [&](int c, int u) -> float4 {
+    return u < S::KF4 ? KC[(int64_t)c * S::KF4 + u] : VC[(int64_t)c * 128 + (u - S::KF4)];
+  };
+  const int rb0 = (rg * 4 + wave) * RB;  // first 32-row block of this wave
+
+  // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
+  // row norm term -kappa |x_I|^2 (k == D + 1), 0 beyond.  With kFold, a wave
+  // whose row-norm terms all lie within kFoldMax leaves out the last step (the
+  // row-norm slot): its exponents are t + kappa |x_I|^2, and the factor
+  // 2^(-kappa |x_I|^2) of each row is applied to its sums in FP64 at the end
+  float qv[RB][S::NK];
+  bool in_range = true;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int rb = rb0 + r < nrb32 ? rb0 + r : 0;  // waves past the rows compute on row block 0, unwritten
+    const float *x = xr + ((int64_t)rb * 32 + li) * D;
+    float nrm = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
+    const float rn = -kappa * nrm;
+#pragma unroll
+    for (int kk = 0; kk < S::NK; ++kk) {
+      const int k = 2 * kk + h;
+      qv[r][kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? rn : 0.f));
+    }
+    in_range = in_range && rn >= -kFoldMax;
+  }
+  const int fold = kFold ? __builtin_amdgcn_readfirstlane(__all(in_range ? 1 : 0) ? 1 : 0) : 0;
+
+  // thread t stages float4s t, t + 256, ... of a chunk: the K operand first,
+  // then V into rows of VS float4s; a stage is kStage32 consecutive chunks,
+  // one barrier each
+#pragma unroll
+  for (int cc = 0; cc < kStage32; ++cc) {
+    if (c0 + cc < c1) {
+#pragma unroll
+      for (int i = 0; i < NST; ++i) {
+        const int v = t + 256 * i;
+        if (v < S::GF4) sb[0][cc * S::LF4 + stage_dst(v)] = chunk_src(c0 + cc, v);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int g = 0; g < S::NG; ++g) tot[r][g][0][lane] = tot[r][g][1][lane] = 0.0;
+  __syncthreads();
+
+  floatx4 acc[RB][S::NG];
+  // one chunk of 32 columns from its LDS buffer; NKS distance steps
+  auto chunk = [&](int c, const float4 *cb, auto nks) {
+    constexpr int NKS = decltype(nks)::value;
+    // per-lane bases; every read below is at a constant offset from them
+    const float *sK = reinterpret_cast<const float *>(cb) + h * 32 + li;
+    const float4 *sV = cb + S::KF4 + 4 * h * S::VS + (lane & 3);
+    float ka[S::NK];
+#pragma unroll
+    for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
+    floatx16 e[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < NKS; ++kk)
+        e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
+      // no clamp: the expanded squared distance exceeds zero only by its rounding
+#pragma unroll
+      for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
+      if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
+        // an empty volatile asm keeps this a branch: if-converted into selects
+        // it would cost sixteen VALU instructions on every tile
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
+      const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int g = 0; g < S::NG; ++g)
+          acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
+    }
+  };
+
+  // the chunk loop, in two copies (all steps, or the folded wave's NK - 1);
+  // both pass the same barriers
+  auto chunks = [&](auto nks) {
+  for (int c = c0; c < c1;) {
+    // groups start kFlush32 (a multiple of kStage32) chunks apart, so a stage
+    // never crosses a group boundary
+    const int gend = min(c1, c + kFlush32);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (; c < gend; c += kStage32) {
+      const int buf = ((c - c0) / kStage32) & 1;
+      const int cn = c + kStage32;  // first chunk of the next stage
+      float4 pre[kStage32][NST];    // the next stage, stored after this one's arithmetic
+#pragma unroll
+      for (int cc = 0; cc < kStage32; ++cc)
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          const int v = t + 256 * i;
+          pre[cc][i] = (cn + cc < c1 && v < S::GF4) ? chunk_src(cn + cc, v) : float4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+      for (int cc = 0; cc < kStage32; ++cc)
+        if (c + cc < gend) chunk(c + cc, sb[buf] + cc * S::LF4, nks);
+      if (cn < c1) {
+#pragma unroll
+        for (int cc = 0; cc < kStage32; ++cc)
+#pragma unroll
+          for (int i = 0; i < NST; ++i) {
+            const int v = t + 256 * i;
+            if (cn + cc < c1 && v < S::GF4) sb[buf ^ 1][cc * S::LF4 + stage_dst(v)] = pre[cc][i];
+          }
+      }
+      // every stage ends at a barrier, the segment's last one too: the next
+      // segment may overwrite either buffer
+      __syncthreads();
+    }
+    // the two lane halves hold the same outputs over different columns: after a
+    // swap of rows (0, 1) and one of rows (2, 3), each sum of the pair leaves
+    // half h with the full row h and the full row 2 + h
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int g = 0; g < S::NG; ++g) {
+        float a0 = acc[r][g][0], a1 = acc[r][g][1], a2 = acc[r][g][2], a3 = acc[r][g][3];
+        permlane32_swap(a0, a1);
+        permlane32_swap(a2, a3);
+        tot[r][g][0][lane] += (double)(a0 + a1);
+        tot[r][g][1][lane] += (double)(a2 + a3);
+      }
+  }
+  };
+  if (fold)  // scalar branch
+    chunks(std::integral_constant<int, S::NK - 1>{});
+  else
+    chunks(std::integral_constant<int, S::NK>{});
+
+  // lane l holds rows 4 ((l % 32) / 4) + h + 2 s (s = 0, 1) and outputs n = 4 g + l % 4;
+  // the weighted kernel sum O[.][D] sits in the lane of the same quad with l % 4 = D % 4
+  const int src = (lane & ~3) | (D & 3);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (rb0 + r >= nrb32) break;
+#pragma unroll
+    for (int sidx = 0; sidx < 2; ++sidx) {
+      const int64_t row = (int64_t)(rb0 + r) * 32 + 4 * (li >> 2) + h + 2 * sidx;
+      double f = 1.0;  // the factor a folded wave's sums still carry
+      if (fold) {
+        float nrm = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(xr[row * D + a], xr[row * D + a], nrm);
+        f = exp2((double)(-kappa * nrm));
+      }
+      const double sv = f * tot[r][D / 4][sidx][src];
+#pragma unroll
+      for (int g = 0; g < S::NG; ++g) {
+        const int n = 4 * g + (lane & 3);
+        if (n < D) out[row * 16 + n] = (float)((double)xr[row * D + n] * sv - f * tot[r][g][sidx][lane]);
+        else if (n == D) out[row * 16 + n] = (float)sv;
+      }
+    }
+  }
+}
+
+template <int D, int RB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_waves<D, RB>()))) void k_pair_mfma32(
+    const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC, const float4 *__restrict__ VC,
+    SplitMap map, int exclude_self, float kappa, float *__restrict__ partial, int64_t part_stride_rows,
+    const int *__restrict__ done) {
+  __shared__ Mfma32Lds<D, RB> lds;
+  if (done != nullptr && *done) return;  // the whole grid returns: no barrier is left waiting
   // workgroups go to the 8 XCDs round robin by linear id, and each XCD has its
   // own L2: with a multiple of 8 runs, XCD x takes the consecutive runs
   // x G / 8 .. (x + 1) G / 8 - 1, i.e. a band of row groups against all columns
@@ -270,13 +458,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
   const int L = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   const int64_t nch = map.nch;
   const int64_t u_end = map.run_start(L + 1);
-  double(*tot)[S::NG][2][64] = stot[wave];
-  constexpr int NST = (S::GF4 + 255) / 256;
-  auto stage_dst = [&](int u) { return u < S::KF4 ? u : S::KF4 + ((u - S::KF4) >> 2) * S::VS + ((u - S::KF4) & 3); };
-  auto chunk_src = [&](int c, int u) -> float4 {
-    return u < S::KF4 ? KC[(int64_t)c * S::KF4 + u] : VC[(int64_t)c * 128 + (u - S::KF4)];
-  };
-
   // one segment per row group this run covers: chunks [c0, c1) of row group rg
   for (int64_t u = map.run_start(L); u < u_end;) {
     const int64_t rg = u / nch;
@@ -284,176 +465,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
     const int c1 = (int)min(nch, u_end - rg * nch);
     const int slot = (int)(L - map.run_of(rg * nch));
     u = rg * nch + c1;
-    const int rb0 = ((int)rg * 4 + wave) * RB;  // first 32-row block of this wave
+    mfma32_segment<D, RB>(xr, nrb32, KC, VC, (int)rg, c0, c1, exclude_self, kappa,
+                          partial + (int64_t)slot * part_stride_rows * 16, lds);
+  }
+}
 
-    // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
-    // row norm term -kappa |x_I|^2 (k == D + 1), 0 beyond.  With kFold, a wave
-    // whose row-norm terms all lie within kFoldMax leaves out the last step (the
-    // row-norm slot): its exponents are t + kappa |x_I|^2, and the factor
-    // 2^(-kappa |x_I|^2) of each row is applied to its sums in FP64 at the end
-    float qv[RB][S::NK];
-    bool in_range = true;
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int rb = rb0 + r < nrb32 ? rb0 + r : 0;  // waves past the rows compute on row block 0, unwritten
-      const float *x = xr + ((int64_t)rb * 32 + li) * D;
-      float nrm = 0.f;
-#pragma unroll
-      for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
-      const float rn = -kappa * nrm;
-#pragma unroll
-      for (int kk = 0; kk < S::NK; ++kk) {
-        const int k = 2 * kk + h;
-        qv[r][kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? rn : 0.f));
-      }
-      in_range = in_range && rn >= -kFoldMax;
-    }
-    const int fold = kFold ? __builtin_amdgcn_readfirstlane(__all(in_range ? 1 : 0) ? 1 : 0) : 0;
-
-    // thread t stages float4s t, t + 256, ... of a chunk: the K operand first,
-    // then V into rows of VS float4s; a stage is kStage32 consecutive chunks,
-    // one barrier each
-#pragma unroll
-    for (int cc = 0; cc < kStage32; ++cc) {
-      if (c0 + cc < c1) {
-#pragma unroll
-        for (int i = 0; i < NST; ++i) {
-          const int v = t + 256 * i;
-          if (v < S::GF4) sb[0][cc * S::LF4 + stage_dst(v)] = chunk_src(c0 + cc, v);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int g = 0; g < S::NG; ++g) tot[r][g][0][lane] = tot[r][g][1][lane] = 0.0;
-    __syncthreads();
-
-    floatx4 acc[RB][S::NG];
-    // one chunk of 32 columns from its LDS buffer; NKS distance steps
-    auto chunk = [&](int c, const float4 *cb, auto nks) {
-      constexpr int NKS = decltype(nks)::value;
-      // per-lane bases; every read below is at a constant offset from them
-      const float *sK = reinterpret_cast<const float *>(cb) + h * 32 + li;
-      const float4 *sV = cb + S::KF4 + 4 * h * S::VS + (lane & 3);
-      float ka[S::NK];
-#pragma unroll
-      for (int kk = 0; kk < S::NK; ++kk) ka[kk] = sK[kk * 64];
-      floatx16 e[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) e[r][v] = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < NKS; ++kk)
-          e[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(ka[kk], qv[r][kk], e[r], 0, 0, 0);
-        // no clamp: the expanded squared distance exceeds zero only by its rounding
-#pragma unroll
-        for (int v = 0; v < 16; ++v) e[r][v] = __builtin_amdgcn_exp2f(e[r][v]);
-        if (exclude_self && c == rb0 + r) {  // scalar branch: the diagonal tile
-          // an empty volatile asm keeps this a branch: if-converted into selects
-          // it would cost sixteen VALU instructions on every tile
-          asm volatile("" ::: "memory");
-#pragma unroll
-          for (int v = 0; v < 16; ++v) e[r][v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 0.f : e[r][v];
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const float4 vv = sV[(8 * (v >> 2) + (v & 3)) * S::VS];
-        const float vg[4] = {vv.x, vv.y, vv.z, vv.w};
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-          for (int g = 0; g < S::NG; ++g)
-            acc[r][g] = __builtin_amdgcn_mfma_f32_4x4x1f32(e[r][v], vg[g], acc[r][g], 0, 0, 0);
-      }
-    };
-
-    // the chunk loop, in two copies (all steps, or the folded wave's NK - 1);
-    // both pass the same barriers
-    auto chunks = [&](auto nks) {
-    for (int c = c0; c < c1;) {
-      // groups start kFlush32 (a multiple of kStage32) chunks apart, so a stage
-      // never crosses a group boundary
-      const int gend = min(c1, c + kFlush32);
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
-      for (; c < gend; c += kStage32) {
-        const int buf = ((c - c0) / kStage32) & 1;
-        const int cn = c + kStage32;  // first chunk of the next stage
-        float4 pre[kStage32][NST];    // the next stage, stored after this one's arithmetic
-#pragma unroll
-        for (int cc = 0; cc < kStage32; ++cc)
-#pragma unroll
-          for (int i = 0; i < NST; ++i) {
-            const int v = t + 256 * i;
-            pre[cc][i] = (cn + cc < c1 && v < S::GF4) ? chunk_src(cn + cc, v) : float4{0.f, 0.f, 0.f, 0.f};
-          }
-#pragma unroll
-        for (int cc = 0; cc < kStage32; ++cc)
-          if (c + cc < gend) chunk(c + cc, sb[buf] + cc * S::LF4, nks);
-        if (cn < c1) {
-#pragma unroll
-          for (int cc = 0; cc < kStage32; ++cc)
-#pragma unroll
-            for (int i = 0; i < NST; ++i) {
-              const int v = t + 256 * i;
-              if (cn + cc < c1 && v < S::GF4) sb[buf ^ 1][cc * S::LF4 + stage_dst(v)] = pre[cc][i];
-            }
-        }
-        // every stage ends at a barrier, the segment's last one too: the next
-        // segment may overwrite either buffer
-        __syncthreads();
-      }
-      // the two lane halves hold the same outputs over different columns: after a
-      // swap of rows (0, 1) and one of rows (2, 3), each sum of the pair leaves
-      // half h with the full row h and the full row 2 + h
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int g = 0; g < S::NG; ++g) {
-          float a0 = acc[r][g][0], a1 = acc[r][g][1], a2 = acc[r][g][2], a3 = acc[r][g][3];
-          permlane32_swap(a0, a1);
-          permlane32_swap(a2, a3);
-          tot[r][g][0][lane] += (double)(a0 + a1);
-          tot[r][g][1][lane] += (double)(a2 + a3);
-        }
-    }
-    };
-    if (fold)  // scalar branch
-      chunks(std::integral_constant<int, S::NK - 1>{});
-    else
-      chunks(std::integral_constant<int, S::NK>{});
-
-    // lane l holds rows 4 ((l % 32) / 4) + h + 2 s (s = 0, 1) and outputs n = 4 g + l % 4;
-    // the weighted kernel sum O[.][D] sits in the lane of the same quad with l % 4 = D % 4
-    float *out = partial + (int64_t)slot * part_stride_rows * 16;
-    const int src = (lane & ~3) | (D & 3);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      if (rb0 + r >= nrb32) break;
-#pragma unroll
-      for (int sidx = 0; sidx < 2; ++sidx) {
-        const int64_t row = (int64_t)(rb0 + r) * 32 + 4 * (li >> 2) + h + 2 * sidx;
-        double f = 1.0;  // the factor a folded wave's sums still carry
-        if (fold) {
-          float nrm = 0.f;
-#pragma unroll
-          for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(xr[row * D + a], xr[row * D + a], nrm);
-          f = exp2((double)(-kappa * nrm));
-        }
-        const double sv = f * tot[r][D / 4][sidx][src];
-#pragma unroll
-        for (int g = 0; g < S::NG; ++g) {
-          const int n = 4 * g + (lane & 3);
-          if (n < D) out[row * 16 + n] = (float)((double)xr[row * D + n] * sv - f * tot[r][g][sidx][lane]);
-          else if (n == D) out[row * 16 + n] = (float)sv;
-        }
-      }
-    }
+// Batched form: a persistent grid walks the (ensemble, row group) items; each
+// item takes all columns of its ensemble (one slot of partial sums).
+template <int D, int RB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_waves<D, RB>()))) void k_batch_pair32(
+    const int2 *__restrict__ items, int nitems, const EnsDesc *__restrict__ ens, const float *__restrict__ xc,
+    const float *__restrict__ KC, const float *__restrict__ VC, int KK, float *__restrict__ partial) {
+  __shared__ Mfma32Lds<D, RB> lds;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 item = items[it];
+    const int64_t off = ens[item.x].pad_off;
+    const int64_t P = ens[item.x].p.P;
+    const int nrb32 = (int)(ens[item.x].p.Ppad / 32);
+    const float kappa = ens[item.x].p.kappa;
+    mfma32_segment<D, RB>(xc + off * D, nrb32, reinterpret_cast<const float4 *>(KC + off * KK * 4),
+                          reinterpret_cast<const float4 *>(VC + off * 16), item.y, 0, (int)((P + 31) / 32), 1, kappa,
+                          partial + off * 16, lds);
   }
 }
 
@@ -823,9 +855,28 @@ static void launch_batch_kk(int rb, int grid, const int2 *items, int nitems, con
   }
 }
 
+template <int D>
+static void launch_batch32_d(int rb, int grid, const int2 *items, int nitems, const EnsDesc *ens, const float *xc,
+                             const float *KC, const float *VC, int KK, float *partial, hipStream_t s) {
+  if (rb == 1)
+    k_batch_pair32<D, 1><<<grid, 256, 0, s>>>(items, nitems, ens, xc, KC, VC, KK, partial);
+  else
+    k_batch_pair32<D, 2><<<grid, 256, 0, s>>>(items, nitems, ens, xc, KC, VC, KK, partial);
+}
+
 void launch_batch_pair(int impl, int rb, int grid, int KK, int D, const int2 *items, int nitems, const EnsDesc *ens,
                        const float *QB, const float *KA, const float *VB, const F16Operands &f16, bool pass_a,
                        const float *xc, float *partial, hipStream_t s) {
+  if (impl == VDS_PAIR_MFMA32) {
+    switch (D) {
+      case 3: launch_batch32_d<3>(rb, grid, items, nitems, ens, xc, KA, VB, KK, partial, s); break;
+      case 6: launch_batch32_d<6>(rb, grid, items, nitems, ens, xc, KA, VB, KK, partial, s); break;
+      case 9: launch_batch32_d<9>(rb, grid, items, nitems, ens, xc, KA, VB, KK, partial, s); break;
+      case 12: launch_batch32_d<12>(rb, grid, items, nitems, ens, xc, KA, VB, KK, partial, s); break;
+      default: launch_batch32_d<15>(rb, grid, items, nitems, ens, xc, KA, VB, KK, partial, s); break;
+    }
+    return;
+  }
   if (impl == VDS_PAIR_MFMA_F16X2 || impl == VDS_PAIR_MFMA_F16X2_ALL) {
     const PairF16Ops ops{QB, KA, reinterpret_cast<const uint4 *>(f16.QH), reinterpret_cast<const uint4 *>(f16.KH),
                          f16.RN, reinterpret_cast<const uint4 *>(VB), 0};

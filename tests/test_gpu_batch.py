@@ -4,8 +4,8 @@ oracle run per ensemble, and of the captured-graph step against eager launches.
 Tolerances: states relative 1e-5 (float32 vs float64 oracle on the same float32
 inputs, a few explicit steps); per-ensemble stress relative Frobenius 1e-4;
 graph replays bitwise equal to eager launches (same kernels, fixed reduction
-order).  Every pair implementation is covered: FP32 MFMA and the FP16-split
-forms."""
+order).  Every pair implementation is covered: the FP32 32x32 form (the
+default), the FP32 16x16 form and the FP16-split forms."""
 import sys
 
 import numpy as np
@@ -51,7 +51,7 @@ def _oracle_steps(q, P, h, G, nsteps):
     return q, ovds.stress(q, w, prob)
 
 
-IMPLS = (0, 2, 3)  # FP32 MFMA and the two FP16-split forms
+IMPLS = (4, 0, 2, 3)  # FP32 32x32 and 16x16 MFMA, the two FP16-split forms
 
 
 @pytest.mark.parametrize("impl", IMPLS)
@@ -99,7 +99,7 @@ def test_tunings_agree_and_autotune_is_valid(lib):
     q0 = b.pack([torch.from_numpy(wl.to_f32(s)).cuda() for s in states])
     refs = {}
     for impl in IMPLS:
-        for rb in (1, 2, 4):
+        for rb in ((1, 2) if impl == 4 else (1, 2, 4)):
             for grid in (7, 256, 2048):
                 _say(f"batch tuning impl {impl} rb {rb} grid {grid}")
                 b.set_tuning(rb, grid, impl=impl)
@@ -110,7 +110,7 @@ def test_tunings_agree_and_autotune_is_valid(lib):
                 assert np.array_equal(r, ref), (impl, rb, grid)   # one split: identical arithmetic
     # the implementations agree with each other to the parity tolerance
     for impl in IMPLS[1:]:
-        assert _rel(refs[impl], refs[0].astype(np.float64)) < 1e-5, impl
+        assert _rel(refs[impl], refs[IMPLS[0]].astype(np.float64)) < 1e-5, impl
     t = b.autotune(q0)
     assert t["impl"] in IMPLS and t["rows_per_wave"] in (1, 2, 4) and t["grid"] >= 1
 
