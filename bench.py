@@ -366,7 +366,10 @@ def _learned_rollout_vs_plain(torch, ctx, m, U, q0, rate, rollout_steps):
     return T_plain, tau_ref, time.perf_counter() - t2, st
 
 
-def _train_learned(pkg, wl, torch, mk, q0, nb, R, rates, n_snap_runs, run_steps, epochs):
+LEARNED_LR, LEARNED_LR_FINAL = 2e-3, 1e-4  # half-cosine decay of the Adam step over the epochs
+
+
+def _train_learned(pkg, wl, torch, mk, q0, nb, R, rates, n_snap_runs, run_steps, epochs, seed=3):
     """POD basis from the snapshots (every 10 steps) of the first n_snap_runs
     runs, training pairs from the projected trajectories of every run, and the
     trained network; returns (U, m, pairs, losses)."""
@@ -384,11 +387,12 @@ def _train_learned(pkg, wl, torch, mk, q0, nb, R, rates, n_snap_runs, run_steps,
     m.set_params(torch.from_numpy(wl.to_f32(init)).cuda())
     X, T = learned.training_set(m, trajs)
     del trajs
-    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=2e-3, seed=3, input_noise=LEARNED_INPUT_NOISE)
+    losses = learned.train(m, X, T, epochs=epochs, batch=64, lr=LEARNED_LR, seed=seed, input_noise=LEARNED_INPUT_NOISE,
+                           lr_final=LEARNED_LR_FINAL)
     return U, m, int(X.shape[0]), losses
 
 
-def measure_learned(pkg, wl, torch, P, n_runs, n_snap_runs, run_steps, epochs, rollout_steps):
+def measure_learned(pkg, wl, torch, P, n_runs, n_snap_runs, run_steps, epochs, rollout_steps, seed=3):
     """Learned reduced step on the 4-bead chain (R = 180, input 541, width 128):
     explicit runs at log-uniform shear rates in [0.1, 10], then a checked rollout
     at a held-out rate against the plain scheme and against the POD-Galerkin
@@ -398,7 +402,7 @@ def measure_learned(pkg, wl, torch, P, n_runs, n_snap_runs, run_steps, epochs, r
     q0 = torch.from_numpy(wl.to_f32(wl.gaussian_bonds(2, 3, P, 1 / 3))).cuda()
     mk = lambda r: pkg.Context(3, P, h, G=wl.shear_gradient(r), dt=1e-3, scheme="explicit")
     t0 = time.perf_counter()
-    U, m, pairs, losses = _train_learned(pkg, wl, torch, mk, q0, 3, R, rates, n_snap_runs, run_steps, epochs)
+    U, m, pairs, losses = _train_learned(pkg, wl, torch, mk, q0, 3, R, rates, n_snap_runs, run_steps, epochs, seed)
     torch.cuda.synchronize()
     T_offline = time.perf_counter() - t0
     ctx = mk(rate)
@@ -415,7 +419,7 @@ def measure_learned(pkg, wl, torch, P, n_runs, n_snap_runs, run_steps, epochs, r
         "workload": f"learned reduced step, 4-bead chain P={P}, R={R} (input {3 * R + 1}, width 128, SiLU), "
                     f"{n_runs} training runs x {run_steps} explicit steps at shear rates log-uniform [0.1, 10] "
                     f"({pairs} pairs; basis from the snapshots of the first {n_snap_runs} runs), {epochs} epochs of "
-                    f"batch 64 at lr 2e-3, input noise {LEARNED_INPUT_NOISE} increment standard deviations; rollout "
+                    f"batch 64 at lr {LEARNED_LR:g} falling to {LEARNED_LR_FINAL:g} (half cosine), input noise {LEARNED_INPUT_NOISE} increment standard deviations; rollout "
                     f"{rollout_steps} steps at the held-out rate {rate}, checked every 50 steps (increment residual "
                     f"<= 0.2, energy-law gap <= 0.5)",
         "offline_s": T_offline, "final_loss": float(losses[-1]), "first_loss": float(losses[0]),
@@ -451,7 +455,7 @@ def measure_learned_fene(pkg, wl, torch, n_runs, R, run_steps, epochs, rollout_s
     return {
         "workload": f"learned reduced step, 6-bead FENE chain P={P}, D=15, b_max={cfg['b_max']}, R={R} per bond "
                     f"(input {5 * R + 1}, width 128, SiLU), {n_runs} training runs x {run_steps} explicit steps at "
-                    f"shear rates log-uniform [0.3, 3] ({pairs} pairs), {epochs} epochs of batch 64 at lr 2e-3, input "
+                    f"shear rates log-uniform [0.3, 3] ({pairs} pairs), {epochs} epochs of batch 64 at lr {LEARNED_LR:g} falling to {LEARNED_LR_FINAL:g}, input "
                     f"noise {LEARNED_INPUT_NOISE}; rollout {rollout_steps} steps at the held-out rate {rate}, checked "
                     f"every 50 steps (increment residual <= 0.2, energy-law gap <= 0.5)",
         "offline_s": T_offline, "final_loss": float(losses[-1]), "first_loss": float(losses[0]),
@@ -596,6 +600,7 @@ def main():
     ap.add_argument("--learned-run-steps", type=int, default=300)
     ap.add_argument("--learned-epochs", type=int, default=60)
     ap.add_argument("--fene-learned-runs", type=int, default=48)
+    ap.add_argument("--learned-seed", type=int, default=3, help="seed of the training order and input noise")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -667,7 +672,7 @@ def main():
                          ("batched", lambda: measure_batched(pkg, wl, torch, args.batched_steps)),
                          ("learned", lambda: measure_learned(pkg, wl, torch, P, args.learned_runs,
                                                             args.learned_snapshot_runs, args.learned_run_steps,
-                                                            args.learned_epochs, 300)),
+                                                            args.learned_epochs, 300, args.learned_seed)),
                          ("learned_fene", lambda: measure_learned_fene(pkg, wl, torch, args.fene_learned_runs, 108,
                                                                        300, 200, 300)),
                          ("implicit_predictor", lambda: measure_predictor(pkg, wl, torch, P, 100)),

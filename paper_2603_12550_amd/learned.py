@@ -50,15 +50,19 @@ def training_set(mlp: Mlp, trajectories):
 
 
 def train(mlp: Mlp, X: torch.Tensor, T: torch.Tensor, epochs: int, batch: int, lr: float, seed: int = 0,
-          input_noise: float = 0.0):
+          input_noise: float = 0.0, lr_final=None):
     """Fits the scaling, then `epochs` passes in seeded random order (with input
     noise of `input_noise` increment standard deviations, vds_mlp_set_input_noise);
-    returns the losses."""
+    returns the losses.  With `lr_final` the step size falls from `lr` to
+    `lr_final` along a half cosine over the epochs, else it stays at `lr`."""
     mlp.fit_scaling(X, T)
     mlp.set_input_noise(input_noise, seed)
     gen = torch.Generator(device="cpu").manual_seed(seed)
     losses = []
-    for _ in range(epochs):
+    for e in range(epochs):
+        rate = lr
+        if lr_final is not None and epochs > 1:
+            rate = lr_final + (lr - lr_final) * 0.5 * (1.0 + np.cos(np.pi * e / (epochs - 1)))
         order = torch.randperm(X.shape[0], generator=gen).to(torch.int32).to(X.device)
-        losses.append(mlp.train_epoch(X, T, batch, lr, order=order))
+        losses.append(mlp.train_epoch(X, T, batch, rate, order=order))
     return np.array(losses)
