@@ -21,27 +21,31 @@ using namespace vds;
 namespace {
 
 // q_k = U p_k for the nb bonds k: thread i sums over r in order, reading U
-// column by column (coalesced over i; eight columns in flight), so U is read
+// column by column (coalesced over i; sixteen columns in flight), so U is read
 // once.
-__global__ __launch_bounds__(64) void k_pod_reconstruct(const float *__restrict__ U, int64_t m, int R, int nb,
-                                                        const float *__restrict__ p, float *__restrict__ q) {
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+constexpr int kReconThreads = 256;
+constexpr int kReconInFlight = 16;
+
+__global__ __launch_bounds__(kReconThreads) void k_pod_reconstruct(const float *__restrict__ U, int64_t m, int R,
+                                                                   int nb, const float *__restrict__ p,
+                                                                   float *__restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * kReconThreads + threadIdx.x;
   if (i >= m) return;
   float acc[kMaxNb];
 #pragma unroll
   for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
   const float *u = U + i;
   int r = 0;
-  for (; r + 8 <= R; r += 8) {
-    float uv[8];
+  for (; r + kReconInFlight <= R; r += kReconInFlight) {
+    float uv[kReconInFlight];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) uv[j] = u[(int64_t)(r + j) * m];
+    for (int j = 0; j < kReconInFlight; ++j) uv[j] = u[(int64_t)(r + j) * m];
 #pragma unroll
     for (int k = 0; k < kMaxNb; ++k)
       if (k < nb) {
         const float *pk = p + (int64_t)k * R + r;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[k] = fmaf(uv[j], pk[j], acc[k]);
+        for (int j = 0; j < kReconInFlight; ++j) acc[k] = fmaf(uv[j], pk[j], acc[k]);
       }
   }
   for (; r < R; ++r) {
@@ -56,50 +60,54 @@ __global__ __launch_bounds__(64) void k_pod_reconstruct(const float *__restrict_
 }
 
 constexpr int kProjThreads = 256;
-constexpr int kProjChunks = 16;
+constexpr int kProjChunks = 32;
+constexpr int kProjRows = 8;
 
-// First stage of p_k[r] = U_r . q_k: block (r, c) takes chunk c of the rows,
-// threads stride over it (four rows in flight), then a fixed-order block
-// reduction per bond into part[c][k][r].
+// First stage of p_k[r] = U_r . q_k: block (g, c) takes the rows
+// r = 8 g .. 8 g + 7 of U against chunk c of the positions; a thread reads
+// q_k[i] once for all eight rows (thirteen loads in flight per position), so U
+// is read once and q once per eight rows.  Then a fixed-order block reduction
+// per (row, bond) into part[c][k][r].
 __global__ __launch_bounds__(kProjThreads) void k_pod_project(const float *__restrict__ U, int64_t m, int R, int nb,
                                                               const float *__restrict__ q, float *__restrict__ part) {
-  __shared__ float red[kMaxNb][kProjThreads / 64];
-  const int r = blockIdx.x, c = blockIdx.y;
+  __shared__ float red[kProjRows * kMaxNb][kProjThreads / 64];
+  const int r0 = (int)blockIdx.x * kProjRows, c = (int)blockIdx.y;
+  const int nr = min(kProjRows, R - r0);
   const int64_t len = (m + kProjChunks - 1) / kProjChunks, i0 = c * len, i1 = min(m, i0 + len);
-  const float *u = U + (int64_t)r * m;
-  float acc[kMaxNb];
+  float acc[kProjRows][kMaxNb];
 #pragma unroll
-  for (int k = 0; k < kMaxNb; ++k) acc[k] = 0.f;
-  int64_t i = i0 + threadIdx.x;
-  for (; i + 3 * kProjThreads < i1; i += 4 * kProjThreads) {
-    float uv[4];
+  for (int j = 0; j < kProjRows; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) uv[j] = u[i + j * kProjThreads];
+    for (int k = 0; k < kMaxNb; ++k) acc[j][k] = 0.f;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kProjThreads) {
+    float qv[kMaxNb];
 #pragma unroll
-    for (int k = 0; k < kMaxNb; ++k)
-      if (k < nb) {
+    for (int k = 0; k < kMaxNb; ++k) qv[k] = k < nb ? q[(int64_t)k * m + i] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[k] = fmaf(uv[j], q[(int64_t)k * m + i + j * kProjThreads], acc[k]);
-      }
-  }
-  for (; i < i1; i += kProjThreads) {
-    const float ui = u[i];
+    for (int j = 0; j < kProjRows; ++j) {
+      const float u = j < nr ? U[(int64_t)(r0 + j) * m + i] : 0.f;
 #pragma unroll
-    for (int k = 0; k < kMaxNb; ++k)
-      if (k < nb) acc[k] = fmaf(ui, q[(int64_t)k * m + i], acc[k]);
+      for (int k = 0; k < kMaxNb; ++k) acc[j][k] = fmaf(u, qv[k], acc[j][k]);
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < kMaxNb; ++k) {
-    float v = acc[k];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) red[k][wave] = v;
-  }
+  for (int j = 0; j < kProjRows; ++j)
+#pragma unroll
+    for (int k = 0; k < kMaxNb; ++k) {
+      float v = acc[j][k];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) red[j * kMaxNb + k][wave] = v;
+    }
   __syncthreads();
-  if (threadIdx.x < nb) {
-    float v = 0.f;
-    for (int w = 0; w < kProjThreads / 64; ++w) v += red[threadIdx.x][w];
-    part[((int64_t)c * nb + threadIdx.x) * R + r] = v;
+  const int t = threadIdx.x;
+  if (t < kProjRows * kMaxNb) {
+    const int j = t / kMaxNb, k = t % kMaxNb;
+    if (j < nr && k < nb) {
+      float v = 0.f;
+      for (int w = 0; w < kProjThreads / 64; ++w) v += red[t][w];
+      part[((int64_t)c * nb + k) * R + r0 + j] = v;
+    }
   }
 }
 
@@ -116,7 +124,7 @@ __global__ void k_pod_project_sum(const float *__restrict__ part, int R, int nb,
 
 namespace vds {
 void launch_pod_reconstruct(const float *U, int64_t m, int R, int nb, const float *p, float *q, hipStream_t s) {
-  k_pod_reconstruct<<<(unsigned)((m + 63) / 64), 64, 0, s>>>(U, m, R, nb, p, q);
+  k_pod_reconstruct<<<(unsigned)((m + kReconThreads - 1) / kReconThreads), kReconThreads, 0, s>>>(U, m, R, nb, p, q);
 }
 }  // namespace vds
 
@@ -325,7 +333,8 @@ vds_status vds_pod_project(vds_ctx c, const float *U, int32_t R, const float *q,
   const int nb = c->prob.nb;
   float *part = static_cast<float *>(ws);
   timed(c, VDS_TIMER_PROJ, 4.0 * m * R, [&] {
-    k_pod_project<<<dim3((unsigned)R, kProjChunks), kProjThreads, 0, c->stream>>>(U, m, R, nb, q, part);
+    k_pod_project<<<dim3((unsigned)((R + kProjRows - 1) / kProjRows), kProjChunks), kProjThreads, 0, c->stream>>>(
+        U, m, R, nb, q, part);
     k_pod_project_sum<<<(nb * R + 255) / 256, 256, 0, c->stream>>>(part, R, nb, p);
   });
   return hip_check(c, hipGetLastError(), "project");
