@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kRedBlock) void k_prep(EvalParams p, const float *_
 // Component n of row I summed over its partial-sum slots in slot order, in FP64.
 __device__ inline double sum_splits(const EvalParams &p, const float *__restrict__ partial, const SplitMap &splits,
                                     int64_t I, int n) {
-  return ordered_sum<double>(partial + I * 16 + n, splits.count(I), p.Ppad * 16);
+  return ordered_sum<double>(partial + I * splits.width + n, splits.count(I), p.Ppad * splits.width);
 }
 
 // Pass-A finalisation: S_I = w_I + sum_{J != I} w_J e_IJ,
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(kRedBlock) void k_density_out(const float *__restri
                                                            float *__restrict__ f) {
   const int64_t I = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
   if (I >= ny) return;
-  f[I] = ordered_sum<float>(partial + I * 16 + D, splits.count(I), stride_rows * 16) * norm;
+  f[I] = ordered_sum<float>(partial + I * splits.width + D, splits.count(I), stride_rows * splits.width) * norm;
 }
 
 // ---- batched ensembles: the same bodies, per ensemble ----

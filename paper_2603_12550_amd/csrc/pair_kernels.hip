@@ -252,9 +252,10 @@ constexpr int mfma32_waves() {
 
 // One segment of the FP32 32x32 form: the workgroup's four waves take row
 // group rg (wave w: 32-row blocks (4 rg + w) RB ..), the columns of chunks
-// [c0, c1), and write partial sums for their rows to out[row][16].  Every
-// thread of the workgroup calls it with the same arguments (it holds barriers).
-template <int D, int RB>
+// [c0, c1), and write partial sums for their rows to out[row][W] (W >= D + 1).
+// Every thread of the workgroup calls it with the same arguments (it holds
+// barriers).
+template <int D, int RB, int W>
 __device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC,
                                const float4 *__restrict__ VC, int rg, int c0, int c1, int exclude_self, float kappa,
                                float *__restrict__ out, Mfma32Lds<D, RB> &lds) {
@@ -437,8 +438,8 @@ __device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int
 #pragma unroll
       for (int g = 0; g < S::NG; ++g) {
         const int n = 4 * g + (lane & 3);
-        if (n < D) out[row * 16 + n] = (float)((double)xr[row * D + n] * sv - f * tot[r][g][sidx][lane]);
-        else if (n == D) out[row * 16 + n] = (float)sv;
+        if (n < D) out[row * W + n] = (float)((double)xr[row * D + n] * sv - f * tot[r][g][sidx][lane]);
+        else if (n == D) out[row * W + n] = (float)sv;
       }
     }
   }
@@ -465,8 +466,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
     const int c1 = (int)min(nch, u_end - rg * nch);
     const int slot = (int)(L - map.run_of(rg * nch));
     u = rg * nch + c1;
-    mfma32_segment<D, RB>(xr, nrb32, KC, VC, (int)rg, c0, c1, exclude_self, kappa,
-                          partial + (int64_t)slot * part_stride_rows * 16, lds);
+    // slots in the compact layout: D + 1 floats per row
+    mfma32_segment<D, RB, D + 1>(xr, nrb32, KC, VC, (int)rg, c0, c1, exclude_self, kappa,
+                                 partial + (int64_t)slot * part_stride_rows * (D + 1), lds);
   }
 }
 
@@ -483,7 +485,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
     const int64_t P = ens[item.x].p.P;
     const int nrb32 = (int)(ens[item.x].p.Ppad / 32);
     const float kappa = ens[item.x].p.kappa;
-    mfma32_segment<D, RB>(xc + off * D, nrb32, reinterpret_cast<const float4 *>(KC + off * KK * 4),
+    mfma32_segment<D, RB, 16>(xc + off * D, nrb32, reinterpret_cast<const float4 *>(KC + off * KK * 4),
                           reinterpret_cast<const float4 *>(VC + off * 16), item.y, 0, (int)((P + 31) / 32), 1, kappa,
                           partial + off * 16, lds);
   }
@@ -963,12 +965,13 @@ int device_cu_count() {
 
 }  // namespace
 
-SplitMap pair_split_map(const vds_tuning &t, int64_t nrow_blocks, int64_t ncol_chunks) {
+SplitMap pair_split_map(const vds_tuning &t, int D, int64_t nrow_blocks, int64_t ncol_chunks) {
   SplitMap m;
   if (t.impl != VDS_PAIR_MFMA32) {
     m.splits = t.col_splits;
     return m;
   }
+  m.width = D + 1;  // the compact layout
   // rows in blocks of 32, four waves of RB blocks per row group; columns in chunks of 32
   const int rb = t.rows_per_wave;
   const int64_t nrb32 = nrow_blocks / 2;
@@ -997,7 +1000,7 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
     // rows in blocks of 32 (nrow_blocks counts 16-row blocks of a multiple of 256 rows, so
     // every row group of 4 waves x RB blocks is whole); columns in chunks of 32, the last
     // inside the padding (ncol_pad is a multiple of 256 columns), whose weights are zero
-    const SplitMap map = pair_split_map(t, nrow_blocks, ncol_chunks);
+    const SplitMap map = pair_split_map(t, D, nrow_blocks, ncol_chunks);
     const int rb = t.rows_per_wave;
     const int nrb32 = (int)(nrow_blocks / 2);
     switch (D) {

@@ -112,7 +112,7 @@ __global__ void k_rom_scalars(const float *__restrict__ part, SplitMap splits, i
     invS[I] = 0.f;
     return;
   }
-  const double o = ordered_sum<double>(part + I * 16 + D, splits.count(I), Ppad * 16);
+  const double o = ordered_sum<double>(part + I * splits.width + D, splits.count(I), Ppad * splits.width);
   const double Si = (double)S[I];
   T[I] = (float)(o + (double)wv[I] / Si);
   invS[I] = (float)(1.0 / Si);

@@ -97,7 +97,7 @@ void pair_pass(vds_ctx c, const float *V, const float *wscale, const int *done) 
 // with the pair implementation.
 void apply_tuning(vds_ctx c, const vds_tuning &t) {
   c->tune = t;
-  c->smap = pair_split_map(t, c->ep.Ppad / 16, ncol_chunks(c));
+  c->smap = pair_split_map(t, c->ep.D, c->ep.Ppad / 16, ncol_chunks(c));
   c->ep.vhalf = (t.impl == VDS_PAIR_MFMA_F16X2 || t.impl == VDS_PAIR_MFMA_F16X2_ALL) ? 1 : 0;
   c->ep.qhalf = t.impl == VDS_PAIR_MFMA_F16X2_ALL ? 1 : 0;
   c->ep.f32x = t.impl == VDS_PAIR_MFMA32 ? 1 : 0;
@@ -713,7 +713,7 @@ vds_status vds_density_at(vds_ctx c, const float *q, const float *w, const float
       launch_pair_pass(c->tune, e.KK, e.D, c->QB, nrb, c->KA, c->VA, ncol_chunks(c), e.Ppad, c->xc, false,
                        c->wscale, c->f16, c->part, e.Ppad, nullptr, c->stream, e.kappa);
     });
-    launch_density_out(e, c->part, pair_split_map(c->tune, nrb, ncol_chunks(c)), nr, norm, f + r0, c->stream);
+    launch_density_out(e, c->part, pair_split_map(c->tune, e.D, nrb, ncol_chunks(c)), nr, norm, f + r0, c->stream);
   }
   return hip_check(c, hipGetLastError(), "launch");
 }

@@ -138,14 +138,16 @@ __host__ __device__ inline int strided_count(int first, int end, int step) {
   return first < end ? (end - first + step - 1) / step : 0;
 }
 
-// Where a pair pass leaves its partial sums: partial[slot][row][16] for the
-// slots 0 .. count(row) - 1, which the consuming kernels add in slot order.
+// Where a pair pass leaves its partial sums: partial[slot][row][width] for the
+// slots 0 .. count(row) - 1, which the consuming kernels add in slot order
+// (width 16, or D + 1 where the pass writes only the D + 1 sums of a row).
 // Fixed splits (G == 0): every row has `splits` slots, one per column range.
 // Balanced grid (VDS_PAIR_MFMA32): the row-group-major sequence of
 // (row group, column chunk) units is cut into G runs of equal length, one per
 // workgroup; a run leaves one slot in every row group it covers, and the runs
 // covering a row group fill its slots in run order.
 struct SplitMap {
+  int width = 16;          // floats per row of a slot: 16, or D + 1 for the compact layout
   int splits = 1;          // fixed splits; with G > 0, a bound on count()
   int G = 0;               // runs (workgroups) of the balanced grid, 0 for fixed splits
   int rows_per_group = 0;  // rows of one row group
@@ -176,8 +178,10 @@ struct PackOps {
 enum CombineMode { MODE_TERMS = 0, MODE_VELOCITY = 1, MODE_EXPLICIT = 2, MODE_PICARD = 3, MODE_OBS_ONLY = 4 };
 
 // ---- launchers (pair_kernels.hip) ----
-// Writes partial[split][row][0..D) = sum_J e wh (x_row - x_J) and [D] = sum_J e wh,
-// J = row left out when exclude_self (rows are the particles themselves).
+// Writes partial[slot][row][0..D) = sum_J e wh (x_row - x_J) and [D] = sum_J e wh
+// in the layout pair_split_map gives for the pass (slot width 16, or D + 1 for
+// VDS_PAIR_MFMA32), J = row left out when exclude_self (rows are the particles
+// themselves).
 // `xc` holds the centred row coordinates the difference sums use; ncol_pad is
 // the padded column count the V operand was written for.  With the FP16-split
 // implementation the V weights were divided by *wscale (NULL: by one), which
@@ -192,7 +196,7 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
 bool pair_shape_ok(const vds_tuning &t, int D);
 // The slots a pass of tuning t over nrow_blocks 16-row blocks and ncol_chunks
 // 16-column chunks writes (launch_pair_pass takes its grid from the same map).
-SplitMap pair_split_map(const vds_tuning &t, int64_t nrow_blocks, int64_t ncol_chunks);
+SplitMap pair_split_map(const vds_tuning &t, int D, int64_t nrow_blocks, int64_t ncol_chunks);
 // Batched pair pass over the (ensemble, row tile) work list `items` with a
 // persistent grid of `grid` workgroups; rb = row blocks per wavefront.
 // impl selects the pair implementation (VDS_PAIR_MFMA or one of the FP16-split
