@@ -60,11 +60,13 @@ def test_pod_gram_matches_exact_products(lib):
     assert _rel(G, X64 @ X64.T) < 1e-6
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (17, 1), (300, 900), (7001, 193), (60000, 300)])
+@pytest.mark.parametrize("m,n", [(1, 1), (17, 1), (300, 900), (7001, 193), (60000, 300), (4097, 513),
+                                 (60000, 900)])
 def test_pod_gram_one_triangle_mirrored(lib, m, n):
     """The Gram launch computes the tiles on and above the diagonal and mirrors
     the rest: exactly symmetric, and within FP32 accumulation of the
-    FP64 product, over single-tile, ragged and many-split shapes."""
+    FP64 product, over single-tile, ragged and many-split shapes (n = 513:
+    one ragged column of tiles; 60000 x 900: the POD workload's shape)."""
     rng = np.random.default_rng(m + n)
     X = wl.to_f32(rng.standard_normal((n, m)))
     ctx = lib.Context(1, 10, 0.5, poison=True)
