@@ -947,8 +947,6 @@ static void launch_mfma32_d(int rb, const float *xr, int nrb32, const float *KC,
     k_pair_mfma32<D, 2><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, map, ex, kappa, partial, stride, done);
 }
 
-namespace {
-
 // Compute units of the current device (256 on MI355X), looked up once per device.
 int device_cu_count() {
   constexpr int kDevs = 64;
@@ -962,8 +960,6 @@ int device_cu_count() {
   }
   return cache[dev];
 }
-
-}  // namespace
 
 SplitMap pair_split_map(const vds_tuning &t, int D, int64_t nrow_blocks, int64_t ncol_chunks) {
   SplitMap m;

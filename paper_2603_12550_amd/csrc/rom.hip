@@ -28,6 +28,18 @@ constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the ke
 constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
 constexpr int kK32Waves = 8;  // waves (32-row blocks) per workgroup of the FP32 32x32 kernel-GEMM
 constexpr int kK32NB = 3;     // its column blocks of 32 per workgroup: 96 columns
+constexpr int kK32Tile = kK32Waves * 32 * 32 * kK32NB;  // floats of one (row group, column group) output tile
+
+// Runs (workgroups) of the FP32 kernel-GEMM's balanced grid for Ppad rows and
+// ncols output columns: two per compute unit (one round), at most one per
+// (row group, column group) item, so that no item spans more than two runs;
+// a multiple of 8 from 8 on (consecutive runs share an XCD).
+int kgemm32_runs(int64_t Ppad, int ncols) {
+  const int64_t items = (Ppad / 32 + kK32Waves - 1) / kK32Waves * ((ncols + 32 * kK32NB - 1) / (32 * kK32NB));
+  int64_t G = std::min<int64_t>(2 * (int64_t)device_cu_count(), items);
+  if (G >= 8) G -= G % 8;
+  return (int)std::max<int64_t>(G, 1);
+}
 
 struct RomLayout {
   size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, pprev, total;
@@ -62,9 +74,11 @@ RomLayout rom_layout(const vds_problem &p, int R) {
   L.T = take(sizeof(float) * Ppad);
   L.invS = take(sizeof(float) * Ppad);
   const int64_t m = 3 * P;
+  // (the GEMMs' split partials, or the kernel-GEMM's continuation tiles: one per run)
   const size_t part = std::max({sizeof(float) * (size_t)gemm_splits(3 * R, 3 * R, P) * 9 * R * R,
                                 sizeof(float) * (size_t)gemm_splits(R, R, P) * R * R,
-                                sizeof(float) * (size_t)m * p.nb});
+                                sizeof(float) * (size_t)m * p.nb,
+                                sizeof(float) * (size_t)kgemm32_runs(Ppad, ncols) * kK32Tile});
   L.part = take(part);
   L.red = take(sizeof(double) * 16);
   L.psave = take(sizeof(float) * (size_t)p.nb * R);
@@ -254,10 +268,17 @@ __global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict
   Bk[t] = v;
 }
 
+// Balanced grid: the (column group, row group) items, column-group major,
+// times their nch chunks, cut into G equal runs (one workgroup each; at most
+// one run per item, so an item meets at most two runs).  A run's segment that
+// starts an item writes the item's output tile to Y; a run whose first segment
+// continues an item begun by the previous run writes that part to its slot,
+// slots[L] (kK32Tile floats: 256 rows x 96 columns), which k_kgemm32_fixup
+// then adds to Y.  Consecutive runs share an XCD (and its L2's B blocks).
 template <int D>
 __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_kernel_gemm32(
     const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC, int nch, const float4 *__restrict__ Bk,
-    int NCG, int ncols, float kappa, float *__restrict__ Y, int64_t ldy) {
+    int NCG, int ncols, float kappa, float *__restrict__ Y, int64_t ldy, float *__restrict__ slots) {
   constexpr int KP = mfma32_kslots(D), NK = KP / 2;
   constexpr int KF4 = KP * 8;             // float4s of a chunk's K operand
   constexpr int BF4 = 32 * 128 / 4;       // float4s of a chunk's B block
@@ -266,89 +287,130 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
   __shared__ float4 sb[2][SF4];
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, li = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int rb = (int)blockIdx.x * kK32Waves + wave;  // this wave's 32-row block
-  const int cg = (int)blockIdx.y;
-  // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
-  // row norm term (k == D + 1), 0 beyond
-  float qv[NK];
-  {
-    const int rr = rb < nrb32 ? rb : 0;  // waves past the rows compute on block 0, unwritten
-    const float *x = xr + ((int64_t)rr * 32 + li) * D;
-    float nrm = 0.f;
+  const int n_rg = (nrb32 + kK32Waves - 1) / kK32Waves;
+  const int64_t U = (int64_t)NCG * n_rg * nch;
+  const int G = (int)gridDim.x;
+  const int L = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int64_t u_end = (int64_t)(L + 1) * U / G;
+  for (int64_t u = (int64_t)L * U / G; u < u_end;) {
+    const int64_t item = u / nch;
+    const int c0 = (int)(u - item * nch);
+    const int c1 = (int)min((int64_t)nch, u_end - item * nch);
+    u = item * nch + c1;
+    const int cg = (int)(item / n_rg);
+    const int rb = (int)(item % n_rg) * kK32Waves + wave;  // this wave's 32-row block
+    // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
+    // row norm term (k == D + 1), 0 beyond
+    float qv[NK];
+    {
+      const int rr = rb < nrb32 ? rb : 0;  // waves past the rows compute on block 0, unwritten
+      const float *x = xr + ((int64_t)rr * 32 + li) * D;
+      float nrm = 0.f;
 #pragma unroll
-    for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
+      for (int a = 0; a < D; ++a) nrm = __builtin_fmaf(x[a], x[a], nrm);
 #pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      const int k = 2 * kk + h;
-      qv[kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? -kappa * nrm : 0.f));
-    }
-  }
-  auto src = [&](int c, int u) -> float4 {
-    return u < KF4 ? KC[(int64_t)c * KF4 + u] : Bk[((int64_t)c * NCG + cg) * BF4 + (u - KF4)];
-  };
-  float4 pre[NST];
-#pragma unroll
-  for (int i = 0; i < NST; ++i) {
-    const int u = t + kK32Waves * 64 * i;
-    if (u < SF4) sb[0][u] = src(0, u);
-  }
-  __syncthreads();
-  floatx16 acc[kK32NB];
-#pragma unroll
-  for (int nb = 0; nb < kK32NB; ++nb)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) {
-#pragma unroll
-      for (int i = 0; i < NST; ++i) {
-        const int u = t + kK32Waves * 64 * i;
-        pre[i] = u < SF4 ? src(c + 1, u) : float4{0.f, 0.f, 0.f, 0.f};
+      for (int kk = 0; kk < NK; ++kk) {
+        const int k = 2 * kk + h;
+        qv[kk] = k < D ? x[k < D ? k : 0] : (k == D ? 1.f : (k == D + 1 ? -kappa * nrm : 0.f));
       }
     }
-    const float *sK = reinterpret_cast<const float *>(sb[buf]) + h * 32 + li;
-    const float4 *sB = sb[buf] + KF4 + h * 128 + li;  // row J(v, h) = 8 (v / 4) + 4 h + v % 4
-    floatx16 z;
+    auto src = [&](int c, int uu) -> float4 {
+      return uu < KF4 ? KC[(int64_t)c * KF4 + uu] : Bk[((int64_t)c * NCG + cg) * BF4 + (uu - KF4)];
+    };
+    float4 pre[NST];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) z[v] = 0.f;
-#pragma unroll
-    for (int kk = 0; kk < NK; ++kk) z = __builtin_amdgcn_mfma_f32_32x32x2f32(sK[kk * 64], qv[kk], z, 0, 0, 0);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) z[v] = __builtin_amdgcn_exp2f(z[v]);
-    if (c == rb) {  // scalar branch: the self pair has Z_II = K_h(0) = 1 exactly
-      asm volatile("" ::: "memory");
-#pragma unroll
-      for (int v = 0; v < 16; ++v) z[v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 1.f : z[v];
-    }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float4 b = sB[(8 * (v >> 2) + (v & 3)) * 32];
-      const float bv[3] = {b.x, b.y, b.z};
-#pragma unroll
-      for (int nb = 0; nb < kK32NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[v], bv[nb], acc[nb], 0, 0, 0);
-    }
-    if (c + 1 < nch) {
-#pragma unroll
-      for (int i = 0; i < NST; ++i) {
-        const int u = t + kK32Waves * 64 * i;
-        if (u < SF4) sb[buf ^ 1][u] = pre[i];
-      }
+    for (int i = 0; i < NST; ++i) {
+      const int uu = t + kK32Waves * 64 * i;
+      if (uu < SF4) sb[0][uu] = src(c0, uu);
     }
     __syncthreads();
-  }
-  if (rb >= nrb32) return;
-  // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 96 cg + 32 nb + li
+    floatx16 acc[kK32NB];
 #pragma unroll
-  for (int nb = 0; nb < kK32NB; ++nb) {
-    const int col = cg * 32 * kK32NB + 32 * nb + li;
-    if (col >= ncols) break;
+    for (int nb = 0; nb < kK32NB; ++nb)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = (int64_t)rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-      Y[row * ldy + col] = acc[nb][v];
+      for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
+    for (int c = c0; c < c1; ++c) {
+      const int buf = (c - c0) & 1;
+      if (c + 1 < c1) {
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          const int uu = t + kK32Waves * 64 * i;
+          pre[i] = uu < SF4 ? src(c + 1, uu) : float4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      const float *sK = reinterpret_cast<const float *>(sb[buf]) + h * 32 + li;
+      const float4 *sB = sb[buf] + KF4 + h * 128 + li;  // row J(v, h) = 8 (v / 4) + 4 h + v % 4
+      floatx16 z;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) z[v] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) z = __builtin_amdgcn_mfma_f32_32x32x2f32(sK[kk * 64], qv[kk], z, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) z[v] = __builtin_amdgcn_exp2f(z[v]);
+      if (c == rb) {  // scalar branch: the self pair has Z_II = K_h(0) = 1 exactly
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int v = 0; v < 16; ++v) z[v] = (8 * (v >> 2) + 4 * h + (v & 3)) == li ? 1.f : z[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const float4 b = sB[(8 * (v >> 2) + (v & 3)) * 32];
+        const float bv[3] = {b.x, b.y, b.z};
+#pragma unroll
+        for (int nb = 0; nb < kK32NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[v], bv[nb], acc[nb], 0, 0, 0);
+      }
+      if (c + 1 < c1) {
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          const int uu = t + kK32Waves * 64 * i;
+          if (uu < SF4) sb[buf ^ 1][uu] = pre[i];
+        }
+      }
+      // every chunk ends at a barrier, the segment's last one too: the next
+      // segment's first stage overwrites buffer 0
+      __syncthreads();
+    }
+    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 96 cg + 32 nb + li
+    if (c0 > 0) {  // a continued item: the whole tile to this run's slot
+      float *o = slots + (int64_t)L * kK32Tile;
+#pragma unroll
+      for (int nb = 0; nb < kK32NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          o[(wave * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * (32 * kK32NB) + 32 * nb + li] = acc[nb][v];
+    } else if (rb < nrb32) {
+#pragma unroll
+      for (int nb = 0; nb < kK32NB; ++nb) {
+        const int col = cg * 32 * kK32NB + 32 * nb + li;
+        if (col >= ncols) break;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = (int64_t)rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          Y[row * ldy + col] = acc[nb][v];
+        }
+      }
     }
   }
+}
+
+// Y += the slot of every run whose first segment continued an item (block
+// (x, L): elements x 256 .. of run L's tile).  An item meets at most two runs,
+// so no two slots add to the same tile.
+__global__ void k_kgemm32_fixup(const float *__restrict__ slots, int nrb32, int nch, int NCG, int ncols,
+                                float *__restrict__ Y, int64_t ldy) {
+  const int L = (int)blockIdx.y, G = (int)gridDim.y;
+  const int n_rg = (nrb32 + kK32Waves - 1) / kK32Waves;
+  const int64_t U = (int64_t)NCG * n_rg * nch;
+  const int64_t u0 = (int64_t)L * U / G;
+  const int64_t item = u0 / nch;
+  if (u0 == item * nch) return;  // the run starts its first item
+  const int cg = (int)(item / n_rg), rg = (int)(item % n_rg);
+  const int e = (int)blockIdx.x * 256 + threadIdx.x;
+  if (e >= kK32Tile) return;
+  const int r = e / (32 * kK32NB), cc = e % (32 * kK32NB);
+  const int64_t row = (int64_t)rg * 32 * kK32Waves + r;
+  const int col = cg * 32 * kK32NB + cc;
+  if (row < (int64_t)nrb32 * 32 && col < ncols) Y[row * ldy + col] += slots[(int64_t)L * kK32Tile + e];
 }
 
 // ---- FP16-split kernel-GEMM (used with the FP16-split pair kernels) ---------
@@ -938,18 +1000,21 @@ vds_status freeze(vds_rom r, const float *p) {
     const int NCG = (int)((2 * 3 * R + 32 * kK32NB - 1) / (32 * kK32NB));
     k_rom_b32<<<nblk256(Ppad * NCG * 128), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, NCG, r->Bsw);
     const int nrb32 = (int)(Ppad / 32), nch = (int)((P + 31) / 32);
-    const dim3 grid((unsigned)((nrb32 + kK32Waves - 1) / kK32Waves), (unsigned)NCG);
+    const int ncols = 2 * 3 * R;
+    const int G = kgemm32_runs(Ppad, ncols);
     const float4 *kc = reinterpret_cast<const float4 *>(c->KA), *bk = reinterpret_cast<const float4 *>(r->Bsw);
     const double flops = 2.0 * (double)P * P * 2 * 3 * R;
-    const int ncols = 2 * 3 * R;
+    float *slots = reinterpret_cast<float *>(r->part);
     timed(c, VDS_TIMER_KGEMM, flops, [&] {
       switch (c->ep.D) {
-        case 3: k_kernel_gemm32<3><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
-        case 6: k_kernel_gemm32<6><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
-        case 9: k_kernel_gemm32<9><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
-        case 12: k_kernel_gemm32<12><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
-        default: k_kernel_gemm32<15><<<grid, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy); break;
+        case 3: k_kernel_gemm32<3><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
+        case 6: k_kernel_gemm32<6><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
+        case 9: k_kernel_gemm32<9><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
+        case 12: k_kernel_gemm32<12><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
+        default: k_kernel_gemm32<15><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
       }
+      k_kgemm32_fixup<<<dim3((unsigned)((kK32Tile + 255) / 256), (unsigned)G), 256, 0, s>>>(slots, nrb32, nch, NCG, ncols,
+                                                                                           r->Y, L.ldy);
     });
   } else {
     // the 16x16 FP32 forms (VDS_PAIR_MFMA, VDS_PAIR_VALU) read the 16-row operand layout

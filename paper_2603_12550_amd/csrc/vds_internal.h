@@ -194,6 +194,8 @@ void launch_pair_pass(const vds_tuning &t, int KK, int D, const float *QB, int64
                       bool exclude_self, const float *wscale, const F16Operands &f16, float *partial,
                       int64_t part_stride_rows, const int *done, hipStream_t s, float kappa = 0.f);
 bool pair_shape_ok(const vds_tuning &t, int D);
+// Compute units of the current device (256 on MI355X; 256 if the query fails).
+int device_cu_count();
 // The slots a pass of tuning t over nrow_blocks 16-row blocks and ncol_chunks
 // 16-column chunks writes (launch_pair_pass takes its grid from the same map).
 SplitMap pair_split_map(const vds_tuning &t, int D, int64_t nrow_blocks, int64_t ncol_chunks);
