@@ -291,12 +291,18 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
   const int64_t U = (int64_t)NCG * n_rg * nch;
   const int G = (int)gridDim.x;
   const int L = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
-  const int64_t u_end = (int64_t)(L + 1) * U / G;
-  for (int64_t u = (int64_t)L * U / G; u < u_end;) {
-    const int64_t item = u / nch;
-    const int c0 = (int)(u - item * nch);
-    const int c1 = (int)min((int64_t)nch, u_end - item * nch);
-    u = item * nch + c1;
+  const int64_t u_beg = (int64_t)L * U / G, u_end = (int64_t)(L + 1) * U / G;
+  // the segments that start an item first (every run's first segment then
+  // starts at chunk 0, so the runs of a column group read its B blocks nearly
+  // in step through their XCD's L2), a continued item's part last
+  const int64_t i_first = u_beg / nch;
+  const bool continued = u_beg > i_first * nch;
+  const int64_t i_lo = continued ? i_first + 1 : i_first;
+  const int64_t n_seg = (u_end - 1) / nch - i_lo + 1 + (continued ? 1 : 0);
+  for (int64_t sgi = 0; sgi < n_seg; ++sgi) {
+    const int64_t item = continued && sgi == n_seg - 1 ? i_first : i_lo + sgi;
+    const int c0 = (int)(max(u_beg, item * nch) - item * nch);
+    const int c1 = (int)(min(u_end, (item + 1) * nch) - item * nch);
     const int cg = (int)(item / n_rg);
     const int rb = (int)(item % n_rg) * kK32Waves + wave;  // this wave's 32-row block
     // row operands: slot 2 kk + h of row I is x_I[k] (k < D), 1 (k == D), the
