@@ -45,6 +45,7 @@ struct RomLayout {
   size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, pprev, total;
   int NB16;
   int64_t ldy;
+  int kg_runs;  // runs of the FP32 kernel-GEMM's balanced grid (its continuation slots are sized for them)
 };
 
 RomLayout rom_layout(const vds_problem &p, int R) {
@@ -75,10 +76,11 @@ RomLayout rom_layout(const vds_problem &p, int R) {
   L.invS = take(sizeof(float) * Ppad);
   const int64_t m = 3 * P;
   // (the GEMMs' split partials, or the kernel-GEMM's continuation tiles: one per run)
+  L.kg_runs = kgemm32_runs(Ppad, ncols);
   const size_t part = std::max({sizeof(float) * (size_t)gemm_splits(3 * R, 3 * R, P) * 9 * R * R,
                                 sizeof(float) * (size_t)gemm_splits(R, R, P) * R * R,
                                 sizeof(float) * (size_t)m * p.nb,
-                                sizeof(float) * (size_t)kgemm32_runs(Ppad, ncols) * kK32Tile});
+                                sizeof(float) * (size_t)L.kg_runs * kK32Tile});
   L.part = take(part);
   L.red = take(sizeof(double) * 16);
   L.psave = take(sizeof(float) * (size_t)p.nb * R);
@@ -1007,7 +1009,7 @@ vds_status freeze(vds_rom r, const float *p) {
     k_rom_b32<<<nblk256(Ppad * NCG * 128), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, NCG, r->Bsw);
     const int nrb32 = (int)(Ppad / 32), nch = (int)((P + 31) / 32);
     const int ncols = 2 * 3 * R;
-    const int G = kgemm32_runs(Ppad, ncols);
+    const int G = L.kg_runs;  // fixed when the model was laid out: its slots hold G tiles
     const float4 *kc = reinterpret_cast<const float4 *>(c->KA), *bk = reinterpret_cast<const float4 *>(r->Bsw);
     const double flops = 2.0 * (double)P * P * 2 * 3 * R;
     float *slots = reinterpret_cast<float *>(r->part);
