@@ -51,6 +51,7 @@
 // and would swamp its neighbours' contributions in FP32.  The caller adds the
 // self weight back in FP64.
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "vds_internal.h"
@@ -947,18 +948,19 @@ static void launch_mfma32_d(int rb, const float *xr, int nrb32, const float *KC,
     k_pair_mfma32<D, 2><<<grid, 256, 0, s>>>(xr, nrb32, kc, vc, map, ex, kappa, partial, stride, done);
 }
 
-// Compute units of the current device (256 on MI355X), looked up once per device.
+// Compute units of the current device (256 on MI355X), looked up once per
+// device (host threads may race to fill a slot; they store the same value).
 int device_cu_count() {
   constexpr int kDevs = 64;
-  static int cache[kDevs] = {};
+  static std::atomic<int> cache[kDevs];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return 256;
-  if (cache[dev] == 0) {
-    int n = 0;
+  int n = cache[dev].load(std::memory_order_relaxed);
+  if (n == 0) {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
-    cache[dev] = n;
+    cache[dev].store(n, std::memory_order_relaxed);
   }
-  return cache[dev];
+  return n;
 }
 
 SplitMap pair_split_map(const vds_tuning &t, int D, int64_t nrow_blocks, int64_t ncol_chunks) {
