@@ -255,11 +255,13 @@ constexpr int mfma32_waves() {
 // group rg (wave w: 32-row blocks (4 rg + w) RB ..), the columns of chunks
 // [c0, c1), and write partial sums for their rows to out[row][W] (W >= D + 1).
 // Every thread of the workgroup calls it with the same arguments (it holds
-// barriers).
+// barriers).  With run_len > 0 the segment is part of a run of run_len chunk
+// units of which done0 came before it, and every stage sets the waves' issue
+// priority by the share of the run still to do (see k_pair_mfma32).
 template <int D, int RB, int W>
 __device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC,
                                const float4 *__restrict__ VC, int rg, int c0, int c1, int exclude_self, float kappa,
-                               float *__restrict__ out, Mfma32Lds<D, RB> &lds) {
+                               float *__restrict__ out, Mfma32Lds<D, RB> &lds, int done0 = 0, int run_len = 0) {
   using S = Mfma32Shape<D>;
   // odd D: the last distance step holds only the row-norm slot and padding
   constexpr bool kFold = (D % 2) == 1;
@@ -373,6 +375,13 @@ __device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int
 #pragma unroll
       for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (; c < gend; c += kStage32) {
+      if (run_len > 0) {  // scalar: priority 3 while more than half the run is left, then 2, 1, 0 below 20 %, 5 %
+        const int rem = run_len - (done0 + (c - c0));
+        if (20 * rem > 10 * run_len) __builtin_amdgcn_s_setprio(3);
+        else if (20 * rem > 4 * run_len) __builtin_amdgcn_s_setprio(2);
+        else if (20 * rem > run_len) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+      }
       const int buf = ((c - c0) / kStage32) & 1;
       const int cn = c + kStage32;  // first chunk of the next stage
       float4 pre[kStage32][NST];    // the next stage, stored after this one's arithmetic
@@ -459,9 +468,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
   const int G = (int)gridDim.x;
   const int L = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   const int64_t nch = map.nch;
-  const int64_t u_end = map.run_start(L + 1);
+  const int64_t u_beg = map.run_start(L), u_end = map.run_start(L + 1);
+  // Four workgroups share a compute unit, and its SIMDs issue for the oldest
+  // ready wave first: left alone, the first workgroup placed runs ahead and
+  // the four finish one after another (at about 60, 75, 90 and 100 % of the
+  // pass), the last with one wave per SIMD to hide latency.  Each workgroup
+  // therefore lowers its waves' priority as its run progresses
+  // (mfma32_segment), so that the laggards are issued first and the four
+  // finish together.
   // one segment per row group this run covers: chunks [c0, c1) of row group rg
-  for (int64_t u = map.run_start(L); u < u_end;) {
+  for (int64_t u = u_beg; u < u_end;) {
     const int64_t rg = u / nch;
     const int c0 = (int)(u - rg * nch);
     const int c1 = (int)min(nch, u_end - rg * nch);
@@ -469,7 +485,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
     u = rg * nch + c1;
     // slots in the compact layout: D + 1 floats per row
     mfma32_segment<D, RB, D + 1>(xr, nrb32, KC, VC, (int)rg, c0, c1, exclude_self, kappa,
-                                 partial + (int64_t)slot * part_stride_rows * (D + 1), lds);
+                                 partial + (int64_t)slot * part_stride_rows * (D + 1), lds,
+                                 (int)(rg * nch + c0 - u_beg), (int)(u_end - u_beg));
   }
 }
 
