@@ -497,15 +497,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
     const int2 *__restrict__ items, int nitems, const EnsDesc *__restrict__ ens, const float *__restrict__ xc,
     const float *__restrict__ KC, const float *__restrict__ VC, int KK, float *__restrict__ partial) {
   __shared__ Mfma32Lds<D, RB> lds;
+  // this workgroup's chunks over all its items, for the issue priority by
+  // progress (see k_pair_mfma32)
+  int total = 0;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) total += (int)((ens[items[it].x].p.P + 31) / 32);
+  total = __builtin_amdgcn_readfirstlane(total);
+  int done = 0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
     const int64_t off = ens[item.x].pad_off;
     const int64_t P = ens[item.x].p.P;
     const int nrb32 = (int)(ens[item.x].p.Ppad / 32);
     const float kappa = ens[item.x].p.kappa;
+    const int nc = (int)((P + 31) / 32);
     mfma32_segment<D, RB, 16>(xc + off * D, nrb32, reinterpret_cast<const float4 *>(KC + off * KK * 4),
-                          reinterpret_cast<const float4 *>(VC + off * 16), item.y, 0, (int)((P + 31) / 32), 1, kappa,
-                          partial + off * 16, lds);
+                          reinterpret_cast<const float4 *>(VC + off * 16), item.y, 0, nc, 1, kappa,
+                          partial + off * 16, lds, done, total);
+    done += nc;
   }
 }
 

@@ -301,6 +301,8 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
   const bool continued = u_beg > i_first * nch;
   const int64_t i_lo = continued ? i_first + 1 : i_first;
   const int64_t n_seg = (u_end - 1) / nch - i_lo + 1 + (continued ? 1 : 0);
+  const int64_t run_len = u_end - u_beg;
+  int64_t seg_done = 0;  // units of the run in the segments before this one
   for (int64_t sgi = 0; sgi < n_seg; ++sgi) {
     const int64_t item = continued && sgi == n_seg - 1 ? i_first : i_lo + sgi;
     const int c0 = (int)(max(u_beg, item * nch) - item * nch);
@@ -338,6 +340,15 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
     for (int c = c0; c < c1; ++c) {
+      {  // scalar: issue priority by the share of the run still to do, so that the
+         // two workgroups of a CU finish together (the SIMDs issue for the oldest
+         // ready wave first): 3 above half, then 2, 1, 0 below 20 %, 5 %
+        const int64_t rem = run_len - (seg_done + (c - c0));
+        if (20 * rem > 10 * run_len) __builtin_amdgcn_s_setprio(3);
+        else if (20 * rem > 4 * run_len) __builtin_amdgcn_s_setprio(2);
+        else if (20 * rem > run_len) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+      }
       const int buf = (c - c0) & 1;
       if (c + 1 < c1) {
 #pragma unroll
@@ -398,6 +409,7 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
         }
       }
     }
+    seg_done += c1 - c0;
   }
 }
 
