@@ -261,7 +261,8 @@ constexpr int mfma32_waves() {
 template <int D, int RB, int W>
 __device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC,
                                const float4 *__restrict__ VC, int rg, int c0, int c1, int exclude_self, float kappa,
-                               float *__restrict__ out, Mfma32Lds<D, RB> &lds, int done0 = 0, int run_len = 0) {
+                               float *__restrict__ out, Mfma32Lds<D, RB> &lds, int64_t done0 = 0,
+                               int64_t run_len = 0) {
   using S = Mfma32Shape<D>;
   // odd D: the last distance step holds only the row-norm slot and padding
   constexpr bool kFold = (D % 2) == 1;
@@ -376,7 +377,7 @@ __device__ __forceinline__ void mfma32_segment(const float *__restrict__ xr, int
       for (int g = 0; g < S::NG; ++g) acc[r][g] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (; c < gend; c += kStage32) {
       if (run_len > 0) {  // scalar: priority 3 while more than half the run is left, then 2, 1, 0 below 20 %, 5 %
-        const int rem = run_len - (done0 + (c - c0));
+        const int64_t rem = run_len - (done0 + (c - c0));
         if (20 * rem > 10 * run_len) __builtin_amdgcn_s_setprio(3);
         else if (20 * rem > 4 * run_len) __builtin_amdgcn_s_setprio(2);
         else if (20 * rem > run_len) __builtin_amdgcn_s_setprio(1);
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
     // slots in the compact layout: D + 1 floats per row
     mfma32_segment<D, RB, D + 1>(xr, nrb32, KC, VC, (int)rg, c0, c1, exclude_self, kappa,
                                  partial + (int64_t)slot * part_stride_rows * (D + 1), lds,
-                                 (int)(rg * nch + c0 - u_beg), (int)(u_end - u_beg));
+                                 rg * nch + c0 - u_beg, u_end - u_beg);
   }
 }
 
@@ -499,10 +500,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mfma32_wave
   __shared__ Mfma32Lds<D, RB> lds;
   // this workgroup's chunks over all its items, for the issue priority by
   // progress (see k_pair_mfma32)
-  int total = 0;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) total += (int)((ens[items[it].x].p.P + 31) / 32);
-  total = __builtin_amdgcn_readfirstlane(total);
-  int done = 0;
+  int64_t total = 0;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) total += (ens[items[it].x].p.P + 31) / 32;
+  int64_t done = 0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 item = items[it];
     const int64_t off = ens[item.x].pad_off;
