@@ -96,6 +96,8 @@ def test_brownian_term_is_scaled_gradient_of_blob_energy():
     w = wl.random_weights(6, P)
     _, t1, t2 = vds.brownian_terms(x, w, h)
     b = t1 + t2
+    # the oracle's own Phi_w against the plain double loop
+    assert vds.blob_energy(x, w, h) == pytest.approx(_brute_phi(x, w, h), rel=1e-13, abs=1e-15)
     eps = 1e-5
     for I in (0, 4, 8):
         for a in range(D):
