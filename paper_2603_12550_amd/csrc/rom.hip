@@ -27,7 +27,8 @@ constexpr int kMaxR = 1024;
 constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the kernel-GEMM
 constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
 constexpr int kK32Waves = 8;  // waves (32-row blocks) per workgroup of the FP32 32x32 kernel-GEMM
-constexpr int kK32NB = 3;     // its column blocks of 32 per workgroup: 96 columns
+constexpr int kK32NB = 4;     // its column blocks of 32 per workgroup: 128 columns
+static_assert(kK32NB == 4, "B is read as one float4 per lane and row of a column group");
 constexpr int kK32Tile = kK32Waves * 32 * 32 * kK32NB;  // floats of one (row group, column group) output tile
 
 // Runs (workgroups) of the FP32 kernel-GEMM's balanced grid for Ppad rows and
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
 // ---- FP32 kernel-GEMM on 32x32 tiles (the operands of VDS_PAIR_MFMA32) -----
 //
 // Y[I][col] = sum_J Z_IJ B[J][col] with a workgroup of kK32Waves waves owning
-// kK32Waves 32-row blocks (256 rows) and kK32NB column blocks of 32 (96
+// kK32Waves 32-row blocks (256 rows) and kK32NB column blocks of 32 (128
 // columns).  Per chunk of 32 columns of Z it stages the chunk's B block and
 // the K operand of its distance product (the pair kernel's per-chunk KC
 // layout) in LDS once, double buffered with one barrier.  Each wave forms its
@@ -245,9 +246,9 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
 // sits in lane l at row J(v, l / 32), column 32 nb + l % 32.  FP32
 // accumulation over all columns of Z (as the FP16-split form: ~1e-6 of the
 // sums).
-// B of the FP32 32x32 kernel-GEMM, one block of 32 rows J x 96 columns per
-// (chunk c, column group cg): element (jj, col = 96 cg + 32 nb + l) at
-// [((c NCG + cg) 32 + jj) 128 + 4 l + nb] (slot nb = 3 of each lane is zero).
+// B of the FP32 32x32 kernel-GEMM, one block of 32 rows J x 128 columns per
+// (chunk c, column group cg): element (jj, col = 128 cg + 32 nb + l) at
+// [((c NCG + cg) 32 + jj) 128 + 4 l + nb], one float4 per lane and row.
 __global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict__ wv, const float *__restrict__ invS,
                           int64_t P, int64_t Ppad, int R, int NCG, float *__restrict__ Bk) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -275,7 +276,7 @@ __global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict
 // one run per item, so an item meets at most two runs).  A run's segment that
 // starts an item writes the item's output tile to Y; a run whose first segment
 // continues an item begun by the previous run writes that part to its slot,
-// slots[L] (kK32Tile floats: 256 rows x 96 columns), which k_kgemm32_fixup
+// slots[L] (kK32Tile floats: 256 rows x 128 columns), which k_kgemm32_fixup
 // then adds to Y.  Consecutive runs share an XCD (and its L2's B blocks).
 template <int D>
 __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_kernel_gemm32(
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const float4 b = sB[(8 * (v >> 2) + (v & 3)) * 32];
-        const float bv[3] = {b.x, b.y, b.z};
+        const float bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
         for (int nb = 0; nb < kK32NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[v], bv[nb], acc[nb], 0, 0, 0);
       }
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
       // segment's first stage overwrites buffer 0
       __syncthreads();
     }
-    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 96 cg + 32 nb + li
+    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 128 cg + 32 nb + li
     if (c0 > 0) {  // a continued item: the whole tile to this run's slot
       float *o = slots + (int64_t)L * kK32Tile;
 #pragma unroll
