@@ -27,26 +27,52 @@ constexpr int kMaxR = 1024;
 constexpr int kNBG = 8;       // 16-column output blocks per workgroup of the kernel-GEMM
 constexpr int kKgFlush = 8;   // chunks per FP32 accumulation group
 constexpr int kK32Waves = 8;  // waves (32-row blocks) per workgroup of the FP32 32x32 kernel-GEMM
-constexpr int kK32NB = 4;     // its column blocks of 32 per workgroup: 128 columns
-static_assert(kK32NB == 4, "B is read as one float4 per lane and row of a column group");
-constexpr int kK32Tile = kK32Waves * 32 * 32 * kK32NB;  // floats of one (row group, column group) output tile
+constexpr int kK32MaxNB = 4;  // its column blocks of 32 per workgroup: 1 to 4 (B holds 4 slots per lane and row)
+// floats of one (row group, column group) output tile with nb column blocks
+constexpr int kgemm32_tile(int nb) { return kK32Waves * 32 * 32 * nb; }
+
+// (row group, column group) items of the FP32 kernel-GEMM with nb column blocks
+int64_t kgemm32_items(int64_t Ppad, int ncols, int nb) {
+  return (Ppad / 32 + kK32Waves - 1) / kK32Waves * ((ncols + 32 * nb - 1) / (32 * nb));
+}
 
 // Runs (workgroups) of the FP32 kernel-GEMM's balanced grid for Ppad rows and
 // ncols output columns: two per compute unit (one round), at most one per
 // (row group, column group) item, so that no item spans more than two runs;
 // a multiple of 8 from 8 on (consecutive runs share an XCD).
-int kgemm32_runs(int64_t Ppad, int ncols) {
-  const int64_t items = (Ppad / 32 + kK32Waves - 1) / kK32Waves * ((ncols + 32 * kK32NB - 1) / (32 * kK32NB));
-  int64_t G = std::min<int64_t>(2 * (int64_t)device_cu_count(), items);
+int kgemm32_runs(int64_t Ppad, int ncols, int nb) {
+  int64_t G = std::min<int64_t>(2 * (int64_t)device_cu_count(), kgemm32_items(Ppad, ncols, nb));
   if (G >= 8) G -= G % 8;
   return (int)std::max<int64_t>(G, 1);
+}
+
+// Column blocks per workgroup: the count whose issue cycles per run are fewest.
+// Per chunk of an item, the distance product and the exponentials cost
+// 64 NK + 128 cycles and each column block 16 x 64; columns past ncols in the
+// last group are computed too.  Wide groups amortise the distances (at
+// P = 20000, R = 180: four blocks); where the items are fewer than the runs a
+// full round would hold (small P), narrow groups give more, shorter runs.
+int kgemm32_nb(int64_t Ppad, int ncols, int D) {
+  const double ko = 64.0 * (mfma32_kslots(D) / 2) + 128.0;
+  int best = kK32MaxNB;
+  double best_cost = 0.0;
+  for (int nb = kK32MaxNB; nb >= 1; --nb) {
+    const double items = (double)kgemm32_items(Ppad, ncols, nb);
+    const double cost = items * (ko + 1024.0 * nb) / kgemm32_runs(Ppad, ncols, nb);
+    if (nb == kK32MaxNB || cost < best_cost) {
+      best = nb;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 struct RomLayout {
   size_t Ude, Mbig, XH, I1, XB1, XB2, XB, Bsw, Y, qt, T, invS, part, red, psave, pprev, total;
   int NB16;
   int64_t ldy;
-  int kg_runs;  // runs of the FP32 kernel-GEMM's balanced grid (its continuation slots are sized for them)
+  int kg_nb;    // column blocks per workgroup of the FP32 kernel-GEMM
+  int kg_runs;  // runs of its balanced grid (its continuation slots are sized for them)
 };
 
 RomLayout rom_layout(const vds_problem &p, int R) {
@@ -69,7 +95,8 @@ RomLayout rom_layout(const vds_problem &p, int R) {
   L.XB2 = take(sizeof(float) * R * R);
   L.XB = take(sizeof(float) * R * R);
   // B of the kernel-GEMM: the 16-column swizzled layout, or that of the 32x32 form
-  const int64_t ncg32 = (ncols + 32 * kK32NB - 1) / (32 * kK32NB);
+  L.kg_nb = kgemm32_nb(Ppad, ncols, 3 * p.nb);
+  const int64_t ncg32 = (ncols + 32 * L.kg_nb - 1) / (32 * L.kg_nb);
   L.Bsw = take(sizeof(float) * (size_t)Ppad * std::max<int64_t>(L.ldy, ncg32 * 128));
   L.Y = take(sizeof(float) * (size_t)Ppad * L.ldy);
   L.qt = take(sizeof(float) * (size_t)p.nb * P * 3);
@@ -77,11 +104,11 @@ RomLayout rom_layout(const vds_problem &p, int R) {
   L.invS = take(sizeof(float) * Ppad);
   const int64_t m = 3 * P;
   // (the GEMMs' split partials, or the kernel-GEMM's continuation tiles: one per run)
-  L.kg_runs = kgemm32_runs(Ppad, ncols);
+  L.kg_runs = kgemm32_runs(Ppad, ncols, L.kg_nb);
   const size_t part = std::max({sizeof(float) * (size_t)gemm_splits(3 * R, 3 * R, P) * 9 * R * R,
                                 sizeof(float) * (size_t)gemm_splits(R, R, P) * R * R,
                                 sizeof(float) * (size_t)m * p.nb,
-                                sizeof(float) * (size_t)L.kg_runs * kK32Tile});
+                                sizeof(float) * (size_t)L.kg_runs * kgemm32_tile(L.kg_nb)});
   L.part = take(part);
   L.red = take(sizeof(double) * 16);
   L.psave = take(sizeof(float) * (size_t)p.nb * R);
@@ -234,8 +261,8 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
 // ---- FP32 kernel-GEMM on 32x32 tiles (the operands of VDS_PAIR_MFMA32) -----
 //
 // Y[I][col] = sum_J Z_IJ B[J][col] with a workgroup of kK32Waves waves owning
-// kK32Waves 32-row blocks (256 rows) and kK32NB column blocks of 32 (128
-// columns).  Per chunk of 32 columns of Z it stages the chunk's B block and
+// kK32Waves 32-row blocks (256 rows) and NB column blocks of 32 (32 NB
+// columns; NB from 1 to 4 by the problem's size).  Per chunk of 32 columns of Z it stages the chunk's B block and
 // the K operand of its distance product (the pair kernel's per-chunk KC
 // layout) in LDS once, double buffered with one barrier.  Each wave forms its
 // 32x32 piece of Z on v_mfma_f32_32x32x2_f32 from the centred row coordinates
@@ -246,11 +273,12 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
 // sits in lane l at row J(v, l / 32), column 32 nb + l % 32.  FP32
 // accumulation over all columns of Z (as the FP16-split form: ~1e-6 of the
 // sums).
-// B of the FP32 32x32 kernel-GEMM, one block of 32 rows J x 128 columns per
-// (chunk c, column group cg): element (jj, col = 128 cg + 32 nb + l) at
-// [((c NCG + cg) 32 + jj) 128 + 4 l + nb], one float4 per lane and row.
+// B of the FP32 32x32 kernel-GEMM, one block of 32 rows J x 32 NB columns per
+// (chunk c, column group cg): element (jj, col = 32 NB cg + 32 nb + l) at
+// [((c NCG + cg) 32 + jj) 128 + 4 l + nb], one float4 per lane and row
+// (slots nb >= NB are zero).
 __global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict__ wv, const float *__restrict__ invS,
-                          int64_t P, int64_t Ppad, int R, int NCG, float *__restrict__ Bk) {
+                          int64_t P, int64_t Ppad, int R, int NCG, int NB, float *__restrict__ Bk) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= Ppad * NCG * 128) return;
   const int e = (int)(t & 127);
@@ -260,10 +288,10 @@ __global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict
   const int cg = (int)(cb % NCG);
   const int64_t J = (cb / NCG) * 32 + jj;
   const int l = e >> 2, nb = e & 3;
-  const int col = cg * 32 * kK32NB + 32 * nb + l;
+  const int col = cg * 32 * NB + 32 * nb + l;
   const int dR = 3 * R;
   float v = 0.f;
-  if (nb < kK32NB && J < P && col < 2 * dR) {
+  if (nb < NB && J < P && col < 2 * dR) {
     const int h = col / dR, rem = col % dR, a = rem / R, tt = rem % R;
     const float wgt = h == 0 ? wv[J] : wv[J] * invS[J];
     v = wgt * Ude[((int64_t)a * R + tt) * P + J];
@@ -276,9 +304,10 @@ __global__ void k_rom_b32(const float *__restrict__ Ude, const float *__restrict
 // one run per item, so an item meets at most two runs).  A run's segment that
 // starts an item writes the item's output tile to Y; a run whose first segment
 // continues an item begun by the previous run writes that part to its slot,
-// slots[L] (kK32Tile floats: 256 rows x 128 columns), which k_kgemm32_fixup
-// then adds to Y.  Consecutive runs share an XCD (and its L2's B blocks).
-template <int D>
+// slots[L] (kgemm32_tile(NB) floats: 256 rows x 32 NB columns), which
+// k_kgemm32_fixup then adds to Y.  Consecutive runs share an XCD (and its L2's
+// B blocks).
+template <int D, int NB>
 __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_kernel_gemm32(
     const float *__restrict__ xr, int nrb32, const float4 *__restrict__ KC, int nch, const float4 *__restrict__ Bk,
     int NCG, int ncols, float kappa, float *__restrict__ Y, int64_t ldy, float *__restrict__ slots) {
@@ -335,9 +364,9 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
       if (uu < SF4) sb[0][uu] = src(c0, uu);
     }
     __syncthreads();
-    floatx16 acc[kK32NB];
+    floatx16 acc[NB];
 #pragma unroll
-    for (int nb = 0; nb < kK32NB; ++nb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[nb][v] = 0.f;
     for (int c = c0; c < c1; ++c) {
@@ -377,7 +406,7 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
         const float4 b = sB[(8 * (v >> 2) + (v & 3)) * 32];
         const float bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-        for (int nb = 0; nb < kK32NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[v], bv[nb], acc[nb], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(z[v], bv[nb], acc[nb], 0, 0, 0);
       }
       if (c + 1 < c1) {
 #pragma unroll
@@ -390,18 +419,18 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
       // segment's first stage overwrites buffer 0
       __syncthreads();
     }
-    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 128 cg + 32 nb + li
+    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 32 NB cg + 32 nb + li
     if (c0 > 0) {  // a continued item: the whole tile to this run's slot
-      float *o = slots + (int64_t)L * kK32Tile;
+      float *o = slots + (int64_t)L * kgemm32_tile(NB);
 #pragma unroll
-      for (int nb = 0; nb < kK32NB; ++nb)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-          o[(wave * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * (32 * kK32NB) + 32 * nb + li] = acc[nb][v];
+          o[(wave * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * (32 * NB) + 32 * nb + li] = acc[nb][v];
     } else if (rb < nrb32) {
 #pragma unroll
-      for (int nb = 0; nb < kK32NB; ++nb) {
-        const int col = cg * 32 * kK32NB + 32 * nb + li;
+      for (int nb = 0; nb < NB; ++nb) {
+        const int col = cg * 32 * NB + 32 * nb + li;
         if (col >= ncols) break;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -417,7 +446,7 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
 // Y += the slot of every run whose first segment continued an item (block
 // (x, L): elements x 256 .. of run L's tile).  An item meets at most two runs,
 // so no two slots add to the same tile.
-__global__ void k_kgemm32_fixup(const float *__restrict__ slots, int nrb32, int nch, int NCG, int ncols,
+__global__ void k_kgemm32_fixup(const float *__restrict__ slots, int nrb32, int nch, int NCG, int NB, int ncols,
                                 float *__restrict__ Y, int64_t ldy) {
   const int L = (int)blockIdx.y, G = (int)gridDim.y;
   const int n_rg = (nrb32 + kK32Waves - 1) / kK32Waves;
@@ -427,11 +456,36 @@ __global__ void k_kgemm32_fixup(const float *__restrict__ slots, int nrb32, int 
   if (u0 == item * nch) return;  // the run starts its first item
   const int cg = (int)(item / n_rg), rg = (int)(item % n_rg);
   const int e = (int)blockIdx.x * 256 + threadIdx.x;
-  if (e >= kK32Tile) return;
-  const int r = e / (32 * kK32NB), cc = e % (32 * kK32NB);
+  const int tile = kgemm32_tile(NB);
+  if (e >= tile) return;
+  const int r = e / (32 * NB), cc = e % (32 * NB);
   const int64_t row = (int64_t)rg * 32 * kK32Waves + r;
-  const int col = cg * 32 * kK32NB + cc;
-  if (row < (int64_t)nrb32 * 32 && col < ncols) Y[row * ldy + col] += slots[(int64_t)L * kK32Tile + e];
+  const int col = cg * 32 * NB + cc;
+  if (row < (int64_t)nrb32 * 32 && col < ncols) Y[row * ldy + col] += slots[(int64_t)L * tile + e];
+}
+
+struct KGemm32Args {
+  const float *xr;
+  int nrb32;
+  const float4 *KC;
+  int nch;
+  const float4 *Bk;
+  int NCG, ncols;
+  float kappa;
+  float *Y;
+  int64_t ldy;
+  float *slots;
+};
+
+template <int D>
+void launch_kgemm32(int NB, int G, const KGemm32Args &a, hipStream_t s) {
+  const dim3 grid((unsigned)G), block(kK32Waves * 64);
+  switch (NB) {
+    case 1: k_kernel_gemm32<D, 1><<<grid, block, 0, s>>>(a.xr, a.nrb32, a.KC, a.nch, a.Bk, a.NCG, a.ncols, a.kappa, a.Y, a.ldy, a.slots); break;
+    case 2: k_kernel_gemm32<D, 2><<<grid, block, 0, s>>>(a.xr, a.nrb32, a.KC, a.nch, a.Bk, a.NCG, a.ncols, a.kappa, a.Y, a.ldy, a.slots); break;
+    case 3: k_kernel_gemm32<D, 3><<<grid, block, 0, s>>>(a.xr, a.nrb32, a.KC, a.nch, a.Bk, a.NCG, a.ncols, a.kappa, a.Y, a.ldy, a.slots); break;
+    default: k_kernel_gemm32<D, 4><<<grid, block, 0, s>>>(a.xr, a.nrb32, a.KC, a.nch, a.Bk, a.NCG, a.ncols, a.kappa, a.Y, a.ldy, a.slots); break;
+  }
 }
 
 // ---- FP16-split kernel-GEMM (used with the FP16-split pair kernels) ---------
@@ -1017,25 +1071,28 @@ vds_status freeze(vds_rom r, const float *p) {
       }
     });
   } else if (c->ep.f32x) {
-    // the 32x32 form reads the pair kernel's operands as the passes left them
-    const int NCG = (int)((2 * 3 * R + 32 * kK32NB - 1) / (32 * kK32NB));
-    k_rom_b32<<<nblk256(Ppad * NCG * 128), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, NCG, r->Bsw);
+    // the 32x32 form reads the pair kernel's operands as the passes left them;
+    // column blocks per workgroup and runs were fixed when the model was laid
+    // out (its slots hold G tiles of that width)
+    const int NB = L.kg_nb, G = L.kg_runs;
+    const int NCG = (int)((2 * 3 * R + 32 * NB - 1) / (32 * NB));
+    k_rom_b32<<<nblk256(Ppad * NCG * 128), 256, 0, s>>>(r->Ude, c->wv, r->invS, P, Ppad, R, NCG, NB, r->Bsw);
     const int nrb32 = (int)(Ppad / 32), nch = (int)((P + 31) / 32);
     const int ncols = 2 * 3 * R;
-    const int G = L.kg_runs;  // fixed when the model was laid out: its slots hold G tiles
     const float4 *kc = reinterpret_cast<const float4 *>(c->KA), *bk = reinterpret_cast<const float4 *>(r->Bsw);
     const double flops = 2.0 * (double)P * P * 2 * 3 * R;
     float *slots = reinterpret_cast<float *>(r->part);
     timed(c, VDS_TIMER_KGEMM, flops, [&] {
+      const KGemm32Args a{c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots};
       switch (c->ep.D) {
-        case 3: k_kernel_gemm32<3><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
-        case 6: k_kernel_gemm32<6><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
-        case 9: k_kernel_gemm32<9><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
-        case 12: k_kernel_gemm32<12><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
-        default: k_kernel_gemm32<15><<<G, kK32Waves * 64, 0, s>>>(c->xc, nrb32, kc, nch, bk, NCG, ncols, c->ep.kappa, r->Y, L.ldy, slots); break;
+        case 3: launch_kgemm32<3>(NB, G, a, s); break;
+        case 6: launch_kgemm32<6>(NB, G, a, s); break;
+        case 9: launch_kgemm32<9>(NB, G, a, s); break;
+        case 12: launch_kgemm32<12>(NB, G, a, s); break;
+        default: launch_kgemm32<15>(NB, G, a, s); break;
       }
-      k_kgemm32_fixup<<<dim3((unsigned)((kK32Tile + 255) / 256), (unsigned)G), 256, 0, s>>>(slots, nrb32, nch, NCG, ncols,
-                                                                                           r->Y, L.ldy);
+      k_kgemm32_fixup<<<dim3((unsigned)((kgemm32_tile(NB) + 255) / 256), (unsigned)G), 256, 0, s>>>(
+          slots, nrb32, nch, NCG, NB, ncols, r->Y, L.ldy);
     });
   } else {
     // the 16x16 FP32 forms (VDS_PAIR_MFMA, VDS_PAIR_VALU) read the 16-row operand layout

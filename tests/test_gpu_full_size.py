@@ -6,9 +6,9 @@ through the C ABI, with the default (FP32) pair kernel:
   at t_end;
 * 4-bead chain, P = 20000, D = 9, h = 0.4: the velocity and one implicit
   step on all rows;
-* the POD-reduced chain, P = 20000, R = 180: the Brownian operators X^B1 and
-  X^B2 of Section 2.4 against the oracle's factored form evaluated one block
-  of kernel-matrix rows at a time;
+* the POD-reduced chain, P = 20000, R = 180 (and R = 60, 120): the Brownian
+  operators X^B1 and X^B2 of Section 2.4 against the oracle's factored form
+  evaluated one block of kernel-matrix rows at a time;
 * the stress history of the reduced run (one entry per output interval).
 
 Tolerances (FP32 GPU against FP64 oracle on the same FP32 inputs): state
@@ -128,27 +128,40 @@ def test_chain4_full_size_velocity_and_implicit_step_on_every_row(lib):
     assert 1 <= d["last_iters"] <= m
 
 
-def test_reduced_operators_at_full_size_match_row_blocked_oracle(lib):
-    # the POD-reduced chain: P = 20000 (3P = 60000), R = 180, operators at the
-    # reconstruction of a state of the chain's own trajectory
+@pytest.fixture(scope="module")
+def chain4_snapshots(lib):
+    # 61 states of the 4-bead chain's own trajectory (P = 20000), the POD input
     cfg = wl.chain4_shear()
-    P, nb, R = cfg["P"], 3, 180
+    P, nb = cfg["P"], 3
     ctx = lib.Context(nb, P, cfg["h"], H=cfg["H"], G=cfg["G"], dt=cfg["dt"], scheme="implicit", poison=True)
     import torch
     q = _dev(cfg["q0"])
     snaps = [q.clone()]
-    _say("POD basis chain4 P=20000 from 61 snapshots (GPU)")
+    _say("chain4 P=20000: 60 implicit steps for the POD snapshots (GPU)")
     for _ in range(60):
         ctx.step(q, nsteps=1)
         snaps.append(q.clone())
     X = torch.stack(snaps).reshape(61 * nb, 3 * P).contiguous()
+    return cfg, ctx, snaps, X
+
+
+# R = 180 is the POD-reduced chain; on the 256 compute units of an MI355X the
+# kernel-GEMM takes 4 column blocks of 32 per workgroup there, 2 at R = 60 and
+# 3 at R = 120 (P = 300 in test_gpu_pod_rom.py takes 1)
+@pytest.mark.parametrize("R", [180, 60, 120])
+def test_reduced_operators_at_full_size_match_row_blocked_oracle(lib, chain4_snapshots, R):
+    # the POD-reduced chain: P = 20000 (3P = 60000), operators at the
+    # reconstruction of a state of the chain's own trajectory
+    cfg, ctx, snaps, X = chain4_snapshots
+    P = cfg["P"]
+    _say(f"POD basis chain4 P=20000 R={R} from 61 snapshots (GPU)")
     U, _ = ctx.pod_basis(X, R)
     p = ctx.pod_project(U, snaps[30])
     rom = lib.Rom(ctx, U)
     _, XB1, XB2 = (_np(t) for t in rom.operators(p))
     Uf = _np(U).T                                   # 3P x R
     qt = opod.reconstruct(Uf, _np(p), P)
-    _say(f"row-blocked oracle operators P=20000 R=180 on {THREADS} threads")
+    _say(f"row-blocked oracle operators P=20000 R={R} on {THREADS} threads")
     XB1_o, XB2_o = orom.brownian_rows(Uf, qt, ovds.uniform_weights(P), cfg["h"], threads=THREADS)
     assert _rel(XB1, XB1_o) < 1e-4
     assert _rel(XB2, XB2_o) < 1e-4
