@@ -419,24 +419,27 @@ __global__ __launch_bounds__(kK32Waves * 64) __attribute__((amdgpu_waves_per_eu(
       // segment's first stage overwrites buffer 0
       __syncthreads();
     }
-    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 32 NB cg + 32 nb + li
+    // output lane l, register v: row 32 rb + 8 (v / 4) + 4 h + v % 4, column 32 NB cg + 32 nb + li.
+    // The output addresses are formed here: formed ahead of the chunk loop
+    // (they do not depend on it) they stay live across it and spill.
+    float *ybase = Y, *sbase = slots;
+    int64_t ld = ldy;
+    int el = lane;
+    asm volatile("" : "+s"(ybase), "+s"(sbase), "+s"(ld), "+v"(el));
+    const int eh = el >> 5, eli = el & 31;
     if (c0 > 0) {  // a continued item: the whole tile to this run's slot
-      float *o = slots + (int64_t)L * kgemm32_tile(NB);
+      float *o = sbase + (int64_t)L * kgemm32_tile(NB) + (wave * 32 + 4 * eh) * (32 * NB) + eli;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          o[(wave * 32 + 8 * (v >> 2) + 4 * h + (v & 3)) * (32 * NB) + 32 * nb + li] = acc[nb][v];
+        for (int v = 0; v < 16; ++v) o[(8 * (v >> 2) + (v & 3)) * (32 * NB) + 32 * nb] = acc[nb][v];
     } else if (rb < nrb32) {
+      float *o = ybase + ((int64_t)rb * 32 + 4 * eh) * ld + cg * 32 * NB + eli;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int col = cg * 32 * NB + 32 * nb + li;
-        if (col >= ncols) break;
+        if (cg * 32 * NB + 32 * nb + eli >= ncols) break;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t row = (int64_t)rb * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-          Y[row * ldy + col] = acc[nb][v];
-        }
+        for (int v = 0; v < 16; ++v) o[(8 * (v >> 2) + (v & 3)) * ld + 32 * nb] = acc[nb][v];
       }
     }
     seg_done += c1 - c0;
