@@ -262,9 +262,10 @@ __global__ __launch_bounds__(256) void k_kernel_gemm(const float *__restrict__ Q
 //
 // Y[I][col] = sum_J Z_IJ B[J][col] with a workgroup of kK32Waves waves owning
 // kK32Waves 32-row blocks (256 rows) and NB column blocks of 32 (32 NB
-// columns; NB from 1 to 4 by the problem's size).  Per chunk of 32 columns of Z it stages the chunk's B block and
-// the K operand of its distance product (the pair kernel's per-chunk KC
-// layout) in LDS once, double buffered with one barrier.  Each wave forms its
+// columns; NB from 1 to 4 by the problem's size).  Per chunk of 32 columns of
+// Z it stages the chunk's B block and the K operand of its distance product
+// (the pair kernel's per-chunk KC layout) in LDS once, double buffered with one
+// barrier.  Each wave forms its
 // 32x32 piece of Z on v_mfma_f32_32x32x2_f32 from the centred row coordinates
 // (Z_II = 1 set exactly) and multiplies it by the staged B block on the same
 // instruction: the distance product leaves lane l with row I = l % 32 and, in
