@@ -53,7 +53,11 @@ vds_status vds_pod_reconstruct(vds_ctx ctx, const float *U_dev, int32_t R, const
 
 typedef struct vds_rom_s *vds_rom;
 
-/* Workspace for a reduced model of rank R on the context's problem. */
+/* Workspace for a reduced model of rank R on the context's problem.  The
+ * kernel-GEMM's launch shape, and so the size, follows the compute-unit count
+ * of the current device: query it with the device current that the model
+ * will run on (vds_rom_create checks the size and fails with VDS_ERR_NOMEM
+ * when it is short). */
 size_t vds_rom_workspace_bytes(const vds_problem *prob, int32_t R);
 
 /* Builds the reduced model of basis U_dev (3P x R column-major, orthonormal
