@@ -198,6 +198,28 @@ def test_rom_operators_small_vs_oracle(lib, tuning):
     assert _rel(XB2, XB2_o) < 1e-4
 
 
+@pytest.mark.parametrize("nb", [1, 2, 4, 5])
+def test_rom_operators_other_bead_counts_vs_oracle(lib, nb):
+    # the FP32 kernel-GEMM at D = 3, 6, 12 and 15 (the chain above is D = 9)
+    P, R = 300, 12
+    rng = np.random.default_rng(40 + nb)
+    U, _ = np.linalg.qr(rng.standard_normal((3 * P, R)))
+    U32 = wl.to_f32(U.T)
+    Uf = U32.astype(np.float64).T
+    q = wl.gaussian_bonds(40 + nb, nb, P, 1 / 3)
+    p32 = wl.to_f32(opod.project(Uf, wl.f32_as_f64(wl.to_f32(q))))
+    prob = ovds.Problem(nb=nb, h=0.4 + 0.1 * nb, dt=1e-3, G=wl.shear_gradient(1.0))
+    ctx = lib.Context(nb, P, prob.h, G=prob.G, dt=prob.dt, scheme="explicit", poison=True)
+    _say(f"reduced operators P=300 R=12 nb={nb} (D={3 * nb})")
+    rom = lib.Rom(ctx, _dev(U32))
+    XH, XB1, XB2 = (_np(t) for t in rom.operators(_dev(p32)))
+    qt = opod.reconstruct(Uf, p32.astype(np.float64), P)
+    XB1_o, XB2_o = orom.brownian(Uf, qt, ovds.uniform_weights(P), prob.h)
+    assert _rel(XH, orom.hydro(Uf, prob.G, P)) < 1e-5
+    assert _rel(XB1, XB1_o) < 1e-4
+    assert _rel(XB2, XB2_o) < 1e-4
+
+
 @pytest.mark.parametrize("tuning", TUNINGS)
 @pytest.mark.parametrize("R", [12, 140, 250])
 def test_rom_run_small_vs_oracle(lib, tuning, R):
